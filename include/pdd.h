@@ -1,0 +1,289 @@
+/*
+ * pdd.h -- C ABI of the MI355X (gfx950) library that assembles and solves the
+ * explicit interfacial system  C u = r  of the overlapping-circle stochastic
+ * substructuring method (Moron-Vidal, Bernal, Suzuki, arXiv 2311.08946).
+ *
+ * Problem (Section 2, eqs. 1-3):  L u + c u + f = 0 in Omega, u = g on the
+ * boundary, with L = a_xx/2 d_xx + a_xy d_xy + a_yy/2 d_yy + b_x d_x + b_y d_y
+ * and c <= 0.  Omega is covered by open disks (eqs. 4-8); the unknowns are the
+ * solution values at N knots on the circles (eqs. 9-12).  Row i of C (eqs.
+ * 28-30) comes from one subdomain containing knot i (Section 3.2):
+ *   - floating circle: C_ij = G_j(x_i), r_i = B(x_i) from local problems (eqs.
+ *     31-35) solved by polar Chebyshev x Fourier collocation (Section 3.3,
+ *     eqs. 40-41) -- batched dense LU on the GPU;
+ *   - perimeter subdomain: Monte Carlo of the Feynman-Kac expectations (eqs.
+ *     29-30 with the SDE of eq. 53), plain Euler-Maruyama on Philox4x32-10
+ *     streams, interface data interpolated by inverse multiquadrics (eqs.
+ *     19-22);
+ *   - junction knot on the boundary: C_ii = 1, r_i = g(x_i).
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns a pdd_status; PDD_OK is 0.  On error a message
+ *     is available from pdd_last_error() (thread-local, valid until the next
+ *     call on the same thread).  No C++ exception crosses this boundary.
+ *   - Handles (pdd_cover, pdd_system) are opaque and owned by the library;
+ *     release them with pdd_destroy_cover / pdd_destroy_system.
+ *   - Array arguments are owned by the caller and only read (or written, for
+ *     outputs) during the call.  "host" arrays are ordinary CPU memory;
+ *     "device" arrays are HIP device memory on the current device.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Device work is
+ *     stream-ordered; functions that must report a device-side status (pivot
+ *     breakdown, path-step cap, solver convergence) synchronise that stream
+ *     before returning.
+ *   - All floating point is IEEE binary64.
+ */
+#ifndef PDD_H
+#define PDD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pdd_status;
+enum {
+  PDD_OK = 0,
+  PDD_EINVAL = 1,      /* bad argument (null pointer, size out of range)          */
+  PDD_ECOVER = 2,      /* cover violates eq. 5, an uncovered knot, multi-arc Gamma */
+  PDD_ENOMEM = 3,      /* device or host allocation failed                         */
+  PDD_EDEVICE = 4,     /* HIP runtime error                                        */
+  PDD_ENOCONV = 5,     /* iterative solve did not reach the tolerance              */
+  PDD_EPATHCAP = 6,    /* a Monte Carlo path exceeded the step cap                 */
+  PDD_EBREAKDOWN = 7   /* zero pivot in a collocation LU or a non-SPD RBF Gram     */
+};
+
+typedef struct pdd_cover_s* pdd_cover;
+typedef struct pdd_system_s* pdd_system;
+
+const char* pdd_last_error(void);
+
+/* ---------------------------------------------------------------- problem */
+
+enum { PDD_DOMAIN_BOX = 0, PDD_DOMAIN_DISK = 1 };
+#define PDD_MAX_HOLES 4
+
+/* Omega: the open box (x0,x1)x(y0,y1), or the open disk |x-c| < R minus up to
+ * four closed disks (hx, hy, hr). */
+typedef struct pdd_domain {
+  int32_t kind;
+  int32_t n_holes;
+  double x0, x1, y0, y1;
+  double cx, cy, R;
+  double holes[PDD_MAX_HOLES][3];
+} pdd_domain;
+
+enum {
+  PDD_FIELD_CONST = 0,     /* value = base                                            */
+  PDD_FIELD_SINSUM = 1,    /* base + sum_q a_q sin(2 pi (b_q x + c_q y) + d_q),
+                              then min(., 0) if clip_nonpos                           */
+  PDD_FIELD_CPOLY_RE = 2,  /* Re sum_k (a_k + i b_k) (x + i y)^k, k < n_terms        */
+  PDD_FIELD_DERIVED_F = 3  /* f = -(L u + c u) for the problem's manufactured u      */
+};
+#define PDD_MAX_TERMS 16
+
+/* A coefficient field, evaluated on the device at nodes and along paths.
+ * The term arrays are host pointers read during the call that receives them. */
+typedef struct pdd_field {
+  int32_t kind;
+  int32_t n_terms;         /* <= PDD_MAX_TERMS                                       */
+  int32_t clip_nonpos;
+  int32_t reserved;
+  double base;
+  const double* a;
+  const double* b;
+  const double* c;
+  const double* d;
+} pdd_field;
+
+/* The model problem of eq. 1.  `u` is the manufactured solution used by
+ * PDD_FIELD_DERIVED_F (SINSUM or CPOLY_RE); otherwise it is ignored. */
+typedef struct pdd_problem {
+  pdd_domain domain;
+  pdd_field axx, axy, ayy, bx, by, c, f, g, u;
+} pdd_problem;
+
+enum {
+  PDD_WHICH_AXX = 0, PDD_WHICH_AXY = 1, PDD_WHICH_AYY = 2, PDD_WHICH_BX = 3, PDD_WHICH_BY = 4,
+  PDD_WHICH_C = 5, PDD_WHICH_F = 6, PDD_WHICH_G = 7, PDD_WHICH_U = 8
+};
+
+/*
+ * pdd_eval_field -- evaluates one field of the problem (eq. 1: a coefficient,
+ * the source f, the boundary data g, or the manufactured solution u) at n
+ * points on the device.
+ *   xy   device [2n] interleaved (x, y);  out  device [n]
+ * Errors: PDD_EINVAL (bad field or `which`), PDD_EDEVICE.  Stream-ordered.
+ */
+pdd_status pdd_eval_field(const pdd_problem* problem, int32_t which, const double* xy, int64_t n,
+                          double* out, void* stream);
+
+/* ------------------------------------------------------------------ cover */
+
+enum { PDD_RULE_FLOAT_FIRST_MAX_DEPTH = 0, PDD_RULE_MAX_DEPTH = 1 };
+
+typedef struct pdd_cover_opts {
+  int32_t rule;            /* row choice of Section 3.2 (see pdd_build_cover)         */
+  int32_t reserved;
+  double rbf_c2;           /* IMQ shape c^2 of eq. 19; <= 0: 1.5 (44/M)^2 per circle   */
+} pdd_cover_opts;
+
+/*
+ * pdd_build_cover -- geometry of Section 2.1 (eqs. 4-12) and the row choice of
+ * Section 3.2, computed on the host.
+ *   centres  host [2*n_circles], (x, y) per circle
+ *   radii    host [n_circles]
+ *   M        host [n_circles]  knots per full circle (even)
+ *   Ntheta   host [n_circles]  angular collocation nodes (even)
+ *   Nr       host [n_circles]  interior radial collocation nodes (>= 1)
+ * Circle m is floating if its closed disk lies in Omega; otherwise its
+ * interface must be a single arc of the circle inside closure(Omega).
+ * Floating knots: angles 2 pi j / M.  Arc knots: the same angles inside the
+ * arc (keeping dtheta/4 away from its ends) plus one junction knot at each
+ * end.  Knots are numbered circle by circle in increasing local angle.  Row
+ * rule FLOAT_FIRST_MAX_DEPTH: the deepest floating circle strictly containing
+ * the knot, else the deepest perimeter one; MAX_DEPTH: the deepest of all.
+ * Errors: PDD_EINVAL, PDD_ECOVER (uncovered knot, multi-arc interface,
+ * circle outside Omega), PDD_ENOMEM.  No device work is done.
+ */
+pdd_status pdd_build_cover(const pdd_domain* domain, int32_t n_circles,
+                           const double* centres, const double* radii,
+                           const int32_t* M, const int32_t* Ntheta, const int32_t* Nr,
+                           const pdd_cover_opts* opts, pdd_cover* out);
+
+typedef struct pdd_cover_info {
+  int64_t N;               /* knots = unknowns                                       */
+  int64_t nnz;             /* entries of C                                           */
+  int64_t n_circles, n_float, n_perim;
+  int64_t n_spectral_rows, n_mc_rows, n_boundary_rows;
+  int64_t sum_n;           /* collocation nodes over floating circles                */
+  int64_t sum_n2;          /* sum of n^2 over floating circles                       */
+  int32_t max_n, max_M, max_arc, n_buckets;
+} pdd_cover_info;
+
+pdd_status pdd_cover_get_info(pdd_cover cover, pdd_cover_info* out);
+
+/* Knot table (host outputs, any may be NULL): xy [2N]; row_class [N]
+ * (0 spectral, 1 Monte Carlo, 2 boundary); assigned [N] (circle of the row,
+ * -1 for boundary rows); owner [N] (circle the knot lies on). */
+pdd_status pdd_cover_knots(pdd_cover cover, double* xy, int32_t* row_class,
+                           int32_t* assigned, int32_t* owner);
+
+/* CSR pattern of C (host outputs): rowptr [N+1], cols [nnz]; columns of each
+ * row increase; row i holds i and, unless boundary, the stencil of its circle. */
+pdd_status pdd_cover_pattern(pdd_cover cover, int64_t* rowptr, int32_t* cols);
+
+/* Collocation nodes of the floating circles (host outputs): xy [2*sum_n],
+ * circle-major, node q = (j-1) Ntheta + l at radius r cos(j pi/(2 Nr + 1)) and
+ * angle 2 pi l / Ntheta; node_off [n_float+1]; float_ids [n_float]. */
+pdd_status pdd_cover_nodes(pdd_cover cover, double* xy, int64_t* node_off, int32_t* float_ids);
+
+void pdd_destroy_cover(pdd_cover cover);
+
+/* -------------------------------------------------------------- assemble */
+
+/* Node samples of the seven coefficients of eq. 1 at the collocation nodes of
+ * the floating circles (device [sum_n] each, layout of pdd_cover_nodes).  A
+ * NULL member is sampled from the problem's field on the device. */
+typedef struct pdd_samples {
+  const double *axx, *axy, *ayy, *bx, *by, *c, *f;
+} pdd_samples;
+
+typedef struct pdd_mc_opts {
+  int64_t paths;           /* Ntilde paths per perimeter knot                         */
+  double h;                /* Euler step                                              */
+  uint64_t seed;           /* Philox key = (seed mod 2^32, seed div 2^32)              */
+  int32_t n_batches;       /* batches for standard errors (2..64)                      */
+  int32_t step_cap;        /* maximum steps of one path (> 0)                          */
+  const double* h_per_circle;  /* host [n_circles] or NULL: per-circle step            */
+} pdd_mc_opts;
+
+enum { PDD_PLAN_BATCHED = 0, PDD_PLAN_PER_CIRCLE = 1 };
+
+typedef struct pdd_assemble_opts {
+  int32_t plan;            /* PDD_PLAN_BATCHED or PDD_PLAN_PER_CIRCLE (one launch per circle) */
+  int32_t keep_factors;    /* keep LU factors for pdd_assemble_G_backward              */
+  int64_t hbm_budget_bytes;/* cap on factor storage; 0 = 64 GiB                        */
+} pdd_assemble_opts;
+
+/*
+ * pdd_assemble_G -- builds C (CSR values on the pdd_cover_pattern layout), r,
+ * and per-entry Monte Carlo standard errors.  Floating rows: for each floating
+ * circle the collocation matrix [A_II | A_IB] of eq. 40 is built from the node
+ * samples, LU-factorised with partial pivoting together with the right-hand
+ * sides [A_IB H | -F] (eqs. 32, 35, 41), and the solutions are interpolated at
+ * the knots assigned to the circle.  Perimeter rows: `mc->paths` Euler paths
+ * per knot; step k of path p from knot i draws Philox4x32-10 at counter
+ * (k, p, i, 0).  Boundary rows: C_ii = 1, r_i = g(x_i).
+ *   samples  may be NULL (all sampled on the device)
+ *   out      receives a system handle owning the device results
+ * Errors: PDD_EINVAL, PDD_ENOMEM, PDD_EDEVICE, PDD_EBREAKDOWN, PDD_EPATHCAP.
+ * Synchronises `stream` once at the end to read the device status.
+ */
+pdd_status pdd_assemble_G(pdd_cover cover, const pdd_problem* problem,
+                          const pdd_samples* samples, const pdd_mc_opts* mc,
+                          const pdd_assemble_opts* opts, void* stream, pdd_system* out);
+
+/* Copies the system to caller buffers (device or host, any may be NULL):
+ * val [nnz], b [N], se [nnz] (standard error of each entry, 0 if exact),
+ * se_b [N].  Stream-ordered on `stream`. */
+pdd_status pdd_system_copy(pdd_system sys, double* val, double* b, double* se, double* se_b,
+                           void* stream);
+
+typedef struct pdd_system_stats {
+  int64_t path_steps;      /* Euler steps over all paths                              */
+  int64_t paths;           /* paths simulated                                         */
+  int64_t capped_paths;    /* paths stopped by the step cap                           */
+  int32_t breakdowns;      /* zero pivots / non-SPD Gram matrices                      */
+  int32_t n_launch_spectral, n_launch_mc;
+  float ms_sample, ms_build, ms_lu, ms_solve, ms_eval, ms_mc, ms_total;
+} pdd_system_stats;
+
+pdd_status pdd_system_get_stats(pdd_system sys, pdd_system_stats* out);
+
+/* ------------------------------------------------------------------ solve */
+
+typedef struct pdd_solve_opts {
+  double rtol;             /* relative residual |r - C u| / |r|, default 1e-12         */
+  int32_t max_iter;        /* default 2000                                             */
+  int32_t use_guess;       /* start from the contents of u                             */
+} pdd_solve_opts;
+
+typedef struct pdd_solve_info {
+  int32_t iterations;
+  int32_t converged;
+  double rel_residual;
+} pdd_solve_info;
+
+/*
+ * pdd_solve_G -- BiCGStab on C (transpose = 0) or C^T (transpose = 1).
+ *   rhs  device [N] or NULL for r;  u  device [N] output (and guess).
+ * Synchronises `stream` once per iteration to test convergence.
+ * Errors: PDD_EINVAL, PDD_ENOCONV (u holds the last iterate), PDD_EDEVICE.
+ */
+pdd_status pdd_solve_G(pdd_system sys, const double* rhs, double* u, int32_t transpose,
+                       const pdd_solve_opts* opts, void* stream, pdd_solve_info* info);
+
+/*
+ * pdd_assemble_G_backward -- gradients of a loss L(u) with respect to the node
+ * samples of pdd_samples, given u (C u = r) and lambda = C^-T dL/du (device
+ * [N] each).  For floating circle m with mu = A_II^-T E_m^T lambda_Km:
+ *   dL/d coef_q = -mu_q (row q of the operator multiplying coef) . [w_I; w_B]
+ *   dL/d f_q    = -mu_q
+ * with w_B = H u_Xi and w_I the local interior solution.  Outputs are device
+ * arrays [sum_n] in the node layout; NULL skips one.  Monte Carlo and boundary
+ * rows do not depend on node samples (dL/dr = lambda).  Needs the system to
+ * have been assembled with keep_factors.
+ */
+pdd_status pdd_assemble_G_backward(pdd_system sys, const double* u, const double* lambda,
+                                   double* g_axx, double* g_axy, double* g_ayy,
+                                   double* g_bx, double* g_by, double* g_c, double* g_f,
+                                   void* stream);
+
+void pdd_destroy_system(pdd_system sys);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDD_H */

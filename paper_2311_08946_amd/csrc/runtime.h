@@ -1,0 +1,118 @@
+// Device memory ownership, per-cover device tables and the opaque handles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "cover.h"
+#include "device_common.h"
+#include "kernels.h"
+
+namespace pdd {
+
+pdd_status fail(pdd_status code, const std::string& msg);
+
+struct HipError : std::runtime_error {
+  hipError_t code;
+  HipError(hipError_t c, const std::string& where)
+      : std::runtime_error(where + ": " + hipGetErrorString(c)), code(c) {}
+};
+
+#define PDD_HIP(call)                                                   \
+  do {                                                                  \
+    hipError_t e_ = (call);                                             \
+    if (e_ != hipSuccess) throw ::pdd::HipError(e_, #call);             \
+  } while (0)
+
+// Owning device allocation.
+class DevBuf {
+ public:
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p_) (void)hipFree(p_);
+    p_ = nullptr;
+    bytes_ = 0;
+  }
+  void alloc(size_t bytes) {
+    release();
+    if (bytes == 0) return;
+    hipError_t e = hipMalloc(&p_, bytes);
+    if (e != hipSuccess) {
+      p_ = nullptr;
+      throw HipError(e, "hipMalloc(" + std::to_string(bytes) + " bytes)");
+    }
+    bytes_ = bytes;
+  }
+  template <class T>
+  void upload(const std::vector<T>& v) {
+    alloc(v.size() * sizeof(T));
+    if (!v.empty()) PDD_HIP(hipMemcpy(p_, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  }
+  template <class T>
+  T* ptr() const { return static_cast<T*>(p_); }
+  size_t bytes() const { return bytes_; }
+
+ private:
+  void* p_ = nullptr;
+  size_t bytes_ = 0;
+};
+
+struct BucketData {
+  int32_t Nr = 0, Nt = 0, M = 0, Nc = 0, n = 0, ld = 0, nrhs = 0, count = 0;
+  DevBuf tables;               // operator tables
+  DevBuf fl;                   // [count] floating-list indices
+  BucketTables T{};
+  std::vector<double> host_H;
+  void build(int Nr, int Nt, int M);
+};
+
+struct DeviceCover {
+  bool ready = false;
+  int device = -1;
+  DevBuf cx, cy, rad, arc0, arc1, rbf_c2, kx, ky, ktheta;
+  DevBuf knot_off, rowptr, cols, assigned, float_ids, node_off, fk_off, fk_ids;
+  DevBuf perim_ids, perim_pos, mc_knots, bnd_knots;
+  std::vector<std::unique_ptr<BucketData>> buckets;
+  void upload(const HostCover& H);
+  ChunkDesc chunk(const BucketData& b, int32_t first, int32_t count) const;
+};
+
+pdd_status make_dev_problem(const pdd_problem& p, DevProblem& D);
+
+// Factor storage of one bucket, kept for the adjoint.
+struct BucketFactors {
+  int32_t bucket = -1;
+  int32_t first = 0, count = 0;
+  int64_t stride = 0;          // doubles per matrix
+  DevBuf A;                    // [count][n][ld]  LU factors and W
+  DevBuf piv;                  // [count][n]
+  DevBuf rowscale;             // [count][n]
+  DevBuf status;               // [count]
+};
+
+}  // namespace pdd
+
+struct pdd_cover_s {
+  pdd::HostCover H;
+  pdd::DeviceCover D;
+};
+
+struct pdd_system_s {
+  pdd_cover cover = nullptr;
+  pdd::DevBuf val, b, se, se_b;
+  pdd::DevBuf problem;               // DevProblem
+  pdd::DevBuf samples;               // [7][sum_n] node samples (owned copy)
+  std::vector<std::unique_ptr<pdd::BucketFactors>> factors;
+  pdd::DevBuf rt_rowptr, rt_cols, rt_perm;   // transpose pattern (built on first use)
+  bool have_transpose = false;
+  pdd_system_stats stats{};
+  std::vector<double> host_problem_bytes;
+};

@@ -1,0 +1,163 @@
+"""GPU parity of the assembled system against the FP64 CPU oracle.
+
+Floating (spectral) rows: per row, max_j |dC_ij| <= 1e-10 max_j |C_ij|; for r,
+|dr_i| <= 1e-10 (|r_i| + r_m^2 max |f| on circle m).  Monte Carlo rows use the
+same Philox streams as the oracle: every entry must lie within 3 of the
+oracle's standard errors (in practice they agree to rounding).  Boundary rows
+must match to rounding of g.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import assemble, fields, geometry, montecarlo, spectral
+from oracle.geometry import ROW_BOUNDARY, ROW_MC, ROW_SPECTRAL
+
+pytestmark = pytest.mark.gpu
+
+TOL_G = 1e-10
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2311_08946_amd.binding as pdd
+    pdd.lib()
+    return pdd
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _gpu_system(pdd, cfg, **kw):
+    prob = cfg["problem"]
+    cv = pdd.Cover(prob["domain"], cfg["cover"])
+    sysm = pdd.System(cv, prob, cfg["mc"], **kw)
+    val, b, se, se_b = (t.cpu().numpy() for t in sysm.copy())
+    return cv, sysm, val, b, se, se_b
+
+
+def _row(cover, vals, i):
+    lo, hi = cover.rowptr[i], cover.rowptr[i + 1]
+    return vals[lo:hi]
+
+
+def _check_spectral_rows(ref_cover, ref_val, ref_b, val, b, rows, prob, samples=None):
+    worst = 0.0
+    for i in rows:
+        g = _row(ref_cover, val, i)
+        o = _row(ref_cover, ref_val, i)
+        d = np.max(np.abs(g - o)) / np.max(np.abs(o))
+        worst = max(worst, d)
+        assert d <= TOL_G, (i, d)
+    return worst
+
+
+def _check_rhs(ref_cover, ref_b, b, rows, fscale):
+    for i in rows:
+        m = ref_cover.assigned[i]
+        bound = TOL_G * (abs(ref_b[i]) + ref_cover.radii[m] ** 2 * fscale.get(m, 0.0))
+        assert abs(b[i] - ref_b[i]) <= bound + 1e-300, (i, b[i], ref_b[i])
+
+
+def _fscale(prob, cv, circles):
+    out = {}
+    for m in circles:
+        grid = spectral.local_grid(cv.Nr[m], cv.Ntheta[m])
+        s = spectral.node_samples(prob, grid, *cv.centres[m], cv.radii[m])
+        out[m] = float(np.max(np.abs(s["f"])))
+    return out
+
+
+def _check_mc_rows(ref_cover, ref_val, ref_se, ref_b, ref_se_b, val, b, rows):
+    """Every entry within 3 standard errors.  With identical Philox streams the
+    path sums agree to rounding: r_i (a plain path average) must match to
+    1e-9 on all but rare rows (an exit decided by the last ulp of a libm
+    result).  C entries pass through K^-1 of the IMQ Gram matrix (condition
+    about 1e11), which amplifies summation-order rounding to about 1e-5, so
+    they are only held to the statistical bar."""
+    close = 0
+    for i in rows:
+        g = _row(ref_cover, val, i)
+        o = _row(ref_cover, ref_val, i)
+        s = _row(ref_cover, ref_se, i)
+        diff = np.abs(g - o)
+        assert np.all(diff <= 3 * s + 1e-12), (i, np.max(diff / (s + 1e-300)))
+        assert abs(b[i] - ref_b[i]) <= 3 * ref_se_b[i] + 1e-12
+        close += int(abs(b[i] - ref_b[i]) <= 1e-9 * (1 + abs(ref_b[i])))
+    return close / max(len(rows), 1)
+
+
+@pytest.mark.parametrize("name", ["config1", "small_variable"])
+def test_small_configs_match_oracle(name):
+    pdd = _gpu()
+    cfg = workloads.config1() if name == "config1" else workloads.small_variable(paths=256)
+    prob = cfg["problem"]
+    _say(f"[gpu] assemble {name}")
+    cv, sysm, val, b, se, se_b = _gpu_system(pdd, cfg)
+    assert sysm.stats.breakdowns == 0 and sysm.stats.capped_paths == 0
+    ref_cover = geometry.build_cover(prob["domain"], cfg["cover"])
+    ref = assemble.assemble(prob, ref_cover, cfg["mc"])
+    assert abs(sysm.stats.path_steps - ref.path_steps) <= 1e-4 * ref.path_steps
+    spec = np.nonzero(ref_cover.row_class == ROW_SPECTRAL)[0]
+    mcr = np.nonzero(ref_cover.row_class == ROW_MC)[0]
+    bnd = np.nonzero(ref_cover.row_class == ROW_BOUNDARY)[0]
+    worst = _check_spectral_rows(ref_cover, ref.val, ref.b, val, b, spec, prob)
+    _check_rhs(ref_cover, ref.b, b, spec, _fscale(prob, ref_cover, np.nonzero(ref_cover.floating)[0]))
+    frac = _check_mc_rows(ref_cover, ref.val, ref.se, ref.b, ref.se_b, val, b, mcr)
+    assert frac > 0.99
+    for i in bnd:
+        assert _row(ref_cover, val, i)[0] == 1.0
+        assert abs(b[i] - ref.b[i]) <= 1e-14 * (1 + abs(ref.b[i]))
+    _say(f"[gpu] {name}: worst spectral row diff {worst:.2e}, MC r_i within 1e-9: {frac:.4f}")
+
+
+def test_per_circle_plan_is_bitwise_equal_to_batched():
+    pdd = _gpu()
+    cfg = workloads.small_variable(paths=64)
+    _say("[gpu] per-circle vs batched plan")
+    _, _, v1, b1, _, _ = _gpu_system(pdd, cfg)
+    _, _, v2, b2, _, _ = _gpu_system(pdd, cfg, plan="per_circle")
+    assert np.array_equal(v1, v2) and np.array_equal(b1, b2)
+
+
+def test_config2_full_size_sampled():
+    """Config 2 at its full size (900 floating circles, n = 1024, 10^4 paths)
+    in the launch configuration the benchmark times; the oracle recomputes a
+    sample of floating circles and Monte Carlo knots one by one."""
+    pdd = _gpu()
+    cfg = workloads.config2()
+    prob = cfg["problem"]
+    _say("[gpu] assemble config2 (full size)")
+    cv, sysm, val, b, se, se_b = _gpu_system(pdd, cfg)
+    assert sysm.stats.breakdowns == 0 and sysm.stats.capped_paths == 0
+    ref_cover = geometry.build_cover(prob["domain"], cfg["cover"])
+    rng = np.random.default_rng(123)
+    fl = np.nonzero(ref_cover.floating)[0]
+    circles = rng.choice(fl, size=3, replace=False)
+    fsc = _fscale(prob, ref_cover, circles)
+    for m in circles:
+        knots, Crows, rv = spectral.floating_rows(prob, ref_cover, m)
+        ref_val = np.zeros(len(ref_cover.cols))
+        ref_b = np.zeros(ref_cover.N)
+        for t, i in enumerate(knots):
+            assemble._put_row(ref_cover, ref_val, ref_val.copy(), i, m, Crows[t])
+            ref_b[i] = rv[t]
+        _check_spectral_rows(ref_cover, ref_val, ref_b, val, b, knots, prob)
+        _check_rhs(ref_cover, ref_b, b, knots, fsc)
+    mc_knots = rng.choice(np.nonzero(ref_cover.row_class == ROW_MC)[0], size=3, replace=False)
+    knots, rows, ses, rv, se_r, steps = montecarlo.mc_rows(prob, ref_cover, cfg["mc"], mc_knots)
+    ref_val = np.zeros(len(ref_cover.cols))
+    ref_se = np.zeros(len(ref_cover.cols))
+    ref_b = np.zeros(ref_cover.N)
+    ref_se_b = np.zeros(ref_cover.N)
+    for t, i in enumerate(knots):
+        assemble._put_row(ref_cover, ref_val, ref_se, i, ref_cover.assigned[i], rows[t], ses[t])
+        ref_b[i] = rv[t]
+        ref_se_b[i] = se_r[t]
+    frac = _check_mc_rows(ref_cover, ref_val, ref_se, ref_b, ref_se_b, val, b, knots)
+    assert frac > 0.99
