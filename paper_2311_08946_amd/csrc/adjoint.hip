@@ -1,7 +1,268 @@
-// Adjoint of the floating-row assembly with respect to the node samples.
+// Adjoint of the floating-row assembly with respect to the node samples of
+// the coefficients (the derivative of the discrete map; not in the paper).
+//
+// For floating circle m with assigned knots K_m, interpolation weights E_m
+// (rows e_i over the interior nodes) and ring weights:
+//   y   = E_m^T lambda_Km
+//   mu  = A_II^-T y            (transpose solves on the stored LU of S A_II,
+//                               S = row equilibration: mu = S (S A_II)^-T y)
+//   w_B = H u_Xi,   w_I = W[:, M] - W[:, :M] u_Xi   (local solution at u)
+//   dL/d coef_q = -mu_q (d row_q / d coef_q) . [w_I; w_B],   dL/d f_q = -mu_q
+// where row_q is the collocation row of eq. 40 at node q, linear in each of
+// the node's coefficient samples.
 #include <hip/hip_runtime.h>
 
 #include "runtime.h"
+
+namespace pdd {
+
+namespace {
+
+constexpr int kAdjThreads = 256;
+constexpr int kAdjKnots = 32;
+constexpr int kTri = 32;
+
+struct AdjArgs {
+  BucketTables T;
+  ChunkDesc C;
+  const double* A;           // factors + W, [count][n][ld]
+  int64_t stride;
+  const int32_t* piv;        // [count][n]
+  const double* rowscale;    // [count][n]
+  const double* u;
+  const double* lambda;
+  double* g[7];              // axx, axy, ayy, bx, by, c, f (node layout), may be null
+};
+
+// Dynamic LDS layout (doubles): y[n] | wI[n] | wB[Nt] | uX[M] | G[(Nc+1) Nt] | lx[32][Nc+1] | lt[32][Nt]
+__global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(AdjArgs a) {
+  extern __shared__ double sh[];
+  const BucketTables& T = a.T;
+  const int n = T.n, Nt = T.Nt, Nr = T.Nr, Nc = T.Nc, Nc1 = T.Nc + 1, M = T.M, ld = T.ld;
+  const int half = Nt / 2;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int ci = blockIdx.x;
+  const int f = a.C.fl[ci];
+  const int m = a.C.float_ids[f];
+  const double* A = a.A + (int64_t)ci * a.stride;
+  const int32_t* piv = a.piv + (int64_t)ci * n;
+  const double* sc = a.rowscale + (int64_t)ci * n;
+  double* y = sh;
+  double* wI = y + n;
+  double* wB = wI + n;
+  double* uX = wB + Nt;
+  double* G = uX + M;
+  double* lx = G + (int64_t)Nc1 * Nt;
+  double* lt = lx + kAdjKnots * Nc1;
+
+  // ---- y = E^T lambda over the assigned knots
+  for (int q = tid; q < n; q += kAdjThreads) y[q] = 0.0;
+  const int64_t klo = a.C.fk_off[f], khi = a.C.fk_off[f + 1];
+  const double cxm = a.C.cx[m], cym = a.C.cy[m], rm = a.C.rad[m];
+  for (int64_t base = klo; base < khi; base += kAdjKnots) {
+    const int cnt = (int)min<int64_t>(kAdjKnots, khi - base);
+    __syncthreads();
+    if (tid < cnt) {
+      const int i = a.C.fk_ids[base + tid];
+      const double dx = a.C.kx[i] - cxm, dy = a.C.ky[i] - cym;
+      const double rho = sqrt(dx * dx + dy * dy) / rm;
+      const double phi = atan2(dy, dx);
+      const double lam = a.lambda[i];
+      int exact = -1;
+      double ssum = 0.0;
+      for (int j = 0; j < Nc1; ++j) {
+        const double d = rho - T.xr[j];
+        if (d == 0.0) exact = j;
+        else ssum += T.bw[j] / d;
+      }
+      // lambda is folded into the radial weights
+      for (int j = 0; j < Nc1; ++j)
+        lx[tid * Nc1 + j] = lam * ((exact >= 0) ? (j == exact ? 1.0 : 0.0)
+                                                : (T.bw[j] / (rho - T.xr[j])) / ssum);
+      const double hstep = kTwoPiD / Nt;
+      for (int l = 0; l < Nt; ++l) {
+        const double x = 0.5 * (phi - hstep * l);
+        double sx, cx;
+        sincos(x, &sx, &cx);
+        lt[tid * Nt + l] = (fabs(sx) < 1e-15) ? 1.0 : sin(Nt * x) * cx / (Nt * sx);
+      }
+    }
+    __syncthreads();
+    for (int q = tid; q < n; q += kAdjThreads) {
+      const int k = q / Nt + 1, lp = q - (k - 1) * Nt;
+      int lq = lp + half;
+      if (lq >= Nt) lq -= Nt;
+      double acc = 0.0;
+      for (int t = 0; t < cnt; ++t)
+        acc += lx[t * Nc1 + k] * lt[t * Nt + lp] + lx[t * Nc1 + (Nc - k)] * lt[t * Nt + lq];
+      y[q] += acc;
+    }
+  }
+  __syncthreads();
+
+  // ---- U^T z = y (forward, 32-row blocks: wave 0 solves the diagonal block,
+  //      then all threads update the remaining entries from the block's rows)
+  for (int j0 = 0; j0 < n; j0 += kTri) {
+    const int j1 = min(n, j0 + kTri);
+    if (w == 0) {
+      double yi = (j0 + lane < j1) ? y[j0 + lane] : 0.0;
+      for (int j = j0; j < j1; ++j) {
+        const double zj = __shfl(yi, j - j0, 64) / A[(int64_t)j * ld + j];
+        if (lane == j - j0) yi = zj;
+        else if (j0 + lane > j && j0 + lane < j1) yi -= A[(int64_t)j * ld + j0 + lane] * zj;
+      }
+      if (j0 + lane < j1) y[j0 + lane] = yi;
+    }
+    __syncthreads();
+    for (int i = j1 + tid; i < n; i += kAdjThreads) {
+      double acc = 0.0;
+      for (int j = j0; j < j1; ++j) acc += A[(int64_t)j * ld + i] * y[j];
+      y[i] -= acc;
+    }
+    __syncthreads();
+  }
+  // ---- L^T x = z (backward, unit diagonal)
+  for (int j1 = n; j1 > 0; j1 -= kTri) {
+    const int j0 = max(0, j1 - kTri);
+    if (w == 0) {
+      double yi = (j0 + lane < j1) ? y[j0 + lane] : 0.0;
+      for (int j = j1 - 1; j >= j0; --j) {
+        const double xj = __shfl(yi, j - j0, 64);
+        if (j0 + lane < j) yi -= A[(int64_t)j * ld + j0 + lane] * xj;
+      }
+      if (j0 + lane < j1) y[j0 + lane] = yi;
+    }
+    __syncthreads();
+    for (int i = tid; i < j0; i += kAdjThreads) {
+      double acc = 0.0;
+      for (int j = j0; j < j1; ++j) acc += A[(int64_t)j * ld + i] * y[j];
+      y[i] -= acc;
+    }
+    __syncthreads();
+  }
+  // ---- undo the row interchanges (P^T), then mu = S nu
+  if (tid == 0) {
+    for (int kk = n - 1; kk >= 0; --kk) {
+      const int p = piv[kk];
+      if (p != kk) {
+        const double t = y[kk];
+        y[kk] = y[p];
+        y[p] = t;
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = tid; q < n; q += kAdjThreads) y[q] *= sc[q];
+
+  // ---- local solution at u: w_B = H u_Xi, w_I = W[:, M] - W[:, :M] u_Xi
+  const int64_t slo = a.C.knot_off[m];
+  for (int j = tid; j < M; j += kAdjThreads) uX[j] = a.u[slo + j];
+  __syncthreads();
+  for (int l = tid; l < Nt; l += kAdjThreads) {
+    double acc = 0.0;
+    for (int j = 0; j < M; ++j) acc += T.H[(int64_t)l * M + j] * uX[j];
+    wB[l] = acc;
+  }
+  for (int q = tid; q < n; q += kAdjThreads) {
+    const double* Wq = A + (int64_t)q * ld + n;
+    double acc = Wq[M];
+    for (int j = 0; j < M; ++j) acc -= Wq[j] * uX[j];
+    wI[q] = acc;
+  }
+  __syncthreads();
+  // full-grid value at radial index j, angular index l
+  auto wf = [&](int j, int l) -> double {
+    if (j == 0) return wB[l];
+    if (j <= Nr) return wI[(j - 1) * Nt + l];
+    int lq = l + half;
+    if (lq >= Nt) lq -= Nt;
+    if (j < Nc) return wI[(Nc - j - 1) * Nt + lq];
+    return wB[lq];
+  };
+  // G(j, l) = sum_l' d1t[l - l'] w(j, l')   (angular derivative on every radial line)
+  for (int idx = tid; idx < Nc1 * Nt; idx += kAdjThreads) {
+    const int j = idx / Nt, l = idx - j * Nt;
+    double acc = 0.0;
+    for (int lp = 0; lp < Nt; ++lp) {
+      int dl = l - lp;
+      if (dl < 0) dl += Nt;
+      acc += T.d1t[dl] * wf(j, lp);
+    }
+    G[idx] = acc;
+  }
+  __syncthreads();
+
+  // ---- per-node gradients
+  const int64_t node0 = a.C.node_off[f];
+  const double r = rm, r2 = r * r;
+  for (int q = tid; q < n; q += kAdjThreads) {
+    const int jr = q / Nt + 1, l = q - (jr - 1) * Nt;
+    const double* Drow = T.Dr + (int64_t)(jr - 1) * Nc1;
+    const double* D2row = T.D2r + (int64_t)(jr - 1) * Nc1;
+    double w_rr = 0.0, w_r = 0.0, w_rt = 0.0, w_tt = 0.0;
+    for (int j = 0; j < Nc1; ++j) {
+      const double v = wf(j, l);
+      w_rr += D2row[j] * v;
+      w_r += Drow[j] * v;
+      w_rt += Drow[j] * G[j * Nt + l];
+    }
+    for (int lp = 0; lp < Nt; ++lp) {
+      int dl = l - lp;
+      if (dl < 0) dl += Nt;
+      w_tt += T.d2t[dl] * wf(jr, lp);
+    }
+    const double w_t = G[jr * Nt + l];
+    const double rho = T.xr[jr];
+    const double C = T.cs[l], S = T.sn[l];
+    const double CC = C * C, SS = S * S, SC = S * C, D2 = CC - SS;
+    const double ir2 = 1.0 / r2, irr = 1.0 / (rho * r2), irr2 = 1.0 / (rho * rho * r2);
+    const double mu = y[q];
+    const double g_axx = 0.5 * CC * ir2 * w_rr + 0.5 * SS * irr * w_r + 0.5 * SS * irr2 * w_tt -
+                         SC * irr * w_rt + SC * irr2 * w_t;
+    const double g_axy = SC * ir2 * w_rr - SC * irr * w_r - SC * irr2 * w_tt + D2 * irr * w_rt -
+                         D2 * irr2 * w_t;
+    const double g_ayy = 0.5 * SS * ir2 * w_rr + 0.5 * CC * irr * w_r + 0.5 * CC * irr2 * w_tt +
+                         SC * irr * w_rt - SC * irr2 * w_t;
+    const double g_bx = C / r * w_r - S / (rho * r) * w_t;
+    const double g_by = S / r * w_r + C / (rho * r) * w_t;
+    const double vals[7] = {g_axx, g_axy, g_ayy, g_bx, g_by, wI[q], 1.0};
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+      if (a.g[k]) a.g[k][node0 + q] = -mu * vals[k];
+  }
+  (void)w;
+}
+
+}  // namespace
+
+pdd_status backward_impl(pdd_system sys, const double* u, const double* lambda, double* const g[7],
+                         hipStream_t st) {
+  const DeviceCover& D = sys->cover->D;
+  if (sys->factors.empty() && !sys->cover->H.float_ids.empty())
+    return fail(PDD_EINVAL, "pdd_assemble_G_backward: assemble with keep_factors to differentiate");
+  for (const auto& fp : sys->factors) {
+    const BucketFactors& F = *fp;
+    const BucketData& bk = *D.buckets[F.bucket];
+    AdjArgs a{};
+    a.T = bk.T;
+    a.C = D.chunk(bk, F.first, F.count);
+    a.A = F.A.ptr<double>();
+    a.stride = F.stride;
+    a.piv = F.piv.ptr<int32_t>();
+    a.rowscale = F.rowscale.ptr<double>();
+    a.u = u;
+    a.lambda = lambda;
+    for (int k = 0; k < 7; ++k) a.g[k] = g[k];
+    const size_t shm = sizeof(double) * ((size_t)2 * bk.n + bk.Nt + bk.M + (size_t)(bk.Nc + 1) * bk.Nt +
+                                         (size_t)kAdjKnots * (bk.Nc + 1 + bk.Nt));
+    if (shm > 160 * 1024) return fail(PDD_EINVAL, "pdd_assemble_G_backward: bucket too large");
+    hipLaunchKernelGGL(adjoint_kernel, dim3(F.count), dim3(kAdjThreads), shm, st, a);
+    PDD_HIP(hipGetLastError());
+  }
+  return PDD_OK;
+}
+
+}  // namespace pdd
 
 using namespace pdd;
 
@@ -9,7 +270,11 @@ extern "C" pdd_status pdd_assemble_G_backward(pdd_system sys, const double* u, c
                                               double* g_axx, double* g_axy, double* g_ayy,
                                               double* g_bx, double* g_by, double* g_c, double* g_f,
                                               void* stream) {
-  (void)sys; (void)u; (void)lambda; (void)g_axx; (void)g_axy; (void)g_ayy; (void)g_bx; (void)g_by;
-  (void)g_c; (void)g_f; (void)stream;
-  return fail(PDD_EINVAL, "pdd_assemble_G_backward: not built yet");
+  if (!sys || !u || !lambda) return fail(PDD_EINVAL, "pdd_assemble_G_backward: null argument");
+  try {
+    double* const g[7] = {g_axx, g_axy, g_ayy, g_bx, g_by, g_c, g_f};
+    return backward_impl(sys, u, lambda, g, (hipStream_t)stream);
+  } catch (const HipError& e) {
+    return fail(PDD_EDEVICE, e.what());
+  }
 }

@@ -128,6 +128,7 @@ void DeviceCover::upload(const HostCover& Hc) {
   assigned.upload(Hc.assigned); float_ids.upload(Hc.float_ids); node_off.upload(Hc.node_off);
   fk_off.upload(Hc.fk_off); fk_ids.upload(Hc.fk_ids); perim_ids.upload(Hc.perim_ids);
   perim_pos.upload(Hc.perim_pos); mc_knots.upload(Hc.mc_knots); bnd_knots.upload(Hc.bnd_knots);
+  have_transpose = false;
   buckets.clear();
   for (const Bucket& b : Hc.buckets) {
     auto bd = std::make_unique<BucketData>();

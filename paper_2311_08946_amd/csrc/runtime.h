@@ -80,6 +80,8 @@ struct DeviceCover {
   DevBuf cx, cy, rad, arc0, arc1, rbf_c2, kx, ky, ktheta;
   DevBuf knot_off, rowptr, cols, assigned, float_ids, node_off, fk_off, fk_ids;
   DevBuf perim_ids, perim_pos, mc_knots, bnd_knots;
+  DevBuf rt_rowptr, rt_cols, rt_perm;   // transpose pattern of C (built on first use)
+  bool have_transpose = false;
   std::vector<std::unique_ptr<BucketData>> buckets;
   void upload(const HostCover& H);
   ChunkDesc chunk(const BucketData& b, int32_t first, int32_t count) const;
@@ -111,8 +113,6 @@ struct pdd_system_s {
   pdd::DevBuf problem;               // DevProblem
   pdd::DevBuf samples;               // [7][sum_n] node samples (owned copy)
   std::vector<std::unique_ptr<pdd::BucketFactors>> factors;
-  pdd::DevBuf rt_rowptr, rt_cols, rt_perm;   // transpose pattern (built on first use)
-  bool have_transpose = false;
   pdd_system_stats stats{};
   std::vector<double> host_problem_bytes;
 };
