@@ -50,15 +50,18 @@ struct PhaseTimer {
   ~PhaseTimer() {
     for (auto& e : evs) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
   }
-  int begin(int phase) {
+  std::vector<hipStream_t> on;
+  int begin(int phase, hipStream_t s = nullptr) {
     Ev e{phase, nullptr, nullptr};
     PDD_HIP(hipEventCreate(&e.a));
     PDD_HIP(hipEventCreate(&e.b));
-    PDD_HIP(hipEventRecord(e.a, st));
+    hipStream_t q = s ? s : st;
+    PDD_HIP(hipEventRecord(e.a, q));
     evs.push_back(e);
+    on.push_back(q);
     return (int)evs.size() - 1;
   }
-  void end(int idx) { PDD_HIP(hipEventRecord(evs[idx].b, st)); }
+  void end(int idx) { PDD_HIP(hipEventRecord(evs[idx].b, on[idx])); }
   float total(int phase) {
     float t = 0.0f;
     for (auto& e : evs)
@@ -159,68 +162,30 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
     timer.end(ev);
   }
 
-  // ---- floating rows, bucket by bucket, in chunks that fit the budget
+  // The Monte Carlo and boundary rows run on a second stream, concurrently
+  // with the floating rows; both write disjoint rows of the CSR arrays.
   DevBuf lu_fail;
   lu_fail.alloc(sizeof(uint64_t) * 4);
   PDD_HIP(hipMemsetAsync(lu_fail.ptr<void>(), 0, sizeof(uint64_t) * 4, st));
-  int32_t n_launch_spectral = 0;
-  std::vector<std::unique_ptr<BucketFactors>> transient;
-  for (size_t bi = 0; bi < D.buckets.size(); ++bi) {
-    BucketData& bk = *D.buckets[bi];
-    const int64_t stride = (int64_t)bk.n * bk.ld;
-    const int64_t per = stride * (int64_t)sizeof(double);
-    int64_t chunk = std::max<int64_t>(1, budget / per);
-    if (plan == PDD_PLAN_PER_CIRCLE) chunk = std::max<int64_t>(1, chunk);
-    for (int32_t first = 0; first < bk.count; first += (int32_t)chunk) {
-      const int32_t cnt = (int32_t)std::min<int64_t>(chunk, bk.count - first);
-      auto f = std::make_unique<BucketFactors>();
-      f->bucket = (int32_t)bi;
-      f->first = first;
-      f->count = cnt;
-      f->stride = stride;
-      f->A.alloc((size_t)cnt * per);
-      f->piv.alloc((size_t)cnt * bk.n * sizeof(int32_t));
-      f->rowscale.alloc((size_t)cnt * bk.n * sizeof(double));
-      f->status.alloc((size_t)cnt * sizeof(int32_t));
-      const int32_t step = (plan == PDD_PLAN_PER_CIRCLE) ? 1 : cnt;
-      for (int32_t s0 = 0; s0 < cnt; s0 += step) {
-        const int32_t c1 = std::min(step, cnt - s0);
-        ChunkDesc C = D.chunk(bk, first + s0, c1);
-        double* A = f->A.ptr<double>() + (int64_t)s0 * stride;
-        int e = timer.begin(PH_BUILD);
-        launch_colloc_build(bk.T, C, S, A, stride, f->rowscale.ptr<double>() + (int64_t)s0 * bk.n, st);
-        timer.end(e);
-        e = timer.begin(PH_LU);
-        launch_lu(bk.T, c1, A, stride, f->piv.ptr<int32_t>() + (int64_t)s0 * bk.n,
-                  f->status.ptr<int32_t>() + s0, st);
-        timer.end(e);
-        e = timer.begin(PH_SOLVE);
-        launch_backsolve(bk.T, c1, A, stride, st);
-        timer.end(e);
-        e = timer.begin(PH_EVAL);
-        launch_eval_scatter(bk.T, C, A, stride, sys->val.ptr<double>(), sys->b.ptr<double>(), st);
-        timer.end(e);
-        n_launch_spectral += 4;
-      }
-      PDD_HIP(hipGetLastError());
-      hipLaunchKernelGGL(reduce_i32_kernel, dim3(1), dim3(256), 0, st, f->status.ptr<int32_t>(),
-                         (int64_t)cnt, lu_fail.ptr<uint64_t>());
-      if (keep) sys->factors.push_back(std::move(f));
-      else transient.push_back(std::move(f));
-      if (!keep && transient.size() > 1) {
-        PDD_HIP(hipStreamSynchronize(st));
-        transient.erase(transient.begin(), transient.end() - 1);
-      }
-    }
-  }
+  if (!D.side) PDD_HIP(hipStreamCreateWithFlags(&D.side, hipStreamNonBlocking));
+  hipStream_t side = D.side;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  PDD_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+  PDD_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  } ev_guard{ev_fork, ev_join};
+  PDD_HIP(hipEventRecord(ev_fork, st));
+  PDD_HIP(hipStreamWaitEvent(side, ev_fork, 0));
 
-  // ---- perimeter rows by Monte Carlo
+  // ---- perimeter rows by Monte Carlo (side stream)
   const int64_t n_mc = (int64_t)H.mc_knots.size();
   const int64_t n_perim = (int64_t)H.perim_ids.size();
   DevBuf out_phi, out_g, out_steps, out_capped, gram, gram_status, hcirc;
   int32_t n_launch_mc = 0;
   if (n_mc > 0) {
-    const int e = timer.begin(PH_MC);
+    const int e = timer.begin(PH_MC, side);
     McArgs a{};
     a.mc_knots = D.mc_knots.ptr<int32_t>();
     a.assigned = D.assigned.ptr<int32_t>();
@@ -254,25 +219,77 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
     a.out_g = out_g.ptr<double>();
     a.out_steps = out_steps.ptr<uint64_t>();
     a.out_capped = out_capped.ptr<uint64_t>();
-    launch_mc_paths(P, dp.const_coef != 0, a, st);
-    launch_gram_cholesky(a, (int32_t)n_perim, gram.ptr<double>(), gram_status.ptr<int32_t>(), st);
+    launch_mc_paths(P, dp.const_coef != 0, a, side);
+    launch_gram_cholesky(a, (int32_t)n_perim, gram.ptr<double>(), gram_status.ptr<int32_t>(), side);
     launch_mc_finalize(a, (int32_t)n_mc, H.max_arc, gram.ptr<double>(), sys->val.ptr<double>(),
-                       sys->se.ptr<double>(), sys->b.ptr<double>(), sys->se_b.ptr<double>(), st);
+                       sys->se.ptr<double>(), sys->b.ptr<double>(), sys->se_b.ptr<double>(), side);
     PDD_HIP(hipGetLastError());
-    hipLaunchKernelGGL(reduce_u64_kernel, dim3(1), dim3(256), 0, st, out_steps.ptr<uint64_t>(),
+    hipLaunchKernelGGL(reduce_u64_kernel, dim3(1), dim3(256), 0, side, out_steps.ptr<uint64_t>(),
                        a.n_units, lu_fail.ptr<uint64_t>() + 1);
-    hipLaunchKernelGGL(reduce_u64_kernel, dim3(1), dim3(256), 0, st, out_capped.ptr<uint64_t>(),
+    hipLaunchKernelGGL(reduce_u64_kernel, dim3(1), dim3(256), 0, side, out_capped.ptr<uint64_t>(),
                        a.n_units, lu_fail.ptr<uint64_t>() + 2);
     if (n_perim > 0)
-      hipLaunchKernelGGL(reduce_i32_kernel, dim3(1), dim3(256), 0, st, gram_status.ptr<int32_t>(),
+      hipLaunchKernelGGL(reduce_i32_kernel, dim3(1), dim3(256), 0, side, gram_status.ptr<int32_t>(),
                          n_perim, lu_fail.ptr<uint64_t>() + 3);
     n_launch_mc = 3;
     timer.end(e);
   }
   launch_boundary_rows(P, D.bnd_knots.ptr<int32_t>(), (int32_t)H.bnd_knots.size(), D.kx.ptr<double>(),
                        D.ky.ptr<double>(), D.rowptr.ptr<int64_t>(), sys->val.ptr<double>(),
-                       sys->se.ptr<double>(), sys->b.ptr<double>(), sys->se_b.ptr<double>(), st);
+                       sys->se.ptr<double>(), sys->b.ptr<double>(), sys->se_b.ptr<double>(), side);
   PDD_HIP(hipGetLastError());
+  PDD_HIP(hipEventRecord(ev_join, side));
+
+  // ---- floating rows, bucket by bucket, in chunks that fit the budget
+  int32_t n_launch_spectral = 0;
+  std::vector<std::unique_ptr<BucketFactors>> transient;
+  for (size_t bi = 0; bi < D.buckets.size(); ++bi) {
+    BucketData& bk = *D.buckets[bi];
+    const int64_t stride = (int64_t)bk.n * bk.ld;
+    const int64_t per = stride * (int64_t)sizeof(double);
+    int64_t chunk = std::max<int64_t>(1, budget / per);
+    if (plan == PDD_PLAN_PER_CIRCLE) chunk = std::max<int64_t>(1, chunk);
+    for (int32_t first = 0; first < bk.count; first += (int32_t)chunk) {
+      const int32_t cnt = (int32_t)std::min<int64_t>(chunk, bk.count - first);
+      auto f = std::make_unique<BucketFactors>();
+      f->bucket = (int32_t)bi;
+      f->first = first;
+      f->count = cnt;
+      f->stride = stride;
+      f->A.alloc((size_t)cnt * per);
+      f->piv.alloc((size_t)cnt * bk.n * sizeof(int32_t));
+      f->rowscale.alloc((size_t)cnt * bk.n * sizeof(double));
+      f->status.alloc((size_t)cnt * sizeof(int32_t));
+      const int32_t step = (plan == PDD_PLAN_PER_CIRCLE) ? 1 : cnt;
+      for (int32_t s0 = 0; s0 < cnt; s0 += step) {
+        const int32_t c1 = std::min(step, cnt - s0);
+        ChunkDesc C = D.chunk(bk, first + s0, c1);
+        double* A = f->A.ptr<double>() + (int64_t)s0 * stride;
+        int e = timer.begin(PH_BUILD);
+        launch_colloc_build(bk.T, C, S, A, stride, f->rowscale.ptr<double>() + (int64_t)s0 * bk.n, st);
+        timer.end(e);
+        e = timer.begin(PH_LU);
+        launch_lu_solve(bk.T, c1, A, stride, f->piv.ptr<int32_t>() + (int64_t)s0 * bk.n,
+                        f->status.ptr<int32_t>() + s0, st);
+        timer.end(e);
+        e = timer.begin(PH_EVAL);
+        launch_eval_scatter(bk.T, C, A, stride, sys->val.ptr<double>(), sys->b.ptr<double>(), st);
+        timer.end(e);
+        n_launch_spectral += 3;
+      }
+      PDD_HIP(hipGetLastError());
+      hipLaunchKernelGGL(reduce_i32_kernel, dim3(1), dim3(256), 0, st, f->status.ptr<int32_t>(),
+                         (int64_t)cnt, lu_fail.ptr<uint64_t>());
+      if (keep) sys->factors.push_back(std::move(f));
+      else transient.push_back(std::move(f));
+      if (!keep && transient.size() > 1) {
+        PDD_HIP(hipStreamSynchronize(st));
+        transient.erase(transient.begin(), transient.end() - 1);
+      }
+    }
+  }
+
+  PDD_HIP(hipStreamWaitEvent(st, ev_join, 0));
   timer.end(t_all);
 
   uint64_t flags[4] = {0, 0, 0, 0};

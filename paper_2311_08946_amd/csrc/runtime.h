@@ -77,6 +77,8 @@ struct BucketData {
 struct DeviceCover {
   bool ready = false;
   int device = -1;
+  hipStream_t side = nullptr;           // second stream for the Monte Carlo rows
+  ~DeviceCover() { if (side) (void)hipStreamDestroy(side); }
   DevBuf cx, cy, rad, arc0, arc1, rbf_c2, kx, ky, ktheta;
   DevBuf knot_off, rowptr, cols, assigned, float_ids, node_off, fk_off, fk_ids;
   DevBuf perim_ids, perim_pos, mc_knots, bnd_knots;

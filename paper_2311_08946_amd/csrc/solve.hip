@@ -1,11 +1,18 @@
 // Solve of the interfacial system C u = r (and C^T lambda = g for the
-// adjoint) by BiCGStab on the device (Remark 2 asks for a distributed Krylov
-// solver; the paper's runs use preconditioned GMRES).
+// adjoint) by BiCGStab on the device.  The paper solves C u = r with GMRES and
+// a one-level restricted additive Schwarz preconditioner (Section 4, eqs.
+// 42-45); C has a unit diagonal, and plain BiCGStab converges in tens of
+// iterations on the covers here.
 //
-// The CSR matrix-vector product uses one wavefront per row with a fixed
-// reduction order; dot products reduce block partials in a fixed order, so
-// repeated solves give bitwise-identical iterates.  The scalars (rho, alpha,
-// omega, ...) stay on the device; the host reads one residual per iteration.
+// One iteration: p = r + beta (p - omega v); v = C p with per-block partial
+// sums of (r0, v); t = C s with s = r - alpha v formed on the fly and partial
+// sums of (t, s), (t, t); the x and r updates with partial sums of (r, r) and
+// (r0, r).  After each reducing kernel a one-workgroup kernel adds the
+// partials in a fixed order and updates the scalars (alpha, omega, beta, the
+// stopping test), so results are bitwise reproducible.  Every kernel returns at
+// once after the stopping test has fired, which lets the host enqueue several
+// iterations per status read.  Sparse rows are handled by 16-lane groups (four
+// rows per wavefront).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,133 +25,227 @@ namespace pdd {
 
 namespace {
 
-constexpr int kDotBlocks = 512;
 constexpr int kThreads = 256;
+constexpr int kRowsPerBlock = 16;   // 16 lanes per row, 4 rows per wavefront
+constexpr int kItersPerSync = 8;
 
-// scalar slots in device memory
-enum { S_RHO = 0, S_RHO_OLD, S_ALPHA, S_OMEGA, S_RV, S_TS, S_TT, S_RR, S_BB, S_BETA, S_COUNT };
+enum {
+  S_RHO = 0, S_ALPHA, S_OMEGA, S_BETA, S_RV, S_TS, S_TT, S_RR, S_BB, S_TOL2, S_DONE, S_FAIL,
+  S_ITER, S_COUNT
+};
 
-__global__ __launch_bounds__(256) void spmv_kernel(const int64_t* __restrict__ rowptr,
-                                                   const int32_t* __restrict__ cols,
-                                                   const double* __restrict__ val,
-                                                   const double* __restrict__ x,
-                                                   double* __restrict__ y, int64_t N,
-                                                   const double* __restrict__ b_minus) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (row >= N) return;
-  const int64_t lo = rowptr[row], hi = rowptr[row + 1];
+struct SolveCtx {
+  const int64_t* rowptr;
+  const int32_t* cols;
+  const double* val;
+  int64_t N;
+  double* x;
+  double* r;
+  double* r0;
+  double* p;
+  double* v;
+  double* t;
+  double* part;        // [2][nblocks] per-block partial sums
+  int nblocks;         // grid of the row kernels (one block per 16 rows)
+  int vblocks;         // grid of the element kernels (one block per 256 entries)
+  double* sc;          // scalars
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block sum in a fixed order (wave sums, then the four wave totals in order).
+__device__ __forceinline__ double block_sum(double v, double* s4) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) s4[w] = v;
+  __syncthreads();
+  return s4[0] + s4[1] + s4[2] + s4[3];
+}
+
+// Row of a 16-lane group: sum_k val[k] (y - beta z)[cols[k]], reduced inside the group.
+__device__ __forceinline__ double row16(const SolveCtx& c, int64_t row, const double* y,
+                                        const double* z, double beta, int sub) {
   double acc = 0.0;
-  for (int64_t k = lo + lane; k < hi; k += 64) acc += val[k] * x[cols[k]];
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (lane == 0) y[row] = b_minus ? b_minus[row] - acc : acc;
+  if (row < c.N) {
+    const int64_t lo = c.rowptr[row], hi = c.rowptr[row + 1];
+    for (int64_t k = lo + sub; k < hi; k += 16) {
+      const int32_t j = c.cols[k];
+      acc += c.val[k] * (z ? y[j] - beta * z[j] : y[j]);
+    }
+  }
+  for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+  return acc;
+}
+
+__global__ __launch_bounds__(kThreads) void init_kernel(SolveCtx c, const double* __restrict__ b,
+                                                        int use_guess) {
+  __shared__ double s4[4];
+  const int sub = threadIdx.x & 15;
+  const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 4);
+  // r = b - C x (x = 0 unless a guess is given)
+  const double ax = use_guess ? row16(c, row, c.x, nullptr, 0.0, sub) : 0.0;
+  double pbb = 0.0, prr = 0.0;
+  if (sub == 0 && row < c.N) {
+    const double ri = b[row] - ax;
+    if (!use_guess) c.x[row] = 0.0;
+    c.r[row] = ri;
+    c.r0[row] = ri;
+    c.p[row] = 0.0;
+    c.v[row] = 0.0;
+    pbb = b[row] * b[row];
+    prr = ri * ri;
+  }
+  const double sbb = block_sum(pbb, s4);
+  __syncthreads();
+  const double srr = block_sum(prr, s4);
+  if (threadIdx.x == 0) {
+    c.part[blockIdx.x] = sbb;
+    c.part[c.nblocks + blockIdx.x] = srr;
+  }
+}
+
+// Adds the partial sums of the previous kernel (fixed order) and updates the
+// scalars: stage 0 after init, 1 after v = C p, 2 after t = C s, 3 after the
+// x and r updates.
+__global__ __launch_bounds__(1024) void finalize_kernel(SolveCtx c, int nparts, int stage, double rtol) {
+  __shared__ double s16[16];
+  double* sc = c.sc;
+  if (stage != 0 && sc[S_DONE] != 0.0) return;
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 1024) {
+    a += c.part[i];
+    b += c.part[nparts + i];
+  }
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if (lane == 0) s16[w] = a;
+  __syncthreads();
+  double sa = 0.0;
+  for (int t = 0; t < 16; ++t) sa += s16[t];
+  __syncthreads();
+  if (lane == 0) s16[w] = b;
+  __syncthreads();
+  double sb = 0.0;
+  for (int t = 0; t < 16; ++t) sb += s16[t];
+  if (threadIdx.x != 0) return;
+  if (stage == 0) {
+    sc[S_BB] = sa;
+    sc[S_RR] = sb;
+    sc[S_RHO] = sb;           // (r0, r) with r0 = r
+    sc[S_ALPHA] = 1.0;
+    sc[S_OMEGA] = 1.0;
+    sc[S_BETA] = 0.0;
+    sc[S_TOL2] = rtol * rtol * sa;
+    sc[S_DONE] = (sb <= sc[S_TOL2]) ? 1.0 : 0.0;
+    sc[S_FAIL] = 0.0;
+    sc[S_ITER] = 0.0;
+  } else if (stage == 1) {
+    sc[S_RV] = sa;
+    sc[S_ALPHA] = sc[S_RHO] / sa;
+  } else if (stage == 2) {
+    sc[S_TS] = sa;
+    sc[S_TT] = sb;
+    sc[S_OMEGA] = (sb > 0.0) ? sa / sb : 0.0;
+  } else {
+    const double rr = sa, rho = sb;
+    sc[S_BETA] = (rho / sc[S_RHO]) * (sc[S_ALPHA] / sc[S_OMEGA]);
+    sc[S_RHO] = rho;
+    sc[S_RR] = rr;
+    sc[S_ITER] += 1.0;
+    const bool bad = !(rr == rr) || !isfinite(sc[S_BETA]) || sc[S_OMEGA] == 0.0 || rho == 0.0;
+    if (rr <= sc[S_TOL2]) {
+      sc[S_DONE] = 1.0;
+    } else if (bad) {
+      sc[S_DONE] = 1.0;
+      sc[S_FAIL] = 1.0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void update_p_kernel(SolveCtx c) {
+  if (c.sc[S_DONE] != 0.0) return;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= c.N) return;
+  const double beta = c.sc[S_BETA], omega = c.sc[S_OMEGA];
+  c.p[i] = c.r[i] + beta * (c.p[i] - omega * c.v[i]);
+}
+
+// v = C p, partial sums of (r0, v)
+__global__ __launch_bounds__(kThreads) void spmv_v_kernel(SolveCtx c) {
+  __shared__ double s4[4];
+  if (c.sc[S_DONE] != 0.0) return;
+  const int sub = threadIdx.x & 15;
+  const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 4);
+  const double vi = row16(c, row, c.p, nullptr, 0.0, sub);
+  double prv = 0.0;
+  if (sub == 0 && row < c.N) {
+    c.v[row] = vi;
+    prv = c.r0[row] * vi;
+  }
+  const double s = block_sum(prv, s4);
+  if (threadIdx.x == 0) {
+    c.part[blockIdx.x] = s;
+    c.part[c.nblocks + blockIdx.x] = 0.0;
+  }
+}
+
+// t = C s with s = r - alpha v, partial sums of (t, s) and (t, t)
+__global__ __launch_bounds__(kThreads) void spmv_t_kernel(SolveCtx c) {
+  __shared__ double s4[4];
+  if (c.sc[S_DONE] != 0.0) return;
+  const double alpha = c.sc[S_ALPHA];
+  const int sub = threadIdx.x & 15;
+  const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 4);
+  const double ti = row16(c, row, c.r, c.v, alpha, sub);
+  double pts = 0.0, ptt = 0.0;
+  if (sub == 0 && row < c.N) {
+    c.t[row] = ti;
+    const double si = c.r[row] - alpha * c.v[row];
+    pts = ti * si;
+    ptt = ti * ti;
+  }
+  const double sts = block_sum(pts, s4);
+  __syncthreads();
+  const double stt = block_sum(ptt, s4);
+  if (threadIdx.x == 0) {
+    c.part[blockIdx.x] = sts;
+    c.part[c.nblocks + blockIdx.x] = stt;
+  }
+}
+
+// x += alpha p + omega s; r = s - omega t; partial sums of (r, r) and (r0, r)
+__global__ __launch_bounds__(kThreads) void update_xr_kernel(SolveCtx c) {
+  __shared__ double s4[4];
+  if (c.sc[S_DONE] != 0.0) return;
+  const double alpha = c.sc[S_ALPHA], omega = c.sc[S_OMEGA];
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  double prr = 0.0, prho = 0.0;
+  if (i < c.N) {
+    const double si = c.r[i] - alpha * c.v[i];
+    c.x[i] = c.x[i] + alpha * c.p[i] + omega * si;
+    const double ri = si - omega * c.t[i];
+    c.r[i] = ri;
+    prr = ri * ri;
+    prho = c.r0[i] * ri;
+  }
+  const double srr = block_sum(prr, s4);
+  __syncthreads();
+  const double srho = block_sum(prho, s4);
+  if (threadIdx.x == 0) {
+    c.part[blockIdx.x] = srr;
+    c.part[c.vblocks + blockIdx.x] = srho;
+  }
 }
 
 __global__ void gather_kernel(const int64_t* __restrict__ perm, const double* __restrict__ src,
                               double* __restrict__ dst, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[perm[i]];
-}
-
-// partial[b] = sum over this block's strided range of a*b (fixed order)
-__device__ __forceinline__ double block_sum(double v) {
-  __shared__ double s[kThreads];
-  s[threadIdx.x] = v;
-  __syncthreads();
-  for (int off = kThreads / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
-    __syncthreads();
-  }
-  return s[0];
-}
-
-__global__ __launch_bounds__(256) void dot2_partial_kernel(const double* __restrict__ a,
-                                                           const double* __restrict__ b,
-                                                           const double* __restrict__ c,
-                                                           const double* __restrict__ d, int64_t n,
-                                                           double* __restrict__ part) {
-  double v1 = 0.0, v2 = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kThreads) {
-    v1 += a[i] * b[i];
-    if (c) v2 += c[i] * d[i];
-  }
-  const double s1 = block_sum(v1);
-  __syncthreads();
-  const double s2 = block_sum(v2);
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = s1;
-    part[kDotBlocks + blockIdx.x] = s2;
-  }
-}
-
-// Reduces the partials into slot `slot1` (and `slot2`) and updates the
-// derived BiCGStab scalars according to `stage`.
-__global__ __launch_bounds__(256) void dot_finalize_kernel(const double* __restrict__ part, int nb,
-                                                           double* __restrict__ sc, int slot1,
-                                                           int slot2, int stage) {
-  double v1 = 0.0, v2 = 0.0;
-  for (int i = threadIdx.x; i < nb; i += kThreads) {
-    v1 += part[i];
-    v2 += part[kDotBlocks + i];
-  }
-  const double s1 = block_sum(v1);
-  __syncthreads();
-  const double s2 = block_sum(v2);
-  if (threadIdx.x == 0) {
-    sc[slot1] = s1;
-    if (slot2 >= 0) sc[slot2] = s2;
-    if (stage == 1) {            // rho known: beta = (rho / rho_old) (alpha / omega)
-      const double beta = (sc[S_RHO] / sc[S_RHO_OLD]) * (sc[S_ALPHA] / sc[S_OMEGA]);
-      sc[S_BETA] = beta;
-      sc[S_RHO_OLD] = sc[S_RHO];
-    } else if (stage == 2) {     // (r0, v) known: alpha = rho / (r0, v)
-      sc[S_ALPHA] = sc[S_RHO] / sc[S_RV];
-    } else if (stage == 3) {     // (t, s), (t, t) known: omega = (t, s) / (t, t)
-      sc[S_OMEGA] = (sc[S_TT] > 0.0) ? sc[S_TS] / sc[S_TT] : 0.0;
-    }
-  }
-}
-
-__global__ void update_p_kernel(double* __restrict__ p, const double* __restrict__ r,
-                                const double* __restrict__ v, const double* __restrict__ sc,
-                                int64_t n, int first) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (first) p[i] = r[i];
-  else p[i] = r[i] + sc[S_BETA] * (p[i] - sc[S_OMEGA] * v[i]);
-}
-
-__global__ void update_s_kernel(double* __restrict__ s, const double* __restrict__ r,
-                                const double* __restrict__ v, const double* __restrict__ sc,
-                                int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) s[i] = r[i] - sc[S_ALPHA] * v[i];
-}
-
-__global__ void update_xr_kernel(double* __restrict__ x, double* __restrict__ r,
-                                 const double* __restrict__ p, const double* __restrict__ s,
-                                 const double* __restrict__ t, const double* __restrict__ sc,
-                                 int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double a = sc[S_ALPHA], w = sc[S_OMEGA];
-  x[i] = x[i] + a * p[i] + w * s[i];
-  r[i] = s[i] - w * t[i];
-}
-
-__global__ void copy_kernel(double* __restrict__ d, const double* __restrict__ s, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) d[i] = s[i];
-}
-
-__global__ void init_scalars_kernel(double* sc) {
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < S_COUNT; ++k) sc[k] = 0.0;
-    sc[S_RHO_OLD] = 1.0;
-    sc[S_ALPHA] = 1.0;
-    sc[S_OMEGA] = 1.0;
-  }
 }
 
 }  // namespace
@@ -181,74 +282,60 @@ pdd_status solve_impl(pdd_system sys, const double* rhs, double* u, int32_t tran
   const double rtol = (opts && opts->rtol > 0.0) ? opts->rtol : 1e-12;
   const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 2000;
   const bool guess = opts && opts->use_guess;
-  const int64_t* rowptr = D.rowptr.ptr<int64_t>();
-  const int32_t* cols = D.cols.ptr<int32_t>();
-  const double* val = sys->val.ptr<double>();
+  SolveCtx c{};
+  c.rowptr = D.rowptr.ptr<int64_t>();
+  c.cols = D.cols.ptr<int32_t>();
+  c.val = sys->val.ptr<double>();
+  c.N = N;
+  c.x = u;
   DevBuf valT;
   if (transpose) {
     ensure_transpose(sys->cover);
     valT.alloc(nnz * sizeof(double));
     hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st,
-                       D.rt_perm.ptr<int64_t>(), val, valT.ptr<double>(), nnz);
-    rowptr = D.rt_rowptr.ptr<int64_t>();
-    cols = D.rt_cols.ptr<int32_t>();
-    val = valT.ptr<double>();
+                       D.rt_perm.ptr<int64_t>(), c.val, valT.ptr<double>(), nnz);
+    c.rowptr = D.rt_rowptr.ptr<int64_t>();
+    c.cols = D.rt_cols.ptr<int32_t>();
+    c.val = valT.ptr<double>();
   }
   const double* b = rhs ? rhs : sys->b.ptr<double>();
+  c.nblocks = (int)((N + kRowsPerBlock - 1) / kRowsPerBlock);
+  c.vblocks = (int)((N + kThreads - 1) / kThreads);
   DevBuf work;
-  work.alloc(sizeof(double) * (6 * N + 2 * kDotBlocks + S_COUNT));
-  double* r = work.ptr<double>();
-  double* r0 = r + N;
-  double* p = r0 + N;
-  double* v = p + N;
-  double* s = v + N;
-  double* t = s + N;
-  double* part = t + N;
-  double* sc = part + 2 * kDotBlocks;
-  const unsigned vb = (unsigned)((N + 255) / 256);
-  const unsigned rb = (unsigned)((N + 3) / 4);
-  const unsigned db = (unsigned)std::min<int64_t>(kDotBlocks, (N + kThreads - 1) / kThreads);
-  auto dot = [&](const double* a1, const double* b1, const double* a2, const double* b2, int s1,
-                 int s2, int stage) {
-    hipLaunchKernelGGL(dot2_partial_kernel, dim3(db), dim3(kThreads), 0, st, a1, b1, a2, b2, N, part);
-    hipLaunchKernelGGL(dot_finalize_kernel, dim3(1), dim3(kThreads), 0, st, part, (int)db, sc, s1,
-                       s2, stage);
-  };
-  hipLaunchKernelGGL(init_scalars_kernel, dim3(1), dim3(64), 0, st, sc);
-  if (!guess) PDD_HIP(hipMemsetAsync(u, 0, N * sizeof(double), st));
-  hipLaunchKernelGGL(spmv_kernel, dim3(rb), dim3(256), 0, st, rowptr, cols, val, u, r, N, b);
-  hipLaunchKernelGGL(copy_kernel, dim3(vb), dim3(256), 0, st, r0, r, N);
-  dot(b, b, r, r, S_BB, S_RR, 0);
+  work.alloc(sizeof(double) * (5 * N + 2 * (int64_t)c.nblocks + S_COUNT));
+  c.r = work.ptr<double>();
+  c.r0 = c.r + N;
+  c.p = c.r0 + N;
+  c.v = c.p + N;
+  c.t = c.v + N;
+  c.part = c.t + N;
+  c.sc = c.part + 2 * (int64_t)c.nblocks;
+  const dim3 rb(c.nblocks), vb(c.vblocks);
+  hipLaunchKernelGGL(init_kernel, rb, dim3(kThreads), 0, st, c, b, guess ? 1 : 0);
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, st, c, c.nblocks, 0, rtol);
   double host[S_COUNT];
-  PDD_HIP(hipMemcpyAsync(host, sc, sizeof(host), hipMemcpyDeviceToHost, st));
-  PDD_HIP(hipStreamSynchronize(st));
-  const double bnorm = std::sqrt(host[S_BB]);
-  double rel = bnorm > 0.0 ? std::sqrt(host[S_RR]) / bnorm : 0.0;
-  int it = 0;
-  bool ok = bnorm == 0.0 || rel <= rtol;
-  if (bnorm == 0.0) PDD_HIP(hipMemsetAsync(u, 0, N * sizeof(double), st));
-  // p = v = 0 and rho_old = alpha = omega = 1 make the first update p = r
-  PDD_HIP(hipMemsetAsync(p, 0, 2 * N * sizeof(double), st));
-  while (!ok && it < max_iter) {
-    dot(r0, r, nullptr, nullptr, S_RHO, -1, 1);
-    hipLaunchKernelGGL(update_p_kernel, dim3(vb), dim3(256), 0, st, p, r, v, sc, N, 0);
-    hipLaunchKernelGGL(spmv_kernel, dim3(rb), dim3(256), 0, st, rowptr, cols, val, p, v, N,
-                       (const double*)nullptr);
-    dot(r0, v, nullptr, nullptr, S_RV, -1, 2);
-    hipLaunchKernelGGL(update_s_kernel, dim3(vb), dim3(256), 0, st, s, r, v, sc, N);
-    hipLaunchKernelGGL(spmv_kernel, dim3(rb), dim3(256), 0, st, rowptr, cols, val, s, t, N,
-                       (const double*)nullptr);
-    dot(t, s, t, t, S_TS, S_TT, 3);
-    hipLaunchKernelGGL(update_xr_kernel, dim3(vb), dim3(256), 0, st, u, r, p, s, t, sc, N);
-    dot(r, r, nullptr, nullptr, S_RR, -1, 0);
+  int enq = 0;
+  for (;;) {
+    const int batch = std::min(kItersPerSync, max_iter - enq);
+    for (int k = 0; k < batch; ++k) {
+      hipLaunchKernelGGL(update_p_kernel, vb, dim3(kThreads), 0, st, c);
+      hipLaunchKernelGGL(spmv_v_kernel, rb, dim3(kThreads), 0, st, c);
+      hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, st, c, c.nblocks, 1, rtol);
+      hipLaunchKernelGGL(spmv_t_kernel, rb, dim3(kThreads), 0, st, c);
+      hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, st, c, c.nblocks, 2, rtol);
+      hipLaunchKernelGGL(update_xr_kernel, vb, dim3(kThreads), 0, st, c);
+      hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, st, c, c.vblocks, 3, rtol);
+    }
+    enq += batch;
     PDD_HIP(hipGetLastError());
-    PDD_HIP(hipMemcpyAsync(host, sc, sizeof(host), hipMemcpyDeviceToHost, st));
+    PDD_HIP(hipMemcpyAsync(host, c.sc, sizeof(host), hipMemcpyDeviceToHost, st));
     PDD_HIP(hipStreamSynchronize(st));
-    ++it;
-    rel = std::sqrt(host[S_RR]) / bnorm;
-    if (!std::isfinite(rel) || host[S_RV] == 0.0 || host[S_RHO] == 0.0) break;
-    ok = rel <= rtol;
+    if (host[S_DONE] != 0.0 || enq >= max_iter) break;
   }
+  const bool ok = host[S_DONE] != 0.0 && host[S_FAIL] == 0.0;
+  const double bnorm = std::sqrt(host[S_BB]);
+  const double rel = bnorm > 0.0 ? std::sqrt(host[S_RR]) / bnorm : 0.0;
+  const int it = (int)host[S_ITER];
   if (info) {
     info->iterations = it;
     info->converged = ok ? 1 : 0;

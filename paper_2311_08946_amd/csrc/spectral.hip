@@ -1,7 +1,7 @@
 // Floating rows of C and r on gfx950: polar Chebyshev x Fourier collocation of
-// the local problems (Section 2.4 eqs. 31-35, Section 3.3 eqs. 40-41), batched
-// LU with partial pivoting on FP64 MFMA, back substitution, interpolation at
-// the assigned knots and scatter into the CSR values.
+// the local problems (Section 2.4 eqs. 31-35, Section 3.3 eqs. 40-41),
+// interpolation of the local solutions at the assigned knots and scatter into
+// the CSR values.  The batched LU and back substitution are in lu.hip.
 //
 // Matrix layout (one per floating circle, row-major, leading dimension ld):
 //   columns [0, n)        A_II, the collocation rows at the n interior nodes
@@ -152,324 +152,6 @@ void launch_colloc_build(const BucketTables& T, const ChunkDesc& C, const NodeSa
   size_t shm = sizeof(double) * 4 * T.Nt;
   hipLaunchKernelGGL(colloc_build_kernel, grid, dim3(256), shm, st, T, C, S, A, mat_stride,
                      rowscale);
-}
-
-// ----------------------------------------------------------------- K2: LU
-
-// One workgroup (8 wavefronts) factorises one matrix, right-looking with a
-// panel of NB columns.  The panel is held in registers (thread t owns rows
-// k0 + t + 512 s), factorised column by column with a workgroup-wide pivot
-// search; its row interchanges are then applied to the remaining columns, the
-// block row of U is formed by a triangular solve, and the trailing matrix
-// (including the right-hand-side columns) is updated on FP64 MFMA
-// (v_mfma_f64_16x16x4: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k,
-// D[i][j] in register v of lane j + 16 (i mod 4) with v = i / 4).
-namespace {
-
-constexpr int kLuThreads = 512;
-constexpr int kTileR = 128;    // trailing tile rows (4 x 32 per wave group)
-constexpr int kTileC = 64;     // trailing tile cols (2 x 32)
-
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-
-template <int NB>
-__device__ __forceinline__ void trailing_update(double* __restrict__ A, int ld, int n, int k0,
-                                                double (*s_Lt)[kTileR + 4],
-                                                double (*s_Ut)[kTileC + 4]) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wr = w >> 1, wc = w & 1;
-  const int R0 = k0 + NB;
-  for (int rb = R0; rb < n; rb += kTileR) {
-    // L21 band, transposed into LDS
-    for (int idx = tid; idx < kTileR * NB; idx += kLuThreads) {
-      const int i = idx / NB, k = idx - i * NB;
-      const int row = rb + i;
-      s_Lt[k][i] = (row < n) ? -A[(int64_t)row * ld + k0 + k] : 0.0;
-    }
-    for (int cb = R0; cb < ld; cb += kTileC) {
-      for (int idx = tid; idx < NB * kTileC; idx += kLuThreads) {
-        const int k = idx / kTileC, j = idx - k * kTileC;
-        const int col = cb + j;
-        s_Ut[k][j] = (col < ld) ? A[(int64_t)(k0 + k) * ld + col] : 0.0;
-      }
-      __syncthreads();
-      dbl4 acc[2][2];
-      const int rbase = rb + 32 * wr, cbase = cb + 32 * wc;
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = rbase + 16 * bi + 4 * v + (lane >> 4);
-            const int col = cbase + 16 * bj + (lane & 15);
-            acc[bi][bj][v] = (row < n && col < ld) ? A[(int64_t)row * ld + col] : 0.0;
-          }
-#pragma unroll
-      for (int ks = 0; ks < NB / 4; ++ks) {
-        const int kr = 4 * ks + (lane >> 4);
-        double a[2], b[2];
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi) a[bi] = s_Lt[kr][32 * wr + 16 * bi + (lane & 15)];
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) b[bj] = s_Ut[kr][32 * wc + 16 * bj + (lane & 15)];
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-          for (int bj = 0; bj < 2; ++bj)
-            acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
-      }
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = rbase + 16 * bi + 4 * v + (lane >> 4);
-            const int col = cbase + 16 * bj + (lane & 15);
-            if (row < n && col < ld) A[(int64_t)row * ld + col] = acc[bi][bj][v];
-          }
-      __syncthreads();
-    }
-  }
-}
-
-template <int ROWS, int NB>
-__global__ __launch_bounds__(kLuThreads) void lu_kernel(double* __restrict__ A0, int n, int ld,
-                                                        int64_t stride, int32_t* __restrict__ piv0,
-                                                        int32_t* __restrict__ status) {
-  __shared__ double s_prow[NB], s_krow[NB];
-  __shared__ double s_L11[NB][NB + 1];
-  __shared__ double s_redv[kLuThreads / 64];
-  __shared__ int s_redi[kLuThreads / 64];
-  __shared__ int s_piv[NB];
-  __shared__ double s_Lt[NB][kTileR + 4];
-  __shared__ double s_Ut[NB][kTileC + 4];
-
-  double* A = A0 + (int64_t)blockIdx.x * stride;
-  int32_t* piv = piv0 + (int64_t)blockIdx.x * n;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  int singular = 0;
-  double P[ROWS][NB];
-
-  for (int k0 = 0; k0 < n; k0 += NB) {
-    const int pw = min(NB, n - k0);
-#pragma unroll
-    for (int s = 0; s < ROWS; ++s) {
-      const int row = k0 + tid + kLuThreads * s;
-#pragma unroll
-      for (int c = 0; c < NB; ++c)
-        P[s][c] = (row < n && c < pw) ? A[(int64_t)row * ld + k0 + c] : 0.0;
-    }
-#pragma unroll 1
-    for (int c = 0; c < pw; ++c) {
-      const int kk = k0 + c;
-      // column c of the owned rows (register arrays are indexed statically)
-      double colv[ROWS];
-#pragma unroll
-      for (int s = 0; s < ROWS; ++s) {
-        double v = 0.0;
-#pragma unroll
-        for (int cc = 0; cc < NB; ++cc) v = (cc == c) ? P[s][cc] : v;
-        colv[s] = v;
-      }
-      // pivot search: largest |a|, smallest row on ties
-      double bv = -1.0;
-      int bi = 0x7fffffff;
-#pragma unroll
-      for (int s = 0; s < ROWS; ++s) {
-        const int row = k0 + tid + kLuThreads * s;
-        const double v = fabs(colv[s]);
-        if (row >= kk && row < n && v > bv) { bv = v; bi = row; }
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(bv, off, kWave);
-        const int oi = __shfl_xor(bi, off, kWave);
-        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-      }
-      if (lane == 0) { s_redv[w] = bv; s_redi[w] = bi; }
-      __syncthreads();
-      bv = s_redv[0];
-      bi = s_redi[0];
-      for (int t = 1; t < kLuThreads / 64; ++t) {
-        const double ov = s_redv[t];
-        const int oi = s_redi[t];
-        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-      }
-      const int p = (bv > 0.0) ? bi : kk;
-      if (!(bv > 0.0)) singular = 1;
-      // interchange rows kk and p inside the panel (owners exchange via LDS)
-      const int tp = (p - k0) & (kLuThreads - 1), sp = (p - k0) / kLuThreads;
-      if (tid == tp) {
-#pragma unroll
-        for (int s = 0; s < ROWS; ++s)
-          if (s == sp)
-#pragma unroll
-            for (int cc = 0; cc < NB; ++cc) s_prow[cc] = P[s][cc];
-      }
-      if (tid == c) {
-#pragma unroll
-        for (int cc = 0; cc < NB; ++cc) s_krow[cc] = P[0][cc];
-      }
-      __syncthreads();
-      if (tid == c) {
-#pragma unroll
-        for (int cc = 0; cc < NB; ++cc) P[0][cc] = s_prow[cc];
-      }
-      if (tid == tp && p != kk) {
-#pragma unroll
-        for (int s = 0; s < ROWS; ++s)
-          if (s == sp)
-#pragma unroll
-            for (int cc = 0; cc < NB; ++cc) P[s][cc] = s_krow[cc];
-      }
-      const double pv = s_prow[c];
-      if (pv != 0.0) {
-        const double inv = 1.0 / pv;
-#pragma unroll
-        for (int s = 0; s < ROWS; ++s) {
-          const int row = k0 + tid + kLuThreads * s;
-          if (row > kk && row < n) {
-            double lv = 0.0;
-#pragma unroll
-            for (int cc = 0; cc < NB; ++cc) lv = (cc == c) ? P[s][cc] : lv;
-            lv *= inv;
-#pragma unroll
-            for (int cc = 0; cc < NB; ++cc) {
-              const double upd = P[s][cc] - lv * s_prow[cc];
-              P[s][cc] = (cc == c) ? lv : ((cc > c) ? upd : P[s][cc]);
-            }
-          }
-        }
-      }
-      if (tid == 0) {
-        s_piv[c] = p;
-        piv[kk] = p;
-      }
-      __syncthreads();
-    }
-    // panel back to memory
-#pragma unroll
-    for (int s = 0; s < ROWS; ++s) {
-      const int row = k0 + tid + kLuThreads * s;
-      if (row < n)
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-          if (c < pw) A[(int64_t)row * ld + k0 + c] = P[s][c];
-    }
-    // the panel's interchanges on every other column (each thread owns columns)
-    for (int col = tid; col < ld; col += kLuThreads) {
-      if (col >= k0 && col < k0 + pw) continue;
-      for (int c = 0; c < pw; ++c) {
-        const int p = s_piv[c];
-        const int kk = k0 + c;
-        if (p != kk) {
-          const double t0 = A[(int64_t)kk * ld + col];
-          A[(int64_t)kk * ld + col] = A[(int64_t)p * ld + col];
-          A[(int64_t)p * ld + col] = t0;
-        }
-      }
-    }
-    if (tid < pw) {
-#pragma unroll
-      for (int c = 0; c < NB; ++c) s_L11[tid][c] = P[0][c];
-    }
-    __syncthreads();
-    // block row of U: L11^-1 A12 (unit lower triangular)
-    for (int col = k0 + pw + tid; col < ld; col += kLuThreads) {
-      double x[NB];
-#pragma unroll
-      for (int c = 0; c < NB; ++c) x[c] = (c < pw) ? A[(int64_t)(k0 + c) * ld + col] : 0.0;
-#pragma unroll 1
-      for (int c = 1; c < pw; ++c) {
-        double acc = 0.0;
-#pragma unroll
-        for (int c2 = 0; c2 < NB; ++c2) acc += (c2 < c) ? s_L11[c][c2] * x[c2] : 0.0;
-#pragma unroll
-        for (int c3 = 0; c3 < NB; ++c3) x[c3] = (c3 == c) ? x[c3] - acc : x[c3];
-      }
-#pragma unroll
-      for (int c = 0; c < NB; ++c)
-        if (c < pw) A[(int64_t)(k0 + c) * ld + col] = x[c];
-    }
-    __syncthreads();
-    if (k0 + NB < n) trailing_update<NB>(A, ld, n, k0, s_Lt, s_Ut);
-    __syncthreads();
-  }
-  if (tid == 0) status[blockIdx.x] = singular;
-  (void)lane;
-}
-
-}  // namespace
-
-void launch_lu(const BucketTables& T, int32_t count, double* A, int64_t mat_stride,
-               int32_t* piv, int32_t* status, hipStream_t st) {
-  const int n = T.n;
-  if (n <= 512)
-    hipLaunchKernelGGL((lu_kernel<1, 32>), dim3(count), dim3(kLuThreads), 0, st, A, n, T.ld,
-                       mat_stride, piv, status);
-  else if (n <= 1024)
-    hipLaunchKernelGGL((lu_kernel<2, 32>), dim3(count), dim3(kLuThreads), 0, st, A, n, T.ld,
-                       mat_stride, piv, status);
-  else if (n <= 2048)
-    hipLaunchKernelGGL((lu_kernel<4, 16>), dim3(count), dim3(kLuThreads), 0, st, A, n, T.ld,
-                       mat_stride, piv, status);
-  else
-    hipLaunchKernelGGL((lu_kernel<8, 8>), dim3(count), dim3(kLuThreads), 0, st, A, n, T.ld,
-                       mat_stride, piv, status);
-}
-
-// ------------------------------------------------------ K3: back substitution
-
-// U W = R' on the right-hand-side columns, 32-row blocks from the bottom: the
-// block is first reduced by the rows already solved, then solved by one
-// thread per right-hand side.
-__global__ __launch_bounds__(512) void backsolve_kernel(double* __restrict__ A0, int n, int ld,
-                                                        int nrhs, int64_t stride) {
-  constexpr int BR = 32;
-  double* A = A0 + (int64_t)blockIdx.x * stride;
-  const int tid = threadIdx.x;
-  const int i = tid >> 4;         // row in block (0..31)
-  const int cg = tid & 15;        // column group
-  for (int k1 = n; k1 > 0; k1 -= BR) {
-    const int k0 = max(0, k1 - BR);
-    if (k0 + i < k1) {
-      const double* urow = A + (int64_t)(k0 + i) * ld;
-      double acc[9];
-#pragma unroll
-      for (int u = 0; u < 9; ++u) acc[u] = 0.0;
-      for (int q = k1; q < n; ++q) {
-        const double uv = urow[q];
-        const double* wrow = A + (int64_t)q * ld + n;
-#pragma unroll
-        for (int u = 0; u < 9; ++u) {
-          const int c = cg + 16 * u;
-          if (c < nrhs) acc[u] += uv * wrow[c];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 9; ++u) {
-        const int c = cg + 16 * u;
-        if (c < nrhs) A[(int64_t)(k0 + i) * ld + n + c] -= acc[u];
-      }
-    }
-    __syncthreads();
-    for (int c = tid; c < nrhs; c += 512) {
-      for (int r = k1 - 1; r >= k0; --r) {
-        const double* urow = A + (int64_t)r * ld;
-        double x = urow[n + c];
-        for (int q = r + 1; q < k1; ++q) x -= urow[q] * A[(int64_t)q * ld + n + c];
-        A[(int64_t)r * ld + n + c] = x / urow[r];
-      }
-    }
-    __syncthreads();
-  }
-}
-
-void launch_backsolve(const BucketTables& T, int32_t count, double* A, int64_t mat_stride,
-                      hipStream_t st) {
-  hipLaunchKernelGGL(backsolve_kernel, dim3(count), dim3(512), 0, st, A, T.n, T.ld, T.nrhs,
-                     mat_stride);
 }
 
 // ------------------------------------------- K4: knot evaluation and scatter
