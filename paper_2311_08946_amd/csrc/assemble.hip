@@ -104,6 +104,10 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
     if (mc->paths < 2 || !(mc->h > 0.0) || mc->n_batches < 2 || mc->n_batches > 63 ||
         mc->step_cap <= 0 || mc->paths < mc->n_batches || mc->paths > ((int64_t)1 << 32))
       return fail(PDD_EINVAL, "pdd_assemble_G: bad Monte Carlo options");
+    const int64_t tri = (int64_t)H.max_arc * (H.max_arc + 1) / 2;
+    if ((tri + (int64_t)(mc->n_batches + 1) * H.max_arc) * (int64_t)sizeof(double) > 160 * 1024)
+      return fail(PDD_EINVAL, "pdd_assemble_G: arc length and batch count exceed the 160 KiB LDS budget "
+                              "of the Monte Carlo finalisation");
   }
   int dev = 0;
   PDD_HIP(hipGetDevice(&dev));
@@ -208,7 +212,7 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
     a.step_cap = mc->step_cap;
     a.n_units = n_mc * mc->n_batches;
     a.out_stride = std::max<int64_t>(1, H.max_arc);
-    a.gram_stride = (int64_t)H.max_arc * H.max_arc;
+    a.gram_stride = (int64_t)H.max_arc * (H.max_arc + 1) / 2;
     out_phi.alloc(std::max<int64_t>(1, a.n_units * a.out_stride) * sizeof(double));
     out_g.alloc(std::max<int64_t>(1, a.n_units) * sizeof(double));
     out_steps.alloc(std::max<int64_t>(1, a.n_units) * sizeof(uint64_t));
@@ -243,6 +247,8 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
   // ---- floating rows, bucket by bucket, in chunks that fit the budget
   int32_t n_launch_spectral = 0;
   std::vector<std::unique_ptr<BucketFactors>> transient;
+  DevBuf lu_work;
+  size_t lu_work_bytes = 0;
   for (size_t bi = 0; bi < D.buckets.size(); ++bi) {
     BucketData& bk = *D.buckets[bi];
     const int64_t stride = (int64_t)bk.n * bk.ld;
@@ -260,6 +266,12 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
       f->piv.alloc((size_t)cnt * bk.n * sizeof(int32_t));
       f->rowscale.alloc((size_t)cnt * bk.n * sizeof(double));
       f->status.alloc((size_t)cnt * sizeof(int32_t));
+      const size_t wbytes = lu_workspace_bytes(plan == PDD_PLAN_PER_CIRCLE ? 1 : cnt, bk.n);
+      if (lu_work_bytes < wbytes) {
+        PDD_HIP(hipStreamSynchronize(st));
+        lu_work.alloc(wbytes);
+        lu_work_bytes = wbytes;
+      }
       const int32_t step = (plan == PDD_PLAN_PER_CIRCLE) ? 1 : cnt;
       for (int32_t s0 = 0; s0 < cnt; s0 += step) {
         const int32_t c1 = std::min(step, cnt - s0);
@@ -269,13 +281,13 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
         launch_colloc_build(bk.T, C, S, A, stride, f->rowscale.ptr<double>() + (int64_t)s0 * bk.n, st);
         timer.end(e);
         e = timer.begin(PH_LU);
-        launch_lu_solve(bk.T, c1, A, stride, f->piv.ptr<int32_t>() + (int64_t)s0 * bk.n,
-                        f->status.ptr<int32_t>() + s0, st);
+        const int lu_launches = launch_lu_solve(bk.T, c1, A, stride, f->piv.ptr<int32_t>() + (int64_t)s0 * bk.n,
+                        f->status.ptr<int32_t>() + s0, lu_work.ptr<void>(), st);
         timer.end(e);
         e = timer.begin(PH_EVAL);
         launch_eval_scatter(bk.T, C, A, stride, sys->val.ptr<double>(), sys->b.ptr<double>(), st);
         timer.end(e);
-        n_launch_spectral += 3;
+        n_launch_spectral += 2 + lu_launches;
       }
       PDD_HIP(hipGetLastError());
       hipLaunchKernelGGL(reduce_i32_kernel, dim3(1), dim3(256), 0, st, f->status.ptr<int32_t>(),

@@ -226,7 +226,7 @@ pdd_status pdd_build_cover(const pdd_domain* domain, int32_t n_circles, const do
       if (cv->H.floating[m] && (cv->H.M[m] + 1 > 136 || (int64_t)cv->H.Nr[m] * cv->H.Nt[m] > 4096))
         return fail(PDD_EINVAL, "pdd_build_cover: M + 1 <= 136 and Nr Ntheta <= 4096 are supported");
     }
-    if (cv->H.max_arc > 192) return fail(PDD_EINVAL, "pdd_build_cover: arcs of more than 192 knots");
+    if (cv->H.max_arc > 160) return fail(PDD_EINVAL, "pdd_build_cover: arcs of more than 160 knots");
     *out = cv.release();
     return PDD_OK;
   } catch (const std::bad_alloc&) {

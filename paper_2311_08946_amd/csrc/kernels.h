@@ -49,9 +49,12 @@ void launch_colloc_build(const BucketTables& T, const ChunkDesc& C, const NodeSa
                          double* A, int64_t mat_stride, double* rowscale, hipStream_t st);
 // K2/K3: in-place LU with partial pivoting of the n x n block, applied to all ld
 // columns (forward elimination of the right-hand sides), then back
-// substitution U W = R' on the right-hand-side columns.
-void launch_lu_solve(const BucketTables& T, int32_t count, double* A, int64_t mat_stride,
-                     int32_t* piv, int32_t* status, hipStream_t st);
+// substitution U W = R' on the right-hand-side columns.  `work` holds
+// lu_workspace_bytes(count, n) bytes of device memory.
+size_t lu_workspace_bytes(int32_t count, int32_t n);
+// Returns the number of kernel launches issued.
+int launch_lu_solve(const BucketTables& T, int32_t count, double* A, int64_t mat_stride,
+                    int32_t* piv, int32_t* status, void* work, hipStream_t st);
 // K4: interpolation at the assigned knots and scatter into CSR values and r.
 void launch_eval_scatter(const BucketTables& T, const ChunkDesc& C, const double* A,
                          int64_t mat_stride, double* val, double* b, hipStream_t st);

@@ -2,23 +2,34 @@
 // solution of the right-hand sides (Section 3.3, eqs. 40-41; the paper uses
 // one QR factorisation per circle, here LU with partial pivoting).
 //
-// One workgroup (8 wavefronts) owns one matrix [A_II | R] (n x ld, row-major).
-// Two-level right-looking factorisation:
-//   * outer panels of kOuter = 128 columns;
-//   * each outer panel is factorised by sub-panels of NBI columns held in
-//     registers (thread t owns rows k0 + t + 512 s), column by column with a
-//     workgroup-wide pivot search; the sub-panel's interchanges, its block row
-//     of U and the update of the rest of the outer panel follow;
-//   * the outer panel's interchanges are applied to all other columns, its
-//     block row of U is formed by a blocked triangular solve, and the trailing
-//     matrix -- including the right-hand-side columns, which are thereby
-//     eliminated forward -- is updated with K = 128.
-// Back substitution U W = R' then runs right-looking from the bottom in
-// 128-row blocks.  Every rectangular update A[r, c] -= A[r, k] A[k, c] goes
-// through one FP64 MFMA routine (v_mfma_f64_16x16x4: A[i][k] in lane i + 16 k,
-// B[k][j] in lane j + 16 k, D[i][j] in register i / 4 of lane j + 16 (i mod 4))
-// with 128 x 128 workgroup tiles and K streamed through LDS in chunks of 32,
-// the next chunk's global loads issued before the current chunk's MFMAs.
+// Each matrix is the augmented array [A_II | R] (n x ld, row-major, R in
+// columns n .. n + nrhs).  Right-looking blocked factorisation in steps of
+// kOuter = 128 columns, three launches per step over the whole batch:
+//   * lu_panel_kernel (one workgroup per matrix): factorises the step's panel
+//     A[K0:n, K0:K0+128] by sub-panels of NB columns held in registers
+//     (thread t owns rows k0 + t + 512 s), column by column with a
+//     workgroup-wide pivot search, each followed by its interchanges, its
+//     block row of U and the update of the rest of the panel; it then stores
+//     the step's composed row permutation and the inverses of the 32 x 32
+//     unit-lower diagonal blocks of L11 in a per-matrix work area;
+//   * lu_urow_kernel (one workgroup per matrix and 128-column tile outside
+//     the panel): applies the step's interchanges to the tile and, right of
+//     the panel, forms the tile of U12 = L11^-1 A12 by 32-row blocks (the
+//     stored inverse on MFMA, then an MFMA update of the rows below);
+//   * lu_update_kernel (one workgroup per matrix and 128 x 128 trailing tile):
+//     A22 -= L21 U12 with K = 128 -- the right-hand-side columns are part of
+//     the trailing matrix and are thereby eliminated forward.
+// The back substitution U W = R' then runs from the bottom in 128-row blocks:
+// lu_bdiag_kernel solves a diagonal block (32-row triangles through the
+// inverses of U's diagonal blocks, stored by the panel kernel, and MFMA
+// updates), lu_bupd_kernel updates the rows above it.
+// Every rectangular update A[r, c] -= A[r, k] A[k, c] goes through one FP64
+// MFMA routine (v_mfma_f64_16x16x4: A[i][k] in lane i + 16 k, B[k][j] in
+// lane j + 16 k, D[i][j] in register i / 4 of lane j + 16 (i mod 4)) with
+// 128 x 128 workgroup tiles and K streamed through LDS in chunks of 32, the
+// next chunk's global loads issued before the current chunk's MFMAs.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace pdd {
@@ -31,6 +42,7 @@ constexpr int kGT = 128;        // update tile (rows and columns)
 constexpr int kGK = 32;         // K chunk
 constexpr int kPad = 1;
 constexpr int kWave = 64;
+constexpr int kTB = 32;         // triangular block
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -137,311 +149,493 @@ __device__ __attribute__((always_inline)) void gemm_sub(double* __restrict__ A, 
   __syncthreads();
 }
 
-// Rows [a, a+w) of columns [c0, c1) <- L^-1 (rows), L = unit lower triangle of
-// A[a:a+w, a:a+w] (w <= NB).  Ends with a barrier.
-template <int NB>
-__device__ __noinline__ void trsm_rows(double* __restrict__ A, int ld, int a, int w, int c0, int c1,
-                          double (*sL)[NB + 1]) {
+// Triangular blocks (w <= NB <= 32 rows) are solved through their explicit
+// inverse: one wavefront inverts the w x w diagonal block column by column
+// (lane j forms column j with fully unrolled substitution), then every
+// wavefront multiplies 16-column blocks of the right-hand side by it on MFMA.
+struct TriLds {
+  double blk[32][33];   // the diagonal block, zero-padded
+  double inv[32][33];   // its inverse, zero-padded
+};
+
+// T = (unit lower triangle of A[a:a+w, a:a+w])^-1 if LOWER, else
+// (upper triangle with diagonal)^-1.  Ends with a barrier.
+template <int NB, bool LOWER>
+__device__ __attribute__((always_inline)) void tri_inverse(const double* __restrict__ A, int ld, int a,
+                                                            int w, TriLds& t) {
   const int tid = threadIdx.x;
   for (int idx = tid; idx < NB * NB; idx += kThreads) {
     const int i = idx / NB, j = idx - i * NB;
-    sL[i][j] = (i < w && j < w) ? A[(int64_t)(a + i) * ld + a + j] : 0.0;
+    t.blk[i][j] = (i < w && j < w) ? A[(a + i) * ld + a + j] : (i == j ? 1.0 : 0.0);
   }
   __syncthreads();
-  for (int col = c0 + tid; col < c1; col += kThreads) {
-    double x[NB];
-#pragma unroll
-    for (int c = 0; c < NB; ++c) x[c] = (c < w) ? A[(int64_t)(a + c) * ld + col] : 0.0;
+  if (tid < NB) {
+    // lane j forms column j of the inverse in place in t.inv (its own column
+    // only, so no synchronisation is needed inside the substitution)
+    const int j = tid;
+    if (LOWER) {
 #pragma unroll 1
-    for (int c = 1; c < w; ++c) {
-      double acc = 0.0;
-#pragma unroll
-      for (int c2 = 0; c2 < NB; ++c2) acc += (c2 < c) ? sL[c][c2] * x[c2] : 0.0;
-#pragma unroll
-      for (int c3 = 0; c3 < NB; ++c3) x[c3] = (c3 == c) ? x[c3] - acc : x[c3];
+      for (int i = 0; i < NB; ++i) {
+        double v = (i == j) ? 1.0 : 0.0;
+#pragma unroll 8
+        for (int k = 0; k < i; ++k) v -= t.blk[i][k] * t.inv[k][j];
+        t.inv[i][j] = v;
+      }
+    } else {
+#pragma unroll 1
+      for (int i = NB - 1; i >= 0; --i) {
+        double v = (i == j) ? 1.0 : 0.0;
+#pragma unroll 8
+        for (int k = i + 1; k < NB; ++k) v -= t.blk[i][k] * t.inv[k][j];
+        t.inv[i][j] = v / t.blk[i][i];
+      }
     }
-#pragma unroll
-    for (int c = 0; c < NB; ++c)
-      if (c < w) A[(int64_t)(a + c) * ld + col] = x[c];
+#pragma unroll 1
+    for (int i = 0; i < NB; ++i)
+      if (i >= w || j >= w) t.inv[i][j] = 0.0;
   }
   __syncthreads();
 }
 
-// Applies the interchanges (base + t) <-> piv[t], t = 0..cnt-1 in order
-// (cnt <= 128), to columns [lo, hi) except [skip0, skip1), as one row
-// permutation: thread 0 composes the interchanges over the touched rows (at
-// most 2 cnt), then the touched rows are staged through LDS in blocks of 32
-// columns and written back permuted.  Ends with a barrier.
+// Rows [a, a+w) of columns [c0, c1) <- T (rows), T = t.inv (w <= NB).  Each
+// wavefront takes 16-column blocks; the block's w rows are loaded in the MFMA
+// B layout, multiplied, and written back in place.  Ends with a barrier.
+template <int NB>
+__device__ __attribute__((always_inline)) void tri_apply(double* __restrict__ A, int ld, int a, int w,
+                                                          int c0, int c1, const TriLds& t) {
+  constexpr int BI = NB / 16, KS = NB / 4;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  double ta[BI][KS];
+#pragma unroll
+  for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) ta[bi][ks] = t.inv[16 * bi + li][4 * ks + lk];
+  const int roff = (a + lk) * ld;
+#pragma unroll 1
+  for (int cb = c0 + 16 * wv; cb < c1; cb += 16 * (kThreads / kWave)) {
+    const int col = cb + li;
+    const bool cok = col < c1;
+    double xb[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const bool ok = cok && 4 * ks + lk < w;
+      const double v = A[ok ? roff + 4 * ks * ld + col : 0];
+      xb[ks] = ok ? v : 0.0;
+    }
+    dbl4 acc[BI];
+#pragma unroll
+    for (int bi = 0; bi < BI; ++bi) acc[bi] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int bi = 0; bi < BI; ++bi)
+        acc[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[bi][ks], xb[ks], acc[bi], 0, 0, 0);
+#pragma unroll
+    for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * bi + 4 * v + lk;
+        if (cok && r < w) A[(a + r) * ld + col] = acc[bi][v];
+      }
+  }
+  __syncthreads();
+}
+
+// Per-matrix work area of one step (global memory).
+struct LuWork {
+  double inv[kOuter / kTB][kTB][kTB];  // inverses of L11's unit-lower diagonal blocks
+  int rows[2 * kOuter];                // rows touched by the step's interchanges
+  int src[2 * kOuter];                 // slot whose old contents end up in each slot's row
+  int count;
+  int pad[63];
+};
+
+// Composes the interchanges (base + t) <-> piv[t], t = 0..cnt-1 in order
+// (cnt <= 128), into one permutation of at most 2 cnt rows: rows[e] receives
+// the old contents of rows[src[e]].  Run by one thread.
+__device__ void compose_perm(const int* __restrict__ piv, int base, int cnt, int* __restrict__ rows,
+                             int* __restrict__ src, int* __restrict__ count) {
+  int nt = cnt;
+  for (int t = 0; t < cnt; ++t) {
+    rows[t] = base + t;
+    src[t] = t;
+  }
+  for (int t = 0; t < cnt; ++t) {
+    const int b = piv[t];
+    if (b == base + t) continue;
+    int sb;
+    if (b < base + cnt) {
+      sb = b - base;
+    } else {
+      sb = -1;
+      for (int e = cnt; e < nt; ++e)
+        if (rows[e] == b) { sb = e; break; }
+      if (sb < 0) {
+        sb = nt++;
+        rows[sb] = b;
+        src[sb] = sb;
+      }
+    }
+    const int tmp = src[t];
+    src[t] = src[sb];
+    src[sb] = tmp;
+  }
+  *count = nt;
+}
+
 struct PermLds {
-  int rows[256];      // touched row ids: [base, base + cnt) then the extra rows
-  int src[256];       // slot whose (old) contents end up in this slot's row
+  int rows[2 * kOuter];
+  int src[2 * kOuter];
   int count;
 };
 
-__device__ __noinline__ void permute_rows(double* __restrict__ A, int ld, const int* __restrict__ piv,
-                                          int base, int cnt, int lo, int hi, int skip0, int skip1,
-                                          PermLds& pl, double* __restrict__ scratch) {
+// Applies a composed permutation to columns [lo, hi) except [skip0, skip1):
+// the touched rows are staged through `scratch` (2 kOuter x 32 doubles) in
+// blocks of 32 columns and written back permuted.  Ends with a barrier.
+__device__ __attribute__((always_inline)) void apply_perm(double* __restrict__ A, int ld, const PermLds& pl,
+                                                           int lo, int hi, int skip0, int skip1,
+                                                           double* __restrict__ scratch) {
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    int nt = cnt;
-    int* cont = pl.src;   // slot of the original row whose contents sit in each slot
-    for (int t = 0; t < cnt; ++t) {
-      pl.rows[t] = base + t;
-      cont[t] = t;
-    }
-    for (int t = 0; t < cnt; ++t) {
-      const int b = piv[t];
-      if (b == base + t) continue;
-      int sb;
-      if (b < base + cnt) {
-        sb = b - base;
-      } else {
-        sb = -1;
-        for (int e = cnt; e < nt; ++e)
-          if (pl.rows[e] == b) { sb = e; break; }
-        if (sb < 0) {
-          sb = nt++;
-          pl.rows[sb] = b;
-          cont[sb] = sb;
-        }
-      }
-      const int tmp = cont[t];
-      cont[t] = cont[sb];
-      cont[sb] = tmp;
-    }
-    pl.count = nt;
-  }
-  __syncthreads();
   const int nt = pl.count;
   for (int c0 = lo; c0 < hi; c0 += 32) {
     const bool skip_block = (c0 >= skip0 && c0 + 32 <= skip1);
     if (!skip_block) {
       for (int idx = tid; idx < nt * 32; idx += kThreads) {
         const int e = idx >> 5, c = c0 + (idx & 31);
-        if (c < hi && !(c >= skip0 && c < skip1)) scratch[idx] = A[(int64_t)pl.rows[e] * ld + c];
+        if (c < hi && !(c >= skip0 && c < skip1)) scratch[idx] = A[pl.rows[e] * ld + c];
       }
     }
     __syncthreads();
     if (!skip_block) {
       for (int idx = tid; idx < nt * 32; idx += kThreads) {
         const int e = idx >> 5, cc = idx & 31, c = c0 + cc;
-        if (c < hi && !(c >= skip0 && c < skip1))
-          A[(int64_t)pl.rows[e] * ld + c] = scratch[(pl.src[e] << 5) + cc];
+        if (c < hi && !(c >= skip0 && c < skip1)) A[pl.rows[e] * ld + c] = scratch[(pl.src[e] << 5) + cc];
       }
     }
     __syncthreads();
   }
 }
 
-// Rows [a, a+w) of columns [c0, c1) <- U^-1 (rows), U = upper triangle of
-// A[a:a+w, a:a+w] with its diagonal (w <= NB).  Ends with a barrier.
+// LDS of the sub-panel factorisation: per column, each wavefront's best pivot
+// candidate (value, row index, full sub-panel row) and the current row kk,
+// double-buffered by column parity so that one barrier per column suffices.
 template <int NB>
-__device__ __noinline__ void trsm_upper_rows(double* __restrict__ A, int ld, int a, int w, int c0,
-                                             int c1, double (*sU)[NB + 1]) {
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < NB * NB; idx += kThreads) {
-    const int i = idx / NB, j = idx - i * NB;
-    sU[i][j] = (i < w && j < w) ? A[(int64_t)(a + i) * ld + a + j] : (i == j ? 1.0 : 0.0);
+struct PanelLds {
+  double cand[2][kThreads / kWave][NB];
+  double krow[2][NB];
+  double cv[2][kThreads / kWave];
+  int ci[2][kThreads / kWave];
+};
+
+// Factorises the sub-panel A[k0:n, k0:k0+pw] (pw <= NB) held in registers:
+// thread t owns rows k0 + t + kThreads s.  The column index is a compile-time
+// constant in the unrolled loop, so the register file is never indexed
+// dynamically.  Pivot: largest magnitude, lowest row index on ties.
+template <int ROWS, int NB>
+__device__ __attribute__((always_inline)) void factor_subpanel(double* __restrict__ A, int ld, int n,
+                                                                int k0, int pw, int K0,
+                                                                int* __restrict__ s_piv,
+                                                                int32_t* __restrict__ piv,
+                                                                PanelLds<NB>& pl, int& singular) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double P[ROWS][NB];
+#pragma unroll
+  for (int s = 0; s < ROWS; ++s) {
+    const int row = k0 + tid + kThreads * s;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) P[s][c] = (row < n && c < pw) ? A[row * ld + k0 + c] : 0.0;
   }
-  __syncthreads();
-  for (int col = c0 + tid; col < c1; col += kThreads) {
-    double x[NB];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) x[c] = (c < w) ? A[(int64_t)(a + c) * ld + col] : 0.0;
-#pragma unroll 1
-    for (int c = w - 1; c >= 0; --c) {
-      double acc = 0.0, xc = 0.0;
+  for (int c = 0; c < NB; ++c) {
+    if (c < pw) {                            // uniform
+      const int kk = k0 + c, buf = c & 1;
+      double bv = -1.0;
+      int bi = 0x7fffffff;
 #pragma unroll
-      for (int c2 = 0; c2 < NB; ++c2) {
-        acc += (c2 > c) ? sU[c][c2] * x[c2] : 0.0;
-        xc = (c2 == c) ? x[c2] : xc;
+      for (int s = 0; s < ROWS; ++s) {
+        const int row = k0 + tid + kThreads * s;
+        const double v = fabs(P[s][c]);
+        if (row >= kk && row < n && v > bv) { bv = v; bi = row; }
       }
-      const double v = (xc - acc) / sU[c][c];
 #pragma unroll
-      for (int c3 = 0; c3 < NB; ++c3) x[c3] = (c3 == c) ? v : x[c3];
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off, kWave);
+        const int oi = __shfl_xor(bi, off, kWave);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+      }
+#pragma unroll
+      for (int s = 0; s < ROWS; ++s) {
+        const int row = k0 + tid + kThreads * s;
+        if (row == bi)
+#pragma unroll
+          for (int cc = 0; cc < NB; ++cc) pl.cand[buf][w][cc] = P[s][cc];
+      }
+      if (lane == 0) { pl.cv[buf][w] = bv; pl.ci[buf][w] = bi; }
+      if (tid == c)
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) pl.krow[buf][cc] = P[0][cc];
+      __syncthreads();
+      double gv = pl.cv[buf][0];
+      int gi = pl.ci[buf][0], gw = 0;
+#pragma unroll
+      for (int t = 1; t < kThreads / kWave; ++t) {
+        const double ov = pl.cv[buf][t];
+        const int oi = pl.ci[buf][t];
+        if (ov > gv || (ov == gv && oi < gi)) { gv = ov; gi = oi; gw = t; }
+      }
+      const bool ok = gv > 0.0;
+      if (!ok) singular = 1;
+      const int p = ok ? gi : kk;
+      const double* prow = ok ? pl.cand[buf][gw] : pl.krow[buf];
+      if (p != kk) {
+#pragma unroll
+        for (int s = 0; s < ROWS; ++s) {
+          const int row = k0 + tid + kThreads * s;
+          if (row == p)
+#pragma unroll
+            for (int cc = 0; cc < NB; ++cc) P[s][cc] = pl.krow[buf][cc];
+        }
+      }
+      if (tid == c)
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) P[0][cc] = prow[cc];
+      if (ok) {
+        const double inv = 1.0 / prow[c];
+#pragma unroll
+        for (int s = 0; s < ROWS; ++s) {
+          const int row = k0 + tid + kThreads * s;
+          if (row > kk && row < n) {
+            const double l = P[s][c] * inv;
+            P[s][c] = l;
+#pragma unroll
+            for (int cc = 0; cc < NB; ++cc)
+              if (cc > c) P[s][cc] -= l * prow[cc];
+          }
+        }
+      }
+      if (tid == 0) {
+        s_piv[kk - K0] = p;
+        piv[kk] = p;
+      }
     }
+  }
 #pragma unroll
-    for (int c = 0; c < NB; ++c)
-      if (c < w) A[(int64_t)(a + c) * ld + col] = x[c];
+  for (int s = 0; s < ROWS; ++s) {
+    const int row = k0 + tid + kThreads * s;
+    if (row < n)
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c < pw) A[row * ld + k0 + c] = P[s][c];
   }
   __syncthreads();
 }
 
 template <int ROWS, int NB>
-__global__ __launch_bounds__(kThreads) void lu_solve_kernel(double* __restrict__ A0, int n, int ld,
-                                                            int nrhs, int64_t stride,
-                                                            int32_t* __restrict__ piv0,
-                                                            int32_t* __restrict__ status) {
-  __shared__ GemmLds g;
-  __shared__ double s_prow[NB], s_krow[NB];
-  __shared__ double s_L[NB][NB + 1];
-  __shared__ double s_redv[kThreads / 64];
-  __shared__ int s_redi[kThreads / 64];
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void lu_panel_kernel(double* __restrict__ A0, int n, int ld,
+                                                            int64_t stride, int32_t* __restrict__ piv0,
+                                                            int32_t* __restrict__ status,
+                                                            LuWork* __restrict__ work,
+                                                            double* __restrict__ uinv0, int K0) {
+  constexpr int TB = NB < 16 ? 16 : NB;
+  __shared__ union {
+    GemmLds g;
+    TriLds t;
+  } u;
+  __shared__ PanelLds<NB> s_pl;
   __shared__ int s_piv[kOuter];
   __shared__ PermLds s_perm;
 
-  double* A = A0 + (int64_t)blockIdx.x * stride;
-  int32_t* piv = piv0 + (int64_t)blockIdx.x * n;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int m = blockIdx.x;
+  double* A = A0 + (int64_t)m * stride;
+  int32_t* piv = piv0 + (int64_t)m * n;
+  LuWork* W = work + m;
+  double* uinv = uinv0 + (int64_t)m * ((n + kTB - 1) / kTB) * kTB * kTB;
+  const int tid = threadIdx.x;
+  const int kb = min(kOuter, n - K0);
   int singular = 0;
-
-  for (int K0 = 0; K0 < n; K0 += kOuter) {
-    const int kb = min(kOuter, n - K0);
-    for (int k0 = K0; k0 < K0 + kb; k0 += NB) {
-      const int pw = min(NB, K0 + kb - k0);
-      // ---- sub-panel in registers
-      double P[ROWS][NB];
-#pragma unroll
-      for (int s = 0; s < ROWS; ++s) {
-        const int row = k0 + tid + kThreads * s;
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-          P[s][c] = (row < n && c < pw) ? A[(int64_t)row * ld + k0 + c] : 0.0;
-      }
-#pragma unroll 1
-      for (int c = 0; c < pw; ++c) {
-        const int kk = k0 + c;
-        double colv[ROWS];
-#pragma unroll
-        for (int s = 0; s < ROWS; ++s) {
-          double v = 0.0;
-#pragma unroll
-          for (int cc = 0; cc < NB; ++cc) v = (cc == c) ? P[s][cc] : v;
-          colv[s] = v;
-        }
-        double bv = -1.0;
-        int bi = 0x7fffffff;
-#pragma unroll
-        for (int s = 0; s < ROWS; ++s) {
-          const int row = k0 + tid + kThreads * s;
-          const double v = fabs(colv[s]);
-          if (row >= kk && row < n && v > bv) { bv = v; bi = row; }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-          const double ov = __shfl_xor(bv, off, kWave);
-          const int oi = __shfl_xor(bi, off, kWave);
-          if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-        }
-        if (lane == 0) { s_redv[w] = bv; s_redi[w] = bi; }
-        __syncthreads();
-        bv = s_redv[0];
-        bi = s_redi[0];
-        for (int t = 1; t < kThreads / 64; ++t) {
-          const double ov = s_redv[t];
-          const int oi = s_redi[t];
-          if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-        }
-        const int p = (bv > 0.0) ? bi : kk;
-        if (!(bv > 0.0)) singular = 1;
-        const int tp = (p - k0) & (kThreads - 1), sp = (p - k0) / kThreads;
-        if (tid == tp) {
-#pragma unroll
-          for (int s = 0; s < ROWS; ++s)
-            if (s == sp)
-#pragma unroll
-              for (int cc = 0; cc < NB; ++cc) s_prow[cc] = P[s][cc];
-        }
-        if (tid == c) {
-#pragma unroll
-          for (int cc = 0; cc < NB; ++cc) s_krow[cc] = P[0][cc];
-        }
-        __syncthreads();
-        if (tid == c) {
-#pragma unroll
-          for (int cc = 0; cc < NB; ++cc) P[0][cc] = s_prow[cc];
-        }
-        if (tid == tp && p != kk) {
-#pragma unroll
-          for (int s = 0; s < ROWS; ++s)
-            if (s == sp)
-#pragma unroll
-              for (int cc = 0; cc < NB; ++cc) P[s][cc] = s_krow[cc];
-        }
-        const double pv = s_prow[c];
-        if (pv != 0.0) {
-          const double inv = 1.0 / pv;
-#pragma unroll
-          for (int s = 0; s < ROWS; ++s) {
-            const int row = k0 + tid + kThreads * s;
-            if (row > kk && row < n) {
-              double lv = 0.0;
-#pragma unroll
-              for (int cc = 0; cc < NB; ++cc) lv = (cc == c) ? P[s][cc] : lv;
-              lv *= inv;
-#pragma unroll
-              for (int cc = 0; cc < NB; ++cc) {
-                const double upd = P[s][cc] - lv * s_prow[cc];
-                P[s][cc] = (cc == c) ? lv : ((cc > c) ? upd : P[s][cc]);
-              }
-            }
-          }
-        }
-        if (tid == 0) {
-          s_piv[kk - K0] = p;
-          piv[kk] = p;
-        }
-        __syncthreads();
-      }
-#pragma unroll
-      for (int s = 0; s < ROWS; ++s) {
-        const int row = k0 + tid + kThreads * s;
-        if (row < n)
-#pragma unroll
-          for (int c = 0; c < NB; ++c)
-            if (c < pw) A[(int64_t)row * ld + k0 + c] = P[s][c];
-      }
-      // ---- the sub-panel's interchanges on the rest of the outer panel
+  // groups of kTB columns, each factorised by sub-panels of NB columns; the
+  // group's update of the rest of the panel uses K = kTB
+  for (int b = 0, g0 = K0; g0 < K0 + kb; ++b, g0 += kTB) {
+    const int gw = min(kTB, K0 + kb - g0);
+    for (int k0 = g0; k0 < g0 + gw; k0 += NB) {
+      const int pw = min(NB, g0 + gw - k0);
+      factor_subpanel<ROWS, NB>(A, ld, n, k0, pw, K0, s_piv, piv, s_pl, singular);
+      if (tid == 0) compose_perm(s_piv + (k0 - K0), k0, pw, s_perm.rows, s_perm.src, &s_perm.count);
       __syncthreads();
-      permute_rows(A, ld, s_piv + (k0 - K0), k0, pw, K0, K0 + kb, k0, k0 + pw, s_perm, &g.Lt[0][0]);
-      if (k0 + pw < K0 + kb) {
-        trsm_rows<NB>(A, ld, k0, pw, k0 + pw, K0 + kb, s_L);
-        gemm_sub(A, ld, k0 + pw, n, k0 + pw, K0 + kb, k0, k0 + pw, g);
+      // the sub-panel's interchanges on the rest of the panel
+      apply_perm(A, ld, s_perm, K0, K0 + kb, k0, k0 + pw, &u.g.Lt[0][0]);
+      if (k0 + pw < g0 + gw) {
+        tri_inverse<TB, true>(A, ld, k0, pw, u.t);
+        tri_apply<TB>(A, ld, k0, pw, k0 + pw, g0 + gw, u.t);
+        gemm_sub(A, ld, k0 + pw, n, k0 + pw, g0 + gw, k0, k0 + pw, u.g);
       }
     }
-    // ---- the outer panel's interchanges on every other column
-    permute_rows(A, ld, s_piv, K0, kb, 0, ld, K0, K0 + kb, s_perm, &g.Lt[0][0]);
-    // ---- block row of U (blocked triangular solve), then the trailing update
-    if (K0 + kb < ld) {
-      for (int a = K0; a < K0 + kb; a += NB) {
-        const int wa = min(NB, K0 + kb - a);
-        trsm_rows<NB>(A, ld, a, wa, K0 + kb, ld, s_L);
-        if (a + wa < K0 + kb) gemm_sub(A, ld, a + wa, K0 + kb, K0 + kb, ld, a, a + wa, g);
-      }
-      if (K0 + kb < n) gemm_sub(A, ld, K0 + kb, n, K0 + kb, ld, K0, K0 + kb, g);
+    // the group's diagonal block is final: keep the inverse of its upper
+    // triangle for the back substitution and that of its unit-lower triangle
+    // for the U12 tiles
+    tri_inverse<kTB, false>(A, ld, g0, gw, u.t);
+    for (int idx = tid; idx < kTB * kTB; idx += kThreads) uinv[(g0 / kTB) * kTB * kTB + idx] = u.t.inv[idx >> 5][idx & 31];
+    __syncthreads();
+    tri_inverse<kTB, true>(A, ld, g0, gw, u.t);
+    for (int idx = tid; idx < kTB * kTB; idx += kThreads) W->inv[b][idx >> 5][idx & 31] = u.t.inv[idx >> 5][idx & 31];
+    if (g0 + gw < K0 + kb) {
+      tri_apply<kTB>(A, ld, g0, gw, g0 + gw, K0 + kb, u.t);
+      gemm_sub(A, ld, g0 + gw, n, g0 + gw, K0 + kb, g0, g0 + gw, u.g);
     }
+    __syncthreads();
   }
+  if (tid == 0) compose_perm(s_piv, K0, kb, W->rows, W->src, &W->count);
+  if (tid == 0 && (K0 == 0 || singular)) status[m] = singular;
+}
 
-  // ---- back substitution U W = R' on columns [n, n + nrhs): 128-row blocks
-  //      from the bottom, each solved by 32-row triangles and MFMA updates
-  for (int k1 = n; k1 > 0; k1 -= kOuter) {
-    const int k0 = max(0, k1 - kOuter);
-    for (int b1 = k1; b1 > k0; b1 -= NB) {
-      const int a0 = max(k0, b1 - NB);
-      trsm_upper_rows<NB>(A, ld, a0, b1 - a0, n, n + nrhs, s_L);
-      if (a0 > k0) gemm_sub(A, ld, k0, a0, n, n + nrhs, a0, b1, g);
-    }
-    if (k0 > 0) gemm_sub(A, ld, 0, k0, n, n + nrhs, k0, k1, g);
+// Grid (left + right tiles, count).  Left tiles (columns < K0) only take the
+// interchanges; right tiles (columns >= K0 + kb, right-hand sides included)
+// then become rows [K0, K0 + kb) of U.
+__global__ __launch_bounds__(kThreads) void lu_urow_kernel(double* __restrict__ A0, int n, int ld,
+                                                           int64_t stride, const LuWork* __restrict__ work,
+                                                           int K0) {
+  __shared__ union {
+    GemmLds g;
+    TriLds t;
+  } u;
+  __shared__ PermLds s_perm;
+  const int m = blockIdx.y;
+  double* A = A0 + (int64_t)m * stride;
+  const LuWork* W = work + m;
+  const int tid = threadIdx.x;
+  const int kb = min(kOuter, n - K0);
+  const int nleft = K0 / kGT;
+  const bool right = (int)blockIdx.x >= nleft;
+  const int c0 = right ? K0 + kb + ((int)blockIdx.x - nleft) * kGT : (int)blockIdx.x * kGT;
+  const int c1 = min(right ? ld : K0, c0 + kGT);
+  if (tid == 0) s_perm.count = W->count;
+  for (int e = tid; e < 2 * kOuter; e += kThreads) {
+    s_perm.rows[e] = W->rows[e];
+    s_perm.src[e] = W->src[e];
   }
-  if (tid == 0) status[blockIdx.x] = singular;
+  __syncthreads();
+  apply_perm(A, ld, s_perm, c0, c1, 0, 0, &u.g.Lt[0][0]);
+  if (!right) return;
+  for (int b = 0; b * kTB < kb; ++b) {
+    const int a = K0 + b * kTB, w = min(kTB, kb - b * kTB);
+    for (int idx = tid; idx < kTB * kTB; idx += kThreads) u.t.inv[idx >> 5][idx & 31] = W->inv[b][idx >> 5][idx & 31];
+    __syncthreads();
+    tri_apply<kTB>(A, ld, a, w, c0, c1, u.t);
+    if (a + w < K0 + kb) gemm_sub(A, ld, a + w, K0 + kb, c0, c1, a, a + w, u.g);
+  }
+}
+
+// Grid (row tiles x column tiles of the trailing matrix, count).
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void lu_update_kernel(double* __restrict__ A0, int n, int ld,
+                                                             int64_t stride, int K0, int ctiles) {
+  __shared__ GemmLds g;
+  const int m = blockIdx.y;
+  double* A = A0 + (int64_t)m * stride;
+  const int kb = min(kOuter, n - K0);
+  const int r0 = K0 + kb;
+  const int i = (int)blockIdx.x / ctiles, j = (int)blockIdx.x - i * ctiles;
+  const int ra = r0 + i * kGT, ca = r0 + j * kGT;
+  gemm_sub(A, ld, ra, min(n, ra + kGT), ca, min(ld, ca + kGT), K0, K0 + kb, g);
+}
+
+// Back substitution U W = R' on columns [n, n + nrhs), right-looking from the
+// bottom in blocks of kOuter rows aligned with the factorisation, two
+// launches per block: lu_bdiag_kernel (one workgroup per matrix) solves the
+// diagonal block by its 32-row triangles (stored inverses on MFMA) and MFMA
+// updates inside the block; lu_bupd_kernel (one workgroup per matrix and
+// 128-row tile above the block) removes the block's contribution from the
+// rows above.
+__global__ __launch_bounds__(kThreads) void lu_bdiag_kernel(double* __restrict__ A0, int n, int ld,
+                                                            int nrhs, int64_t stride,
+                                                            const double* __restrict__ uinv0, int k0) {
+  __shared__ union {
+    GemmLds g;
+    TriLds t;
+  } u;
+  double* A = A0 + (int64_t)blockIdx.x * stride;
+  const double* uinv = uinv0 + (int64_t)blockIdx.x * ((n + kTB - 1) / kTB) * kTB * kTB;
+  const int tid = threadIdx.x;
+  const int k1 = min(n, k0 + kOuter);
+  for (int a0 = k0 + (k1 - 1 - k0) / kTB * kTB; a0 >= k0; a0 -= kTB) {
+    const int b1 = min(k1, a0 + kTB);
+    for (int idx = tid; idx < kTB * kTB; idx += kThreads)
+      u.t.inv[idx >> 5][idx & 31] = uinv[(a0 / kTB) * kTB * kTB + idx];
+    __syncthreads();
+    tri_apply<kTB>(A, ld, a0, b1 - a0, n, n + nrhs, u.t);
+    if (a0 > k0) gemm_sub(A, ld, k0, a0, n, n + nrhs, a0, b1, u.g);
+  }
+}
+
+// Grid (k0 / kGT row tiles, count).
+__global__ __launch_bounds__(kThreads) void lu_bupd_kernel(
+    double* __restrict__ A0, int n, int ld, int nrhs, int64_t stride, int k0) {
+  __shared__ GemmLds g;
+  double* A = A0 + (int64_t)blockIdx.y * stride;
+  const int k1 = min(n, k0 + kOuter);
+  const int r0 = (int)blockIdx.x * kGT;
+  gemm_sub(A, ld, r0, min(k0, r0 + kGT), n, n + nrhs, k0, k1, g);
+}
+
+template <int ROWS, int NB>
+int launch_steps(const BucketTables& T, int32_t count, double* A, int64_t stride, int32_t* piv,
+                  int32_t* status, LuWork* work, double* uinv, hipStream_t st) {
+  const int n = T.n, ld = T.ld;
+  int launches = 0;
+  for (int K0 = 0; K0 < n; K0 += kOuter) {
+    const int kb = std::min(kOuter, n - K0);
+    hipLaunchKernelGGL((lu_panel_kernel<ROWS, NB>), dim3(count), dim3(kThreads), 0, st, A, n, ld, stride,
+                       piv, status, work, uinv, K0);
+    ++launches;
+    const int tiles = K0 / kGT + (ld - K0 - kb + kGT - 1) / kGT;
+    if (tiles > 0)
+    {
+      hipLaunchKernelGGL(lu_urow_kernel, dim3(tiles, count), dim3(kThreads), 0, st, A, n, ld, stride,
+                         work, K0);
+      ++launches;
+    }
+    const int rt = (n - K0 - kb + kGT - 1) / kGT, ct = (ld - K0 - kb + kGT - 1) / kGT;
+    if (rt > 0 && ct > 0)
+    {
+      hipLaunchKernelGGL(lu_update_kernel, dim3(rt * ct, count), dim3(kThreads), 0, st, A, n, ld, stride,
+                         K0, ct);
+      ++launches;
+    }
+  }
+  for (int k0 = (n - 1) / kOuter * kOuter; k0 >= 0; k0 -= kOuter) {
+    hipLaunchKernelGGL(lu_bdiag_kernel, dim3(count), dim3(kThreads), 0, st, A, n, ld, T.nrhs, stride, uinv, k0);
+    ++launches;
+    if (k0 > 0) {
+      hipLaunchKernelGGL(lu_bupd_kernel, dim3(k0 / kGT, count), dim3(kThreads), 0, st, A, n, ld, T.nrhs, stride,
+                         k0);
+      ++launches;
+    }
+  }
+  return launches;
 }
 
 }  // namespace
 
-void launch_lu_solve(const BucketTables& T, int32_t count, double* A, int64_t mat_stride,
-                     int32_t* piv, int32_t* status, hipStream_t st) {
+// Work area: count LuWork records, then the inverses of the upper triangles
+// of the 32 x 32 diagonal blocks of U ([count][ceil(n / 32)][32][32]).
+size_t lu_workspace_bytes(int32_t count, int32_t n) {
+  const size_t nblk = (size_t)(n + kTB - 1) / kTB;
+  return (size_t)count * (sizeof(LuWork) + nblk * kTB * kTB * sizeof(double));
+}
+
+int launch_lu_solve(const BucketTables& T, int32_t count, double* A, int64_t mat_stride,
+                    int32_t* piv, int32_t* status, void* work, hipStream_t st) {
+  LuWork* w = static_cast<LuWork*>(work);
+  double* uinv = reinterpret_cast<double*>(w + count);
   const int n = T.n;
   if (n <= 512)
-    hipLaunchKernelGGL((lu_solve_kernel<1, 32>), dim3(count), dim3(kThreads), 0, st, A, n, T.ld,
-                       T.nrhs, mat_stride, piv, status);
+    return launch_steps<1, 16>(T, count, A, mat_stride, piv, status, w, uinv, st);
   else if (n <= 1024)
-    hipLaunchKernelGGL((lu_solve_kernel<2, 32>), dim3(count), dim3(kThreads), 0, st, A, n, T.ld,
-                       T.nrhs, mat_stride, piv, status);
+    return launch_steps<2, 16>(T, count, A, mat_stride, piv, status, w, uinv, st);
   else if (n <= 2048)
-    hipLaunchKernelGGL((lu_solve_kernel<4, 16>), dim3(count), dim3(kThreads), 0, st, A, n, T.ld,
-                       T.nrhs, mat_stride, piv, status);
+    return launch_steps<4, 16>(T, count, A, mat_stride, piv, status, w, uinv, st);
   else
-    hipLaunchKernelGGL((lu_solve_kernel<8, 8>), dim3(count), dim3(kThreads), 0, st, A, n, T.ld,
-                       T.nrhs, mat_stride, piv, status);
+    return launch_steps<8, 8>(T, count, A, mat_stride, piv, status, w, uinv, st);
 }
 
 }  // namespace pdd

@@ -252,55 +252,70 @@ __global__ __launch_bounds__(256) void paths_kernel(const DevProblem* __restrict
   }
 }
 
+// Packed lower-triangle index (j <= i).
+__device__ __forceinline__ int tri(int i, int j) { return (i * (i + 1) >> 1) + j; }
+
 // Cholesky factor of the IMQ Gram matrix K_lk = phi_k(theta_l) (eq. 20) of
-// each perimeter circle, lower triangle stored row-major in `Lf`.
+// each perimeter circle, factorised in LDS and stored as a packed lower
+// triangle in `Lf` (stride n_max (n_max + 1) / 2).
 __global__ __launch_bounds__(256) void gram_cholesky_kernel(McArgs a, double* __restrict__ Lf,
                                                             int32_t* __restrict__ status) {
+  extern __shared__ double sL[];                       // packed lower triangle
   const int pc = blockIdx.x;
   const int m = a.perim_ids[pc];
   const int64_t alo = a.knot_off[m];
   const int n = (int)(a.knot_off[m + 1] - alo);
   const double c2 = a.rbf_c2[m];
-  double* L = Lf + (int64_t)pc * a.gram_stride;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < n * n; idx += blockDim.x) {
-    const int i = idx / n, j = idx - i * n;
-    const double d = a.ktheta[alo + i] - a.ktheta[alo + j];
-    L[idx] = 1.0 / sqrt(d * d + c2);
-  }
+  const int np = n * (n + 1) / 2;
+  for (int i = 0; i < n; ++i)
+    for (int j = tid; j <= i; j += blockDim.x) {
+      const double d = a.ktheta[alo + i] - a.ktheta[alo + j];
+      sL[tri(i, j)] = 1.0 / sqrt(d * d + c2);
+    }
   __shared__ int s_bad;
-  __shared__ double s_piv;
   if (tid == 0) s_bad = 0;
   __syncthreads();
   for (int k = 0; k < n; ++k) {
+    const double d = sL[tri(k, k)];
+    const double piv = sqrt(fmax(d, 1e-300));
+    __syncthreads();                                   // every thread has read the diagonal
     if (tid == 0) {
-      const double d = L[k * n + k];
       if (!(d > 0.0)) s_bad = 1;
-      s_piv = sqrt(fmax(d, 1e-300));
-      L[k * n + k] = s_piv;
+      sL[tri(k, k)] = piv;
     }
+    const double inv = 1.0 / piv;
+    for (int i = k + 1 + tid; i < n; i += blockDim.x) sL[tri(i, k)] *= inv;
     __syncthreads();
-    for (int i = k + 1 + tid; i < n; i += blockDim.x) L[i * n + k] /= s_piv;
-    __syncthreads();
+    // trailing update of the lower triangle, rows and columns > k
     const int rem = n - k - 1;
-    for (int idx = tid; idx < rem * rem; idx += blockDim.x) {
-      const int i = k + 1 + idx / rem, j = k + 1 + idx % rem;
-      if (j <= i) L[i * n + j] -= L[i * n + k] * L[j * n + k];
+    const int cnt = rem * (rem + 1) / 2;
+    for (int idx = tid; idx < cnt; idx += blockDim.x) {
+      // idx -> (ii, jj) with jj <= ii < rem
+      int ii = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+      while ((ii + 1) * (ii + 2) / 2 <= idx) ++ii;
+      while (ii * (ii + 1) / 2 > idx) --ii;
+      const int jj = idx - ii * (ii + 1) / 2;
+      const int i = k + 1 + ii, j = k + 1 + jj;
+      sL[tri(i, j)] -= sL[tri(i, k)] * sL[tri(j, k)];
     }
     __syncthreads();
   }
+  double* L = Lf + (int64_t)pc * a.gram_stride;
+  for (int idx = tid; idx < np; idx += blockDim.x) L[idx] = sL[idx];
   if (tid == 0) status[pc] = s_bad;
 }
 
 // Per Monte Carlo knot: K^-1 applied to the total and to each batch's phi sums
-// (lane b solves right-hand side b), rows of C = -K^-1 S / Ntilde, batch
-// standard errors, r and its standard error, scattered into the CSR arrays.
+// (lane b solves right-hand side b against the packed Cholesky factor staged
+// in LDS), rows of C = -K^-1 S / Ntilde, batch standard errors, r and its
+// standard error, scattered into the CSR arrays.
 __global__ __launch_bounds__(64) void mc_finalize_kernel(McArgs a, const double* __restrict__ Lf,
                                                          double* __restrict__ val,
                                                          double* __restrict__ se,
                                                          double* __restrict__ bvec,
                                                          double* __restrict__ se_b) {
-  extern __shared__ double sx[];                      // [B + 1][n_arc]
+  extern __shared__ double smem[];                    // packed L, then [B + 1][n] solutions
   const int slot = blockIdx.x;
   const int lane = threadIdx.x;
   const int knot = a.mc_knots[slot];
@@ -309,33 +324,40 @@ __global__ __launch_bounds__(64) void mc_finalize_kernel(McArgs a, const double*
   const int64_t alo = a.knot_off[m];
   const int n = (int)(a.knot_off[m + 1] - alo);
   const int B = a.n_batches;
+  const int np = n * (n + 1) / 2;
+  double* sL = smem;
+  double* sx = smem + np;
   const double* L = Lf + (int64_t)pc * a.gram_stride;
+  for (int idx = lane; idx < np; idx += 64) sL[idx] = L[idx];
   const int64_t Ptot = a.paths;
   const int64_t u0 = (int64_t)slot * B;
   // right-hand sides: lane b < B -> batch mean, lane B -> overall mean
+  for (int idx = lane; idx < (B + 1) * n; idx += 64) {
+    const int b = idx / n, j = idx - b * n;
+    double v;
+    if (b < B) {
+      const int64_t cnt = ((b + 1) * Ptot + B - 1) / B - (b * Ptot + B - 1) / B;
+      v = a.out_phi[(u0 + b) * a.out_stride + j] / (double)cnt;
+    } else {
+      v = 0.0;
+      for (int bb = 0; bb < B; ++bb) v += a.out_phi[(u0 + bb) * a.out_stride + j];
+      v /= (double)Ptot;
+    }
+    sx[idx] = v;
+  }
+  __syncthreads();
   if (lane <= B) {
     double* x = sx + (int64_t)lane * n;
-    for (int j = 0; j < n; ++j) {
-      double v;
-      if (lane < B) {
-        const int64_t cnt = ((lane + 1) * Ptot + B - 1) / B - (lane * Ptot + B - 1) / B;
-        v = a.out_phi[(u0 + lane) * a.out_stride + j] / (double)cnt;
-      } else {
-        v = 0.0;
-        for (int b = 0; b < B; ++b) v += a.out_phi[(u0 + b) * a.out_stride + j];
-        v /= (double)Ptot;
-      }
-      x[j] = v;
-    }
     for (int i = 0; i < n; ++i) {             // L z = y
+      const double* Li = sL + tri(i, 0);
       double v = x[i];
-      for (int j = 0; j < i; ++j) v -= L[i * n + j] * x[j];
-      x[i] = v / L[i * n + i];
+      for (int j = 0; j < i; ++j) v -= Li[j] * x[j];
+      x[i] = v / Li[i];
     }
     for (int i = n - 1; i >= 0; --i) {        // L^T x = z
       double v = x[i];
-      for (int j = i + 1; j < n; ++j) v -= L[j * n + i] * x[j];
-      x[i] = v / L[i * n + i];
+      for (int j = i + 1; j < n; ++j) v -= sL[tri(j, i)] * x[j];
+      x[i] = v / sL[tri(i, i)];
     }
   }
   __syncthreads();
@@ -402,13 +424,18 @@ void launch_mc_paths(const DevProblem* P, bool const_coef, const McArgs& a, hipS
 void launch_gram_cholesky(const McArgs& a, int32_t n_perim, double* Lf, int32_t* status,
                           hipStream_t st) {
   if (n_perim == 0) return;
-  hipLaunchKernelGGL(gram_cholesky_kernel, dim3(n_perim), dim3(256), 0, st, a, Lf, status);
+  const size_t shm = sizeof(double) * (size_t)a.gram_stride;
+  hipFuncSetAttribute((const void*)gram_cholesky_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)shm);
+  hipLaunchKernelGGL(gram_cholesky_kernel, dim3(n_perim), dim3(256), shm, st, a, Lf, status);
 }
 
 void launch_mc_finalize(const McArgs& a, int32_t n_mc, int32_t max_arc, const double* Lf,
                         double* val, double* se, double* b, double* se_b, hipStream_t st) {
   if (n_mc == 0) return;
-  const size_t shm = sizeof(double) * (size_t)(a.n_batches + 1) * max_arc;
+  const size_t shm = sizeof(double) * ((size_t)a.gram_stride + (size_t)(a.n_batches + 1) * max_arc);
+  hipFuncSetAttribute((const void*)mc_finalize_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)shm);
   hipLaunchKernelGGL(mc_finalize_kernel, dim3(n_mc), dim3(64), shm, st, a, Lf, val, se, b, se_b);
 }
 

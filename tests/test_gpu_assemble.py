@@ -125,6 +125,30 @@ def test_per_circle_plan_is_bitwise_equal_to_batched():
     assert np.array_equal(v1, v2) and np.array_equal(b1, b2)
 
 
+def test_mixed_resolution_buckets_match_oracle():
+    """Uneven resolutions in one assembly (collocation sizes 576 to 4096, one
+    size bucket each): every floating row against the oracle, and the batched
+    plan bitwise equal to the plain per-circle loop."""
+    pdd = _gpu()
+    cfg = workloads.mixed_small()
+    prob = cfg["problem"]
+    _say("[gpu] assemble mixed_small (n = 576 .. 4096)")
+    cv, sysm, val, b, se, se_b = _gpu_system(pdd, cfg)
+    assert sysm.stats.breakdowns == 0 and sysm.stats.capped_paths == 0
+    ref_cover = geometry.build_cover(prob["domain"], cfg["cover"])
+    fl = np.nonzero(ref_cover.floating)[0]
+    assert sorted(int(ref_cover.Nr[m] * ref_cover.Ntheta[m]) for m in fl) == [576, 1024, 2304, 4096]
+    ref = assemble.assemble(prob, ref_cover, cfg["mc"])
+    spec = np.nonzero(ref_cover.row_class == ROW_SPECTRAL)[0]
+    mcr = np.nonzero(ref_cover.row_class == ROW_MC)[0]
+    worst = _check_spectral_rows(ref_cover, ref.val, ref.b, val, b, spec, prob)
+    _check_rhs(ref_cover, ref.b, b, spec, _fscale(prob, ref_cover, fl))
+    _check_mc_rows(ref_cover, ref.val, ref.se, ref.b, ref.se_b, val, b, mcr)
+    _, _, v2, b2, _, _ = _gpu_system(pdd, cfg, plan="per_circle")
+    assert np.array_equal(val, v2) and np.array_equal(b, b2)
+    _say(f"[gpu] mixed_small: worst spectral row diff {worst:.2e}")
+
+
 def test_config2_full_size_sampled():
     """Config 2 at its full size (900 floating circles, n = 1024, 10^4 paths)
     in the launch configuration the benchmark times; the oracle recomputes a

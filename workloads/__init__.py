@@ -254,6 +254,19 @@ def small_variable(paths=200, h=1e-3, seed=7, n_side=4, radius=0.2, M=16, Ntheta
             "mc": mc_opts(paths, h, seed=seed)}
 
 
+def mixed_small(paths=64, h=1e-3, seed=8):
+    """Config-3-style uneven resolutions on the small variable-coefficient case:
+    the four floating circles of the 4x4 cover get Ntheta = 48, 64, 96, 128
+    (collocation sizes 576, 1024, 2304, 4096), the twelve perimeter circles
+    Ntheta = 32; M = Ntheta and Nr = Ntheta / 4 throughout."""
+    cfg = small_variable(paths=paths, h=h, seed=seed)
+    nth = np.full(16, 32, dtype=np.int32)
+    nth[[5, 6, 9, 10]] = [48, 64, 96, 128]
+    cfg["cover"] = _cover(cfg["cover"]["centres"], cfg["cover"]["radii"], nth, nth, nth // 4)
+    cfg["name"] = "mixed_small"
+    return cfg
+
+
 CONFIGS = {
     "config1": config1, "config2": config2, "config3": config3,
     "config4": config4, "config5": config5,
