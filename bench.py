@@ -6,9 +6,11 @@ Monte Carlo perimeter rows, boundary rows), solve C u = r, solve
 C^T lambda = dL/du and the adjoint with respect to the node samples, for the
 loss sum_i (u_i - u_target_i)^2.
 
-Workload: the variable-coefficient configuration (32 x 32 circles of radius
-0.045 on the unit square, M = Ntheta = 64, Nr = 16, 10^4 paths per perimeter
-knot, h = 1e-4), synthetic seeded inputs.
+Default workload: the variable-coefficient configuration (32 x 32 circles of
+radius 0.045 on the unit square, M = Ntheta = 64, Nr = 16, 10^4 paths per
+perimeter knot, h = 1e-4), synthetic seeded inputs.  --workload selects the
+uneven-resolution (assembly only; --per-circle adds the plain per-circle loop
+on a reduced cover), differentiation and scale workloads.
 
 Prints one JSON line (rank 0).  Only one GPU is supported.
 """
@@ -36,7 +38,7 @@ def lu_flops(n, nrhs):
     return 2.0 / 3.0 * n ** 3 + 2.0 * n * n * nrhs
 
 
-def run_gpu(cfg, steps, warmup, with_adjoint=True):
+def run_gpu(cfg, steps, warmup, with_adjoint=True, budget=0, plan="batched"):
     import numpy as np
     import torch
 
@@ -53,11 +55,13 @@ def run_gpu(cfg, steps, warmup, with_adjoint=True):
     xy, rc, asg, own = cover.knots()
     # loss target: the manufactured solution at the knots plus N(0, 1e-3) noise
     xy_d = torch.tensor(xy, dtype=torch.float64, device=dev)
-    noise = workloads.target_noise({"noise_seed": 20, "noise_std": 1e-3}, cover.N)
+    noise = workloads.target_noise({"noise_seed": cfg.get("noise_seed", 20),
+                                    "noise_std": cfg.get("noise_std", 1e-3)}, cover.N)
     target = pdd.eval_field(prob, "u", xy_d) + torch.tensor(noise, dtype=torch.float64, device=dev)
 
     def step():
-        sysm = pdd.System(cover, prob, cfg["mc"], keep_factors=with_adjoint)
+        sysm = pdd.System(cover, prob, cfg["mc"], keep_factors=with_adjoint, hbm_budget_bytes=budget,
+                          plan=plan)
         res = {"stats": sysm.stats}
         if with_adjoint:
             u, si = sysm.solve()
@@ -126,13 +130,61 @@ def cpu_baseline(cfg, budget_s=20.0):
     }
 
 
+WORKLOADS = {
+    "config2": dict(adjoint=True, budget=0,
+                    label="variable-coefficient operator on the unit square, 32x32 circles r=0.045, "
+                          "M=Ntheta=64, Nr=16 (n=1024), 1e4 paths/perimeter knot, h=1e-4"),
+    "config3": dict(adjoint=False, budget=0,
+                    label="Laplace on the unit disk minus a hole, ~2e4 circles of uneven radius, "
+                          "Ntheta in {32,48,64,96,128}, Nr=Ntheta/4 (n=256..4096), 1e3 paths/knot"),
+    "config4": dict(adjoint=True, budget=0,
+                    label="Laplace base point on a 64x64 cover, M=Ntheta=64, Nr=16 (n=1024), "
+                          "1e3 paths/knot, h=8.1e-6; loss sum (u - u_target)^2"),
+    "config5": dict(adjoint=True, budget=8 << 30,
+                    label="Laplace on a 128x128 cover, M=64, Ntheta=48, Nr=12 (n=576), 1e5 paths/knot, "
+                          "h=1e-5; LU factors recomputed in chunks under an 8 GiB budget"),
+}
+
+
+def spectral_flops(cover, cfg):
+    """Algorithmic LU flops of all floating circles of the cover."""
+    import numpy as np
+    _, off, ids = cover.nodes()
+    n = np.diff(off).astype(np.float64)
+    M = np.asarray(cfg["cover"]["M"], dtype=np.float64)[ids]
+    return float(np.sum(2.0 / 3.0 * n ** 3 + 2.0 * n * n * (M + 1)))
+
+
+def per_circle_comparison(steps):
+    """The plain per-circle loop (same kernels, one launch sequence per circle)
+    against the batched plan, on a reduced uneven-resolution cover (lattice
+    spacing 0.055 instead of 0.0123: about 1e3 circles with the same
+    resolution draw), assembly only."""
+    import workloads
+    cfg = workloads.config3(spacing=0.055)
+    out = {}
+    for plan in ("batched", "per_circle"):
+        cover, results, dt, _ = run_gpu(cfg, steps, 1, with_adjoint=False, plan=plan)
+        st = [r["stats"] for r in results]
+        out[plan] = {"ms_assembly": sum(s.ms_total for s in st) / len(st),
+                     "ms_lu": sum(s.ms_lu for s in st) / len(st),
+                     "launches": int(st[-1].n_launch_spectral)}
+    out["circles"] = int(cover.info.n_circles)
+    out["floating"] = int(cover.info.n_float)
+    out["speedup"] = out["per_circle"]["ms_assembly"] / out["batched"]["ms_assembly"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="config2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--per-circle", action="store_true",
+                    help="also time the plain per-circle loop on a reduced uneven cover")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -141,9 +193,11 @@ def main():
         sys.exit(2)
 
     import workloads
-    cfg = workloads.config2()
-    with_adj = not args.no_adjoint
-    cover, results, dt, t_cover = run_gpu(cfg, args.steps, args.warmup, with_adjoint=with_adj)
+    wl = WORKLOADS[args.workload]
+    cfg = workloads.CONFIGS[args.workload]()
+    with_adj = wl["adjoint"] and not args.no_adjoint
+    cover, results, dt, t_cover = run_gpu(cfg, args.steps, args.warmup, with_adjoint=with_adj,
+                                          budget=wl["budget"])
     info = cover.info
     st = [r["stats"] for r in results]
     n_circles = int(info.n_circles)
@@ -153,10 +207,14 @@ def main():
     ms_mc = sum(s.ms_mc for s in st) / len(st)
     ms_asm = sum(s.ms_total for s in st) / len(st)
     path_steps = st[-1].path_steps
-    n = 16 * 64
-    nrhs = 65
-    flops = lu_flops(n, nrhs) * n_float
+    flops = spectral_flops(cover, cfg)
     achieved = flops / (ms_lu * 1e-3) / 1e12
+    if args.workload == "config2":
+        kernel = ("batched LU + triangular solves of 900 circles (n=1024, 65 right-hand sides): "
+                  "lu_panel/lu_urow/lu_update/lu_bdiag/lu_bupd kernels, 38 launches")
+    else:
+        kernel = (f"batched LU + triangular solves of {n_float} circles: "
+                  "lu_panel/lu_urow/lu_update/lu_bdiag/lu_bupd kernels")
     out = {
         "metric": "G assembly circles/s + MC path-steps/s at fixed error; fwd+adjoint seconds",
         "value": n_circles / dt,
@@ -171,8 +229,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "variable-coefficient operator on the unit square, 32x32 circles r=0.045, "
-                        "M=Ntheta=64, Nr=16 (n=1024), 1e4 paths/perimeter knot, h=1e-4",
+            "workload": wl["label"],
             "circles": n_circles, "floating": n_float, "N": int(info.N), "nnz": int(info.nnz),
             "step": "assemble + solve + transpose solve + adjoint" if with_adj else "assemble",
         },
@@ -185,10 +242,11 @@ def main():
         "phase_ms": {k: sum(getattr(s, "ms_" + k) for s in st) / len(st)
                      for k in ("sample", "build", "lu", "solve", "eval", "mc", "total")},
         "build_cover_s": t_cover,
+        "factor_bytes_kept": int(st[-1].factor_bytes),
+        "factors_recomputed_in_backward": bool(st[-1].recompute),
         "roofline": {
             "bound": "mfma",
-            "kernel": "batched LU + triangular solves of 900 circles (n=1024, 65 right-hand sides): "
-                      "lu_panel/lu_urow/lu_update/lu_bdiag/lu_bupd kernels, 38 launches",
+            "kernel": kernel,
             "achieved": achieved, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_MFMA_TFLOPS, "traffic": None,
         },
@@ -196,6 +254,8 @@ def main():
     if with_adj:
         out["solve_iterations"] = results[-1]["iters"]
         out["solve_iterations_transpose"] = results[-1]["iters_t"]
+    if args.per_circle:
+        out["per_circle_vs_batched"] = per_circle_comparison(max(1, min(args.steps, 2)))
     if not args.no_cpu_baseline:
         cb = cpu_baseline(cfg, args.cpu_budget)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}

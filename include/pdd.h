@@ -203,7 +203,13 @@ enum { PDD_PLAN_BATCHED = 0, PDD_PLAN_PER_CIRCLE = 1 };
 typedef struct pdd_assemble_opts {
   int32_t plan;            /* PDD_PLAN_BATCHED or PDD_PLAN_PER_CIRCLE (one launch per circle) */
   int32_t keep_factors;    /* keep LU factors for pdd_assemble_G_backward              */
-  int64_t hbm_budget_bytes;/* cap on factor storage; 0 = 64 GiB                        */
+  int64_t hbm_budget_bytes;/* device bytes allowed for factor storage; 0 = 64 GiB.
+                              Assembly processes each size bucket in chunks of at most
+                              this many bytes of factors.  With keep_factors, the
+                              factors are kept when all of them fit; otherwise the
+                              system keeps a copy of the node samples and
+                              pdd_assemble_G_backward recomputes the factors chunk by
+                              chunk (stats.recompute = 1)                              */
 } pdd_assemble_opts;
 
 /*
@@ -237,6 +243,10 @@ typedef struct pdd_system_stats {
   int32_t breakdowns;      /* zero pivots / non-SPD Gram matrices                      */
   int32_t n_launch_spectral, n_launch_mc;
   float ms_sample, ms_build, ms_lu, ms_solve, ms_eval, ms_mc, ms_total;
+  int64_t factor_bytes;    /* LU factor bytes kept on the device for the backward pass */
+  int32_t recompute;       /* 1: keep_factors asked for more than hbm_budget_bytes, so
+                              the backward pass rebuilds the factors chunk by chunk   */
+  int32_t reserved;
 } pdd_system_stats;
 
 pdd_status pdd_system_get_stats(pdd_system sys, pdd_system_stats* out);
@@ -273,7 +283,8 @@ pdd_status pdd_solve_G(pdd_system sys, const double* rhs, double* u, int32_t tra
  * with w_B = H u_Xi and w_I the local interior solution.  Outputs are device
  * arrays [sum_n] in the node layout; NULL skips one.  Monte Carlo and boundary
  * rows do not depend on node samples (dL/dr = lambda).  Needs the system to
- * have been assembled with keep_factors.
+ * have been assembled with keep_factors (stored factors, or a chunked
+ * recomputation when they exceeded hbm_budget_bytes).
  */
 pdd_status pdd_assemble_G_backward(pdd_system sys, const double* u, const double* lambda,
                                    double* g_axx, double* g_axy, double* g_ayy,

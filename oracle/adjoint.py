@@ -35,8 +35,9 @@ def circle_weights(cover, m, grid):
     return knots, E, Eps
 
 
-def circle_gradient(cover, m, samples, u, lam):
-    """Gradients of the loss w.r.t. the seven node samples of floating circle m."""
+def circle_terms(cover, m, samples, u, lam):
+    """The adjoint quantities of floating circle m: mu = A_II^-T E^T lambda_Km,
+    the local solution [w_I; w_B] at u, and the coefficient operator rows."""
     grid = spectral.local_grid(cover.Nr[m], cover.Ntheta[m])
     r = float(cover.radii[m])
     A_II, A_IB = grid.collocation(r, samples)
@@ -49,7 +50,12 @@ def circle_gradient(cover, m, samples, u, lam):
     w_B = H @ u[cover.knot_off[m]:cover.knot_off[m + 1]]
     w_I = -sla.lu_solve(lu, A_IB @ w_B + samples["f"])
     w_full = np.concatenate([w_I, w_B])
-    ops = grid.coefficient_ops(r)
+    return mu, w_full, grid.coefficient_ops(r)
+
+
+def circle_gradient(cover, m, samples, u, lam):
+    """Gradients of the loss w.r.t. the seven node samples of floating circle m."""
+    mu, w_full, ops = circle_terms(cover, m, samples, u, lam)
     g = {name: -mu * (ops[name] @ w_full) for name in COEFS}
     g["f"] = -mu
     return g

@@ -84,7 +84,8 @@ class SystemStats(C.Structure):
                 ("breakdowns", C.c_int32), ("n_launch_spectral", C.c_int32),
                 ("n_launch_mc", C.c_int32)] + \
                [(n, C.c_float) for n in ("ms_sample", "ms_build", "ms_lu", "ms_solve", "ms_eval",
-                                         "ms_mc", "ms_total")]
+                                         "ms_mc", "ms_total")] + \
+               [("factor_bytes", C.c_int64), ("recompute", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SolveOpts(C.Structure):

@@ -12,6 +12,8 @@
 // the node's coefficient samples.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "runtime.h"
 
 namespace pdd {
@@ -238,10 +240,9 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(AdjArgs a) {
 pdd_status backward_impl(pdd_system sys, const double* u, const double* lambda, double* const g[7],
                          hipStream_t st) {
   const DeviceCover& D = sys->cover->D;
-  if (sys->factors.empty() && !sys->cover->H.float_ids.empty())
+  if (sys->factors.empty() && !sys->recompute && !sys->cover->H.float_ids.empty())
     return fail(PDD_EINVAL, "pdd_assemble_G_backward: assemble with keep_factors to differentiate");
-  for (const auto& fp : sys->factors) {
-    const BucketFactors& F = *fp;
+  auto run = [&](const BucketFactors& F) -> pdd_status {
     const BucketData& bk = *D.buckets[F.bucket];
     AdjArgs a{};
     a.T = bk.T;
@@ -258,6 +259,36 @@ pdd_status backward_impl(pdd_system sys, const double* u, const double* lambda, 
     if (shm > 160 * 1024) return fail(PDD_EINVAL, "pdd_assemble_G_backward: bucket too large");
     hipLaunchKernelGGL(adjoint_kernel, dim3(F.count), dim3(kAdjThreads), shm, st, a);
     PDD_HIP(hipGetLastError());
+    return PDD_OK;
+  };
+  if (!sys->recompute) {
+    for (const auto& fp : sys->factors) {
+      const pdd_status ps = run(*fp);
+      if (ps != PDD_OK) return ps;
+    }
+    return PDD_OK;
+  }
+  // The factors did not fit the budget at assembly: rebuild them chunk by
+  // chunk from the system's own copy of the node samples (the same kernels,
+  // so the same factors) and differentiate each chunk before the next.
+  const int64_t sum_n = sys->cover->H.sum_n;
+  NodeSamples S{};
+  for (int t = 0; t < 7; ++t) S.s[t] = sys->samples.ptr<double>() + (int64_t)t * sum_n;
+  LuScratch ws;
+  for (size_t bi = 0; bi < D.buckets.size(); ++bi) {
+    const BucketData& bk = *D.buckets[bi];
+    const int32_t chunk = (int32_t)std::min<int64_t>(
+        bk.count, std::max<int64_t>(1, sys->budget / factor_bytes_per_circle(bk)));
+    BucketFactors f;
+    f.bucket = (int32_t)bi;
+    alloc_factors(f, bk, chunk);
+    for (int32_t first = 0; first < bk.count; first += chunk) {
+      const int32_t cnt = std::min(chunk, bk.count - first);
+      factor_chunk(D, bk, S, sys->plan, f, first, cnt, ws, st, nullptr, nullptr, nullptr);
+      const pdd_status ps = run(f);
+      if (ps != PDD_OK) return ps;
+    }
+    PDD_HIP(hipStreamSynchronize(st));   // before the chunk buffers are freed
   }
   return PDD_OK;
 }

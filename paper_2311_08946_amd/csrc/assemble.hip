@@ -42,7 +42,7 @@ __global__ void reduce_i32_kernel(const int32_t* __restrict__ a, int64_t n, uint
   if (threadIdx.x == 0) out[0] += s[0];
 }
 
-struct PhaseTimer {
+struct PhaseTimer : PhaseHooks {
   hipStream_t st;
   struct Ev { int phase; hipEvent_t a, b; };
   std::vector<Ev> evs;
@@ -51,7 +51,7 @@ struct PhaseTimer {
     for (auto& e : evs) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
   }
   std::vector<hipStream_t> on;
-  int begin(int phase, hipStream_t s = nullptr) {
+  int begin(int phase, hipStream_t s = nullptr) override {
     Ev e{phase, nullptr, nullptr};
     PDD_HIP(hipEventCreate(&e.a));
     PDD_HIP(hipEventCreate(&e.b));
@@ -61,7 +61,7 @@ struct PhaseTimer {
     on.push_back(q);
     return (int)evs.size() - 1;
   }
-  void end(int idx) { PDD_HIP(hipEventRecord(evs[idx].b, on[idx])); }
+  void end(int idx) override { PDD_HIP(hipEventRecord(evs[idx].b, on[idx])); }
   float total(int phase) {
     float t = 0.0f;
     for (auto& e : evs)
@@ -72,8 +72,6 @@ struct PhaseTimer {
     return t;
   }
 };
-
-enum { PH_SAMPLE, PH_BUILD, PH_LU, PH_SOLVE, PH_EVAL, PH_MC, PH_TOTAL };
 
 __global__ void eval_field_kernel(const DevProblem* __restrict__ P, int which,
                                   const double* __restrict__ xy, int64_t n, double* __restrict__ out) {
@@ -94,6 +92,50 @@ __global__ void eval_field_kernel(const DevProblem* __restrict__ P, int which,
 }
 
 }  // namespace
+
+void alloc_factors(BucketFactors& f, const BucketData& bk, int32_t count) {
+  f.stride = (int64_t)bk.n * bk.ld;
+  f.A.alloc((size_t)count * f.stride * sizeof(double));
+  f.piv.alloc((size_t)count * bk.n * sizeof(int32_t));
+  f.rowscale.alloc((size_t)count * bk.n * sizeof(double));
+  f.status.alloc((size_t)count * sizeof(int32_t));
+}
+
+int factor_chunk(const DeviceCover& D, const BucketData& bk, const NodeSamples& S, int plan,
+                 BucketFactors& f, int32_t first, int32_t cnt, LuScratch& ws, hipStream_t st,
+                 PhaseHooks* hooks, double* val, double* b) {
+  const size_t wbytes = lu_workspace_bytes(plan == PDD_PLAN_PER_CIRCLE ? 1 : cnt, bk.n);
+  if (ws.bytes < wbytes) {
+    PDD_HIP(hipStreamSynchronize(st));
+    ws.buf.alloc(wbytes);
+    ws.bytes = wbytes;
+  }
+  f.first = first;
+  f.count = cnt;
+  const int64_t stride = f.stride;
+  int launches = 0;
+  const int32_t step = (plan == PDD_PLAN_PER_CIRCLE) ? 1 : cnt;
+  for (int32_t s0 = 0; s0 < cnt; s0 += step) {
+    const int32_t c1 = std::min(step, cnt - s0);
+    ChunkDesc C = D.chunk(bk, first + s0, c1);
+    double* A = f.A.ptr<double>() + (int64_t)s0 * stride;
+    int e = hooks ? hooks->begin(PH_BUILD) : -1;
+    launch_colloc_build(bk.T, C, S, A, stride, f.rowscale.ptr<double>() + (int64_t)s0 * bk.n, st);
+    if (hooks) hooks->end(e);
+    e = hooks ? hooks->begin(PH_LU) : -1;
+    launches += 1 + launch_lu_solve(bk.T, c1, A, stride, f.piv.ptr<int32_t>() + (int64_t)s0 * bk.n,
+                                    f.status.ptr<int32_t>() + s0, ws.buf.ptr<void>(), st);
+    if (hooks) hooks->end(e);
+    if (val) {
+      e = hooks ? hooks->begin(PH_EVAL) : -1;
+      launch_eval_scatter(bk.T, C, A, stride, val, b, st);
+      if (hooks) hooks->end(e);
+      ++launches;
+    }
+  }
+  PDD_HIP(hipGetLastError());
+  return launches;
+}
 
 pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_samples* samples,
                          const pdd_mc_opts* mc, const pdd_assemble_opts* opts, hipStream_t st,
@@ -137,6 +179,12 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
   const bool keep = opts ? opts->keep_factors != 0 : false;
   const int64_t budget = (opts && opts->hbm_budget_bytes > 0) ? opts->hbm_budget_bytes
                                                               : (int64_t)64 << 30;
+  int64_t factor_total = 0;
+  for (auto& bp : D.buckets) factor_total += (int64_t)bp->count * factor_bytes_per_circle(*bp);
+  const bool keep_all = keep && factor_total <= budget;
+  sys->recompute = keep && !keep_all;
+  sys->budget = budget;
+  sys->plan = plan;
   PhaseTimer timer(st);
   const int t_all = timer.begin(PH_TOTAL);
 
@@ -151,9 +199,15 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
   }
   bool need = false;
   for (int t = 0; t < 7; ++t) need = need || !given[t];
-  if (need && sum_n > 0) sys->samples.alloc(7 * sum_n * sizeof(double));
-  for (int t = 0; t < 7; ++t)
-    S.s[t] = given[t] ? given[t] : sys->samples.ptr<double>() + (int64_t)t * sum_n;
+  // a system whose factors are recomputed in the backward pass keeps its own
+  // copy of every sample
+  if ((need || sys->recompute) && sum_n > 0) sys->samples.alloc(7 * sum_n * sizeof(double));
+  for (int t = 0; t < 7; ++t) {
+    double* own = (need || sys->recompute) && sum_n > 0 ? sys->samples.ptr<double>() + (int64_t)t * sum_n : nullptr;
+    if (given[t] && own)
+      PDD_HIP(hipMemcpyAsync(own, given[t], sum_n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    S.s[t] = own ? own : given[t];
+  }
   if (need && sum_n > 0) {
     const int ev = timer.begin(PH_SAMPLE);
     double* outs[7];
@@ -244,61 +298,40 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
   PDD_HIP(hipGetLastError());
   PDD_HIP(hipEventRecord(ev_join, side));
 
-  // ---- floating rows, bucket by bucket, in chunks that fit the budget
+  // ---- floating rows, bucket by bucket, in chunks that fit the budget.  The
+  //      factors are kept when asked for and when all of them fit; otherwise
+  //      one chunk buffer per bucket is reused (stream order protects it).
   int32_t n_launch_spectral = 0;
-  std::vector<std::unique_ptr<BucketFactors>> transient;
-  DevBuf lu_work;
-  size_t lu_work_bytes = 0;
+  LuScratch lu_work;
+  int64_t kept = 0;
   for (size_t bi = 0; bi < D.buckets.size(); ++bi) {
     BucketData& bk = *D.buckets[bi];
-    const int64_t stride = (int64_t)bk.n * bk.ld;
-    const int64_t per = stride * (int64_t)sizeof(double);
-    int64_t chunk = std::max<int64_t>(1, budget / per);
-    if (plan == PDD_PLAN_PER_CIRCLE) chunk = std::max<int64_t>(1, chunk);
-    for (int32_t first = 0; first < bk.count; first += (int32_t)chunk) {
-      const int32_t cnt = (int32_t)std::min<int64_t>(chunk, bk.count - first);
-      auto f = std::make_unique<BucketFactors>();
-      f->bucket = (int32_t)bi;
-      f->first = first;
-      f->count = cnt;
-      f->stride = stride;
-      f->A.alloc((size_t)cnt * per);
-      f->piv.alloc((size_t)cnt * bk.n * sizeof(int32_t));
-      f->rowscale.alloc((size_t)cnt * bk.n * sizeof(double));
-      f->status.alloc((size_t)cnt * sizeof(int32_t));
-      const size_t wbytes = lu_workspace_bytes(plan == PDD_PLAN_PER_CIRCLE ? 1 : cnt, bk.n);
-      if (lu_work_bytes < wbytes) {
-        PDD_HIP(hipStreamSynchronize(st));
-        lu_work.alloc(wbytes);
-        lu_work_bytes = wbytes;
+    const int64_t per = factor_bytes_per_circle(bk);
+    const int32_t chunk = keep_all ? bk.count
+                                   : (int32_t)std::min<int64_t>(bk.count, std::max<int64_t>(1, budget / per));
+    std::unique_ptr<BucketFactors> reuse;
+    for (int32_t first = 0; first < bk.count; first += chunk) {
+      const int32_t cnt = std::min(chunk, bk.count - first);
+      std::unique_ptr<BucketFactors> f;
+      if (keep_all || !reuse) {
+        f = std::make_unique<BucketFactors>();
+        f->bucket = (int32_t)bi;
+        alloc_factors(*f, bk, keep_all ? cnt : chunk);
+      } else {
+        f = std::move(reuse);
       }
-      const int32_t step = (plan == PDD_PLAN_PER_CIRCLE) ? 1 : cnt;
-      for (int32_t s0 = 0; s0 < cnt; s0 += step) {
-        const int32_t c1 = std::min(step, cnt - s0);
-        ChunkDesc C = D.chunk(bk, first + s0, c1);
-        double* A = f->A.ptr<double>() + (int64_t)s0 * stride;
-        int e = timer.begin(PH_BUILD);
-        launch_colloc_build(bk.T, C, S, A, stride, f->rowscale.ptr<double>() + (int64_t)s0 * bk.n, st);
-        timer.end(e);
-        e = timer.begin(PH_LU);
-        const int lu_launches = launch_lu_solve(bk.T, c1, A, stride, f->piv.ptr<int32_t>() + (int64_t)s0 * bk.n,
-                        f->status.ptr<int32_t>() + s0, lu_work.ptr<void>(), st);
-        timer.end(e);
-        e = timer.begin(PH_EVAL);
-        launch_eval_scatter(bk.T, C, A, stride, sys->val.ptr<double>(), sys->b.ptr<double>(), st);
-        timer.end(e);
-        n_launch_spectral += 2 + lu_launches;
-      }
-      PDD_HIP(hipGetLastError());
+      n_launch_spectral += factor_chunk(D, bk, S, plan, *f, first, cnt, lu_work, st, &timer,
+                                        sys->val.ptr<double>(), sys->b.ptr<double>());
       hipLaunchKernelGGL(reduce_i32_kernel, dim3(1), dim3(256), 0, st, f->status.ptr<int32_t>(),
                          (int64_t)cnt, lu_fail.ptr<uint64_t>());
-      if (keep) sys->factors.push_back(std::move(f));
-      else transient.push_back(std::move(f));
-      if (!keep && transient.size() > 1) {
-        PDD_HIP(hipStreamSynchronize(st));
-        transient.erase(transient.begin(), transient.end() - 1);
+      if (keep_all) {
+        kept += (int64_t)cnt * per;
+        sys->factors.push_back(std::move(f));
+      } else {
+        reuse = std::move(f);
       }
     }
+    if (reuse) PDD_HIP(hipStreamSynchronize(st));   // before its buffers are freed
   }
 
   PDD_HIP(hipStreamWaitEvent(st, ev_join, 0));
@@ -313,6 +346,8 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
   s.paths = mc ? n_mc * mc->paths : 0;
   s.breakdowns = (int32_t)(flags[0] + flags[3]);
   s.n_launch_spectral = n_launch_spectral;
+  s.factor_bytes = kept;
+  s.recompute = sys->recompute ? 1 : 0;
   s.n_launch_mc = n_launch_mc;
   s.ms_sample = timer.total(PH_SAMPLE);
   s.ms_build = timer.total(PH_BUILD);

@@ -102,6 +102,36 @@ struct BucketFactors {
   DevBuf status;               // [count]
 };
 
+// Device bytes of one circle's factors in a bucket (matrix, pivots, row
+// scales, status).
+inline int64_t factor_bytes_per_circle(const BucketData& bk) {
+  return (int64_t)bk.n * bk.ld * 8 + (int64_t)bk.n * (4 + 8) + 4;
+}
+
+// Phase timing hooks of the orchestration (events on the given stream).
+enum { PH_SAMPLE, PH_BUILD, PH_LU, PH_SOLVE, PH_EVAL, PH_MC, PH_TOTAL };
+struct PhaseHooks {
+  virtual int begin(int phase, hipStream_t s = nullptr) = 0;
+  virtual void end(int idx) = 0;
+  virtual ~PhaseHooks() = default;
+};
+
+// Growable device work area of the LU launches.
+struct LuScratch {
+  DevBuf buf;
+  size_t bytes = 0;
+};
+
+void alloc_factors(BucketFactors& f, const BucketData& bk, int32_t count);
+
+// Builds, factorises and solves circles [first, first + cnt) of bucket bk into
+// f (allocated for at least cnt circles); with val/b non-null also
+// interpolates and scatters their rows.  hooks may be null.  Returns the
+// number of kernel launches.
+int factor_chunk(const DeviceCover& D, const BucketData& bk, const NodeSamples& S, int plan,
+                 BucketFactors& f, int32_t first, int32_t cnt, LuScratch& ws, hipStream_t st,
+                 PhaseHooks* hooks, double* val, double* b);
+
 }  // namespace pdd
 
 struct pdd_cover_s {
@@ -115,6 +145,9 @@ struct pdd_system_s {
   pdd::DevBuf problem;               // DevProblem
   pdd::DevBuf samples;               // [7][sum_n] node samples (owned copy)
   std::vector<std::unique_ptr<pdd::BucketFactors>> factors;
+  bool recompute = false;            // factors exceed the budget: backward rebuilds them by chunks
+  int64_t budget = 0;                // device bytes allowed for factors
+  int32_t plan = 0;
   pdd_system_stats stats{};
   std::vector<double> host_problem_bytes;
 };

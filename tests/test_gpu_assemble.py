@@ -17,7 +17,8 @@ from oracle.geometry import ROW_BOUNDARY, ROW_MC, ROW_SPECTRAL
 
 pytestmark = pytest.mark.gpu
 
-TOL_G = 1e-10
+from helpers_parity import (TOL_G, _check_mc_rows, _check_rhs, _check_spectral_rows, _fscale,
+                            _gpu_system, _row, _say, pick_mc_knots, sampled_parity)
 
 
 def _gpu():
@@ -27,69 +28,6 @@ def _gpu():
     import paper_2311_08946_amd.binding as pdd
     pdd.lib()
     return pdd
-
-
-def _say(msg):
-    print(msg, file=sys.stderr, flush=True)
-
-
-def _gpu_system(pdd, cfg, **kw):
-    prob = cfg["problem"]
-    cv = pdd.Cover(prob["domain"], cfg["cover"])
-    sysm = pdd.System(cv, prob, cfg["mc"], **kw)
-    val, b, se, se_b = (t.cpu().numpy() for t in sysm.copy())
-    return cv, sysm, val, b, se, se_b
-
-
-def _row(cover, vals, i):
-    lo, hi = cover.rowptr[i], cover.rowptr[i + 1]
-    return vals[lo:hi]
-
-
-def _check_spectral_rows(ref_cover, ref_val, ref_b, val, b, rows, prob, samples=None):
-    worst = 0.0
-    for i in rows:
-        g = _row(ref_cover, val, i)
-        o = _row(ref_cover, ref_val, i)
-        d = np.max(np.abs(g - o)) / np.max(np.abs(o))
-        worst = max(worst, d)
-        assert d <= TOL_G, (i, d)
-    return worst
-
-
-def _check_rhs(ref_cover, ref_b, b, rows, fscale):
-    for i in rows:
-        m = ref_cover.assigned[i]
-        bound = TOL_G * (abs(ref_b[i]) + ref_cover.radii[m] ** 2 * fscale.get(m, 0.0))
-        assert abs(b[i] - ref_b[i]) <= bound + 1e-300, (i, b[i], ref_b[i])
-
-
-def _fscale(prob, cv, circles):
-    out = {}
-    for m in circles:
-        grid = spectral.local_grid(cv.Nr[m], cv.Ntheta[m])
-        s = spectral.node_samples(prob, grid, *cv.centres[m], cv.radii[m])
-        out[m] = float(np.max(np.abs(s["f"])))
-    return out
-
-
-def _check_mc_rows(ref_cover, ref_val, ref_se, ref_b, ref_se_b, val, b, rows):
-    """Every entry within 3 standard errors.  With identical Philox streams the
-    path sums agree to rounding: r_i (a plain path average) must match to
-    1e-9 on all but rare rows (an exit decided by the last ulp of a libm
-    result).  C entries pass through K^-1 of the IMQ Gram matrix (condition
-    about 1e11), which amplifies summation-order rounding to about 1e-5, so
-    they are only held to the statistical bar."""
-    close = 0
-    for i in rows:
-        g = _row(ref_cover, val, i)
-        o = _row(ref_cover, ref_val, i)
-        s = _row(ref_cover, ref_se, i)
-        diff = np.abs(g - o)
-        assert np.all(diff <= 3 * s + 1e-12), (i, np.max(diff / (s + 1e-300)))
-        assert abs(b[i] - ref_b[i]) <= 3 * ref_se_b[i] + 1e-12
-        close += int(abs(b[i] - ref_b[i]) <= 1e-9 * (1 + abs(ref_b[i])))
-    return close / max(len(rows), 1)
 
 
 @pytest.mark.parametrize("name", ["config1", "small_variable"])
@@ -163,25 +101,5 @@ def test_config2_full_size_sampled():
     rng = np.random.default_rng(123)
     fl = np.nonzero(ref_cover.floating)[0]
     circles = rng.choice(fl, size=3, replace=False)
-    fsc = _fscale(prob, ref_cover, circles)
-    for m in circles:
-        knots, Crows, rv = spectral.floating_rows(prob, ref_cover, m)
-        ref_val = np.zeros(len(ref_cover.cols))
-        ref_b = np.zeros(ref_cover.N)
-        for t, i in enumerate(knots):
-            assemble._put_row(ref_cover, ref_val, ref_val.copy(), i, m, Crows[t])
-            ref_b[i] = rv[t]
-        _check_spectral_rows(ref_cover, ref_val, ref_b, val, b, knots, prob)
-        _check_rhs(ref_cover, ref_b, b, knots, fsc)
-    mc_knots = rng.choice(np.nonzero(ref_cover.row_class == ROW_MC)[0], size=3, replace=False)
-    knots, rows, ses, rv, se_r, steps = montecarlo.mc_rows(prob, ref_cover, cfg["mc"], mc_knots)
-    ref_val = np.zeros(len(ref_cover.cols))
-    ref_se = np.zeros(len(ref_cover.cols))
-    ref_b = np.zeros(ref_cover.N)
-    ref_se_b = np.zeros(ref_cover.N)
-    for t, i in enumerate(knots):
-        assemble._put_row(ref_cover, ref_val, ref_se, i, ref_cover.assigned[i], rows[t], ses[t])
-        ref_b[i] = rv[t]
-        ref_se_b[i] = se_r[t]
-    frac = _check_mc_rows(ref_cover, ref_val, ref_se, ref_b, ref_se_b, val, b, knots)
+    frac = sampled_parity(prob, ref_cover, cfg["mc"], val, b, circles, pick_mc_knots(ref_cover, rng, 3))
     assert frac > 0.99
