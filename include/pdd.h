@@ -198,10 +198,24 @@ typedef struct pdd_mc_opts {
   const double* h_per_circle;  /* host [n_circles] or NULL: per-circle step            */
 } pdd_mc_opts;
 
-enum { PDD_PLAN_BATCHED = 0, PDD_PLAN_PER_CIRCLE = 1 };
+enum { PDD_PLAN_BATCHED = 0, PDD_PLAN_PER_CIRCLE = 1, PDD_PLAN_AUTOTUNED = 2 };
 
+/*
+ * Schedule of the floating circles (batching of the size buckets, not in the
+ * paper).  Circles are grouped in size buckets (Nr, Ntheta, M); a group is a
+ * set of circles whose factors are resident together (at most
+ * hbm_budget_bytes).  Each group goes through one build launch per bucket,
+ * one sequence of persistent LU launches over all its matrices whatever their
+ * size (per 128-column step: panel, U-row and trailing-update launches; then
+ * the back substitution), and one evaluation launch per bucket.
+ *   PDD_PLAN_BATCHED    groups as given by mixed_buckets / grid_cap / use_graph;
+ *   PDD_PLAN_PER_CIRCLE the plain loop: one circle per group;
+ *   PDD_PLAN_AUTOTUNED  the library times the candidate schedules on a sample
+ *                       of each bucket on first use with a cover and keeps the
+ *                       fastest for that cover (stats report the choice).
+ */
 typedef struct pdd_assemble_opts {
-  int32_t plan;            /* PDD_PLAN_BATCHED or PDD_PLAN_PER_CIRCLE (one launch per circle) */
+  int32_t plan;            /* PDD_PLAN_BATCHED, PDD_PLAN_PER_CIRCLE or PDD_PLAN_AUTOTUNED */
   int32_t keep_factors;    /* keep LU factors for pdd_assemble_G_backward              */
   int64_t hbm_budget_bytes;/* device bytes allowed for factor storage; 0 = 64 GiB.
                               Assembly processes each size bucket in chunks of at most
@@ -210,6 +224,15 @@ typedef struct pdd_assemble_opts {
                               system keeps a copy of the node samples and
                               pdd_assemble_G_backward recomputes the factors chunk by
                               chunk (stats.recompute = 1)                              */
+  int32_t mixed_buckets;   /* 1: every group takes the same share of every bucket (one
+                              LU launch sequence serves all sizes); 0: groups hold one
+                              bucket each                                             */
+  int32_t grid_cap;        /* workgroups of the tiled LU launches, as a multiple of the
+                              compute units (each strides over its work list);
+                              0 = one workgroup per tile                              */
+  int32_t use_graph;       /* 1: capture the LU launch sequence of a group in a HIP
+                              graph and replay it for groups of the same shape        */
+  int32_t reserved;
 } pdd_assemble_opts;
 
 /*
@@ -246,7 +269,11 @@ typedef struct pdd_system_stats {
   int64_t factor_bytes;    /* LU factor bytes kept on the device for the backward pass */
   int32_t recompute;       /* 1: keep_factors asked for more than hbm_budget_bytes, so
                               the backward pass rebuilds the factors chunk by chunk   */
-  int32_t reserved;
+  int32_t n_groups;        /* groups of circles (see the schedule above)              */
+  int32_t mixed_buckets;   /* schedule used (chosen by the autotuner for            */
+  int32_t grid_cap;        /*   PDD_PLAN_AUTOTUNED)                                    */
+  int32_t graph_replays;   /* LU launch sequences replayed from a captured graph     */
+  float ms_autotune;       /* time spent tuning in this call (0 when cached)         */
 } pdd_system_stats;
 
 pdd_status pdd_system_get_stats(pdd_system sys, pdd_system_stats* out);

@@ -76,7 +76,12 @@ class McOpts(C.Structure):
 
 
 class AssembleOpts(C.Structure):
-    _fields_ = [("plan", C.c_int32), ("keep_factors", C.c_int32), ("hbm_budget_bytes", C.c_int64)]
+    _fields_ = [("plan", C.c_int32), ("keep_factors", C.c_int32), ("hbm_budget_bytes", C.c_int64),
+                ("mixed_buckets", C.c_int32), ("grid_cap", C.c_int32), ("use_graph", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+PLANS = {"batched": 0, "per_circle": 1, "autotuned": 2}
 
 
 class SystemStats(C.Structure):
@@ -85,7 +90,9 @@ class SystemStats(C.Structure):
                 ("n_launch_mc", C.c_int32)] + \
                [(n, C.c_float) for n in ("ms_sample", "ms_build", "ms_lu", "ms_solve", "ms_eval",
                                          "ms_mc", "ms_total")] + \
-               [("factor_bytes", C.c_int64), ("recompute", C.c_int32), ("reserved", C.c_int32)]
+               [("factor_bytes", C.c_int64), ("recompute", C.c_int32), ("n_groups", C.c_int32),
+                ("mixed_buckets", C.c_int32), ("grid_cap", C.c_int32), ("graph_replays", C.c_int32),
+                ("ms_autotune", C.c_float)]
 
 
 class SolveOpts(C.Structure):
@@ -290,7 +297,7 @@ class System:
     """Assembled C (CSR on the cover's pattern), r and standard errors, on the device."""
 
     def __init__(self, cover, problem, mc, samples=None, keep_factors=False, plan="batched",
-                 hbm_budget_bytes=0, stream=None):
+                 hbm_budget_bytes=0, mixed_buckets=True, grid_cap=0, use_graph=False, stream=None):
         import torch
         L = lib()
         self.cover = cover
@@ -302,7 +309,8 @@ class System:
             hpc = np.ascontiguousarray(mc["h_per_circle"], dtype=np.float64)
             keep.append(hpc)
             mo.h_per_circle = _dptr(hpc)
-        ao = AssembleOpts(0 if plan == "batched" else 1, int(bool(keep_factors)), int(hbm_budget_bytes))
+        ao = AssembleOpts(PLANS[plan], int(bool(keep_factors)), int(hbm_budget_bytes),
+                          int(bool(mixed_buckets)), int(grid_cap), int(bool(use_graph)), 0)
         sm = None
         if samples is not None:
             for k, v in samples.items():

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -137,6 +138,275 @@ int factor_chunk(const DeviceCover& D, const BucketData& bk, const NodeSamples& 
   return launches;
 }
 
+// ---------------------------------------------------------------------------
+// Schedule of the floating circles: groups of bucket slices, one persistent LU
+// launch sequence per group.
+
+struct Slice {
+  int32_t bucket, first, cnt;
+};
+
+struct Schedule {
+  bool mixed = true;
+  int grid_cap = 0;          // multiple of the compute units; 0 = one workgroup per tile
+  bool graph = false;
+};
+
+// Groups of circles whose factors are resident together.
+std::vector<std::vector<Slice>> make_groups(const DeviceCover& D, int plan, bool keep_all, int64_t budget,
+                                            bool mixed) {
+  std::vector<std::vector<Slice>> groups;
+  const int nb = (int)D.buckets.size();
+  if (plan == PDD_PLAN_PER_CIRCLE) {
+    for (int b = 0; b < nb; ++b)
+      for (int32_t i = 0; i < D.buckets[b]->count; ++i) groups.push_back({Slice{b, i, 1}});
+    return groups;
+  }
+  if (!mixed) {
+    for (int b = 0; b < nb; ++b) {
+      const BucketData& bk = *D.buckets[b];
+      const int32_t chunk = keep_all ? bk.count
+                                     : (int32_t)std::min<int64_t>(bk.count,
+                                                                  std::max<int64_t>(1, budget / factor_bytes_per_circle(bk)));
+      for (int32_t first = 0; first < bk.count; first += chunk)
+        groups.push_back({Slice{b, first, std::min(chunk, bk.count - first)}});
+    }
+    return groups;
+  }
+  int64_t total = 0, most = 1;
+  for (int b = 0; b < nb; ++b) {
+    total += (int64_t)D.buckets[b]->count * factor_bytes_per_circle(*D.buckets[b]);
+    most = std::max<int64_t>(most, D.buckets[b]->count);
+  }
+  // a group holds the same share of every bucket; the number of groups G
+  // grows geometrically until the largest group fits the budget, and stops at
+  // one circle per bucket and group
+  int64_t G = keep_all ? 1 : std::min(most, std::max<int64_t>(1, (total + budget - 1) / budget));
+  while (!keep_all && G < most) {
+    int64_t worst = 0;
+    for (int64_t g = 0; g < G; ++g) {
+      int64_t bytes = 0;
+      for (int b = 0; b < nb; ++b) {
+        const int64_t c = D.buckets[b]->count;
+        bytes += (c * (g + 1) / G - c * g / G) * factor_bytes_per_circle(*D.buckets[b]);
+      }
+      worst = std::max(worst, bytes);
+    }
+    if (worst <= budget) break;
+    G = std::min(most, std::max(G + 1, G + G / 4));
+  }
+  for (int64_t g = 0; g < G; ++g) {
+    std::vector<Slice> grp;
+    for (int b = 0; b < nb; ++b) {
+      const int64_t c = D.buckets[b]->count;
+      const int32_t lo = (int32_t)(c * g / G), hi = (int32_t)(c * (g + 1) / G);
+      if (hi > lo) grp.push_back(Slice{b, lo, hi - lo});
+    }
+    if (!grp.empty()) groups.push_back(std::move(grp));
+  }
+  return groups;
+}
+
+// Runs groups: build launches per slice, the group's LU plan (replayed from a
+// captured graph when the previous group had the same shape and buffers),
+// evaluation launches per slice.
+struct GroupRun {
+  const DeviceCover& D;
+  hipStream_t st;
+  Schedule sched;
+  int cus = 256;
+  LuScratch work;
+  std::vector<std::unique_ptr<BucketFactors>> reuse;   // per bucket, transient groups
+  std::vector<std::unique_ptr<LuPlan>> plans;          // alive until finish()
+  LuPlan* last_plan = nullptr;
+  std::vector<int32_t> last_counts;
+  std::vector<BucketFactors*> last_fs;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int replays = 0;
+
+  GroupRun(const DeviceCover& d, hipStream_t s, const Schedule& sc) : D(d), st(s), sched(sc) {
+    int dev = 0;
+    PDD_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    PDD_HIP(hipGetDeviceProperties(&prop, dev));
+    cus = prop.multiProcessorCount;
+    reuse.resize(D.buckets.size());
+  }
+  ~GroupRun() { drop_graph(); if (cap_stream) (void)hipStreamDestroy(cap_stream); }
+
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+
+  BucketFactors* reusable(int b, const std::vector<std::vector<Slice>>& groups) {
+    if (!reuse[b]) {
+      int32_t most = 1;
+      for (const auto& g : groups)
+        for (const auto& sl : g)
+          if (sl.bucket == b) most = std::max(most, sl.cnt);
+      reuse[b] = std::make_unique<BucketFactors>();
+      reuse[b]->bucket = b;
+      alloc_factors(*reuse[b], *D.buckets[b], most);
+    }
+    return reuse[b].get();
+  }
+
+  int grid_cap() const { return sched.grid_cap > 0 ? sched.grid_cap * cus : (1 << 30); }
+
+  int group(const std::vector<Slice>& grp, const std::vector<BucketFactors*>& fs, const NodeSamples& S,
+            PhaseHooks* hooks, double* val, double* b, uint64_t* fail_count) {
+    int launches = 0;
+    size_t wbytes = 0;
+    for (const auto& sl : grp) wbytes += (size_t)sl.cnt * lu_work_bytes_per_matrix(D.buckets[sl.bucket]->n);
+    if (work.bytes < wbytes) {
+      PDD_HIP(hipStreamSynchronize(st));
+      drop_graph();
+      last_plan = nullptr;
+      work.buf.alloc(wbytes);
+      work.bytes = wbytes;
+    }
+    int e = hooks ? hooks->begin(PH_BUILD) : -1;
+    for (size_t k = 0; k < grp.size(); ++k) {
+      const BucketData& bk = *D.buckets[grp[k].bucket];
+      ChunkDesc C = D.chunk(bk, grp[k].first, grp[k].cnt);
+      launch_colloc_build(bk.T, C, S, fs[k]->A.ptr<double>(), fs[k]->stride, fs[k]->rowscale.ptr<double>(), st);
+      ++launches;
+    }
+    if (hooks) hooks->end(e);
+    // the group's matrices, in slice order
+    std::vector<int32_t> counts;
+    for (const auto& sl : grp) counts.push_back(sl.bucket), counts.push_back(sl.cnt);
+    const bool same = last_plan && counts == last_counts && fs == last_fs;
+    e = hooks ? hooks->begin(PH_LU) : -1;
+    if (!same) {
+      std::vector<LuItem> its;
+      char* w = static_cast<char*>(work.buf.ptr<void>());
+      for (size_t k = 0; k < grp.size(); ++k) {
+        const BucketData& bk = *D.buckets[grp[k].bucket];
+        const size_t per = lu_work_bytes_per_matrix(bk.n);
+        for (int32_t i = 0; i < grp[k].cnt; ++i) {
+          LuItem it;
+          it.A = fs[k]->A.ptr<double>() + (int64_t)i * fs[k]->stride;
+          it.piv = fs[k]->piv.ptr<int32_t>() + (int64_t)i * bk.n;
+          it.status = fs[k]->status.ptr<int32_t>() + i;
+          it.work = reinterpret_cast<LuWork*>(w);
+          it.uinv = reinterpret_cast<double*>(w + lu_work_header_bytes());
+          it.n = bk.n;
+          it.ld = bk.ld;
+          it.nrhs = bk.nrhs;
+          it.cls = lu_panel_class(bk.n);
+          its.push_back(it);
+          w += per;
+        }
+      }
+      auto plan = std::make_unique<LuPlan>();
+      plan->build(its);
+      last_plan = plan.get();
+      plans.push_back(std::move(plan));
+      last_counts = counts;
+      last_fs = fs;
+      drop_graph();
+      if (sched.graph) {
+        if (!cap_stream) PDD_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+        PDD_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+        last_plan->launch(cap_stream, grid_cap());
+        PDD_HIP(hipStreamEndCapture(cap_stream, &graph));
+        PDD_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        PDD_HIP(hipGraphLaunch(exec, st));
+        launches += 1;
+      } else {
+        launches += last_plan->launch(st, grid_cap());
+      }
+    } else if (exec) {
+      PDD_HIP(hipGraphLaunch(exec, st));
+      ++replays;
+      launches += 1;
+    } else {
+      launches += last_plan->launch(st, grid_cap());
+    }
+    if (hooks) hooks->end(e);
+    if (val) {
+      e = hooks ? hooks->begin(PH_EVAL) : -1;
+      for (size_t k = 0; k < grp.size(); ++k) {
+        const BucketData& bk = *D.buckets[grp[k].bucket];
+        ChunkDesc C = D.chunk(bk, grp[k].first, grp[k].cnt);
+        launch_eval_scatter(bk.T, C, fs[k]->A.ptr<double>(), fs[k]->stride, val, b, st);
+        ++launches;
+      }
+      if (hooks) hooks->end(e);
+    }
+    for (size_t k = 0; k < grp.size(); ++k)
+      hipLaunchKernelGGL(reduce_i32_kernel, dim3(1), dim3(256), 0, st, fs[k]->status.ptr<int32_t>(),
+                         (int64_t)grp[k].cnt, fail_count);
+    PDD_HIP(hipGetLastError());
+    return launches;
+  }
+
+  void finish() { PDD_HIP(hipStreamSynchronize(st)); }
+};
+
+// Times the candidate schedules (mixed or per-bucket groups, grid caps) on a
+// sample of up to 64 circles per bucket (build and LU only) and returns the
+// fastest.
+void autotune(const DeviceCover& D, const NodeSamples& S, int64_t budget, hipStream_t st, bool& mixed,
+              int& cap) {
+  std::vector<std::vector<Slice>> sample_mixed(1), sample_sep;
+  for (int b = 0; b < (int)D.buckets.size(); ++b) {
+    const int32_t c = std::min<int32_t>(64, D.buckets[b]->count);
+    if (c == 0) continue;
+    sample_mixed[0].push_back(Slice{b, 0, c});
+    sample_sep.push_back({Slice{b, 0, c}});
+  }
+  std::vector<std::unique_ptr<BucketFactors>> fac(D.buckets.size());
+  for (const auto& sl : sample_mixed[0]) {
+    fac[sl.bucket] = std::make_unique<BucketFactors>();
+    fac[sl.bucket]->bucket = sl.bucket;
+    alloc_factors(*fac[sl.bucket], *D.buckets[sl.bucket], sl.cnt);
+  }
+  DevBuf fails;
+  fails.alloc(sizeof(uint64_t));
+  hipEvent_t e0, e1;
+  PDD_HIP(hipEventCreate(&e0));
+  PDD_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  const int caps[3] = {0, 1, 2};
+  bool first = true;
+  for (int mx = 1; mx >= 0; --mx)
+    for (int ci = 0; ci < 3; ++ci) {
+      Schedule sc;
+      sc.mixed = mx != 0;
+      sc.grid_cap = caps[ci];
+      const auto& groups = sc.mixed ? sample_mixed : sample_sep;
+      for (int rep = 0; rep < (first ? 2 : 1); ++rep) {
+        GroupRun run(D, st, sc);
+        PDD_HIP(hipEventRecord(e0, st));
+        for (const auto& grp : groups) {
+          std::vector<BucketFactors*> fs;
+          for (const auto& sl : grp) fs.push_back(fac[sl.bucket].get());
+          run.group(grp, fs, S, nullptr, nullptr, nullptr, fails.ptr<uint64_t>());
+        }
+        PDD_HIP(hipEventRecord(e1, st));
+        run.finish();
+      }
+      first = false;
+      float ms = 0.0f;
+      PDD_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        mixed = sc.mixed;
+        cap = sc.grid_cap;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)budget;
+}
+
 pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_samples* samples,
                          const pdd_mc_opts* mc, const pdd_assemble_opts* opts, hipStream_t st,
                          pdd_system* out) {
@@ -220,6 +490,22 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
     timer.end(ev);
   }
 
+  // ---- schedule of the floating rows (tuned before the Monte Carlo work starts)
+  Schedule sched;
+  sched.mixed = opts ? opts->mixed_buckets != 0 : true;
+  sched.grid_cap = opts ? std::max(0, opts->grid_cap) : 0;
+  sched.graph = opts ? opts->use_graph != 0 : false;
+  float ms_tune = 0.0f;
+  if (plan == PDD_PLAN_AUTOTUNED) {
+    if (!D.tuned) {
+      const auto t0 = std::chrono::steady_clock::now();
+      autotune(D, S, budget, st, D.tuned_mixed, D.tuned_cap);
+      D.tuned = true;
+      ms_tune = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    sched.mixed = D.tuned_mixed;
+    sched.grid_cap = D.tuned_cap;
+  }
   // The Monte Carlo and boundary rows run on a second stream, concurrently
   // with the floating rows; both write disjoint rows of the CSR arrays.
   DevBuf lu_fail;
@@ -298,41 +584,34 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
   PDD_HIP(hipGetLastError());
   PDD_HIP(hipEventRecord(ev_join, side));
 
-  // ---- floating rows, bucket by bucket, in chunks that fit the budget.  The
-  //      factors are kept when asked for and when all of them fit; otherwise
-  //      one chunk buffer per bucket is reused (stream order protects it).
+  // ---- floating rows in groups (see the schedule in pdd.h)
+  const auto groups = make_groups(D, plan, keep_all, budget, sched.mixed);
+  GroupRun run(D, st, sched);
   int32_t n_launch_spectral = 0;
-  LuScratch lu_work;
   int64_t kept = 0;
-  for (size_t bi = 0; bi < D.buckets.size(); ++bi) {
-    BucketData& bk = *D.buckets[bi];
-    const int64_t per = factor_bytes_per_circle(bk);
-    const int32_t chunk = keep_all ? bk.count
-                                   : (int32_t)std::min<int64_t>(bk.count, std::max<int64_t>(1, budget / per));
-    std::unique_ptr<BucketFactors> reuse;
-    for (int32_t first = 0; first < bk.count; first += chunk) {
-      const int32_t cnt = std::min(chunk, bk.count - first);
-      std::unique_ptr<BucketFactors> f;
-      if (keep_all || !reuse) {
-        f = std::make_unique<BucketFactors>();
-        f->bucket = (int32_t)bi;
-        alloc_factors(*f, bk, keep_all ? cnt : chunk);
-      } else {
-        f = std::move(reuse);
-      }
-      n_launch_spectral += factor_chunk(D, bk, S, plan, *f, first, cnt, lu_work, st, &timer,
-                                        sys->val.ptr<double>(), sys->b.ptr<double>());
-      hipLaunchKernelGGL(reduce_i32_kernel, dim3(1), dim3(256), 0, st, f->status.ptr<int32_t>(),
-                         (int64_t)cnt, lu_fail.ptr<uint64_t>());
+  for (const auto& grp : groups) {
+    std::vector<BucketFactors*> fs(grp.size());
+    for (size_t k = 0; k < grp.size(); ++k) {
+      const Slice& sl = grp[k];
       if (keep_all) {
-        kept += (int64_t)cnt * per;
+        auto f = std::make_unique<BucketFactors>();
+        f->bucket = sl.bucket;
+        alloc_factors(*f, *D.buckets[sl.bucket], sl.cnt);
+        f->first = sl.first;
+        f->count = sl.cnt;
+        fs[k] = f.get();
+        kept += (int64_t)sl.cnt * factor_bytes_per_circle(*D.buckets[sl.bucket]);
         sys->factors.push_back(std::move(f));
       } else {
-        reuse = std::move(f);
+        fs[k] = run.reusable(sl.bucket, groups);
+        fs[k]->first = sl.first;
+        fs[k]->count = sl.cnt;
       }
     }
-    if (reuse) PDD_HIP(hipStreamSynchronize(st));   // before its buffers are freed
+    n_launch_spectral += run.group(grp, fs, S, &timer, sys->val.ptr<double>(), sys->b.ptr<double>(),
+                                   lu_fail.ptr<uint64_t>());
   }
+  run.finish();
 
   PDD_HIP(hipStreamWaitEvent(st, ev_join, 0));
   timer.end(t_all);
@@ -348,6 +627,11 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
   s.n_launch_spectral = n_launch_spectral;
   s.factor_bytes = kept;
   s.recompute = sys->recompute ? 1 : 0;
+  s.n_groups = (int32_t)groups.size();
+  s.mixed_buckets = sched.mixed ? 1 : 0;
+  s.grid_cap = sched.grid_cap;
+  s.graph_replays = run.replays;
+  s.ms_autotune = ms_tune;
   s.n_launch_mc = n_launch_mc;
   s.ms_sample = timer.total(PH_SAMPLE);
   s.ms_build = timer.total(PH_BUILD);

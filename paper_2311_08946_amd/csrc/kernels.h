@@ -49,10 +49,26 @@ void launch_colloc_build(const BucketTables& T, const ChunkDesc& C, const NodeSa
                          double* A, int64_t mat_stride, double* rowscale, hipStream_t st);
 // K2/K3: in-place LU with partial pivoting of the n x n block, applied to all ld
 // columns (forward elimination of the right-hand sides), then back
-// substitution U W = R' on the right-hand-side columns.  `work` holds
-// lu_workspace_bytes(count, n) bytes of device memory.
+// substitution U W = R' on the right-hand-side columns.
+struct LuWork;                 // per-matrix step data (device)
+struct LuItem {                // one matrix of a batch (device pointers)
+  double* A;                   // [n][ld]
+  int32_t* piv;                // [n]
+  int32_t* status;             // 1 = zero pivot met
+  LuWork* work;                // lu_work_bytes_per_matrix(n) bytes: LuWork, then
+  double* uinv;                //   the inverses of U's 32 x 32 diagonal blocks
+  int32_t n, ld, nrhs, cls;    // cls = lu_panel_class(n)
+};
+// launch kinds: the panel kernel per size class, then the tiled kinds
+enum { LU_PANEL0, LU_PANEL1, LU_PANEL2, LU_PANEL3, LU_UROW, LU_UPDATE, LU_BDIAG, LU_BUPD, LU_KINDS };
+int lu_panel_class(int n);
+size_t lu_work_bytes_per_matrix(int32_t n);
+size_t lu_work_header_bytes();   // sizeof(LuWork): the inverses of U's blocks follow
 size_t lu_workspace_bytes(int32_t count, int32_t n);
-// Returns the number of kernel launches issued.
+// Work units of one matrix in one launch of the given kind at the given step.
+int lu_plan_tiles(const LuItem& it, int kind, int step);
+// One bucket chunk of `count` matrices with a contiguous work area; returns
+// the number of kernel launches.
 int launch_lu_solve(const BucketTables& T, int32_t count, double* A, int64_t mat_stride,
                     int32_t* piv, int32_t* status, void* work, hipStream_t st);
 // K4: interpolation at the assigned knots and scatter into CSR values and r.

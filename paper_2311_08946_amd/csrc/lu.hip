@@ -29,8 +29,9 @@
 // 128 x 128 workgroup tiles and K streamed through LDS in chunks of 32, the
 // next chunk's global loads issued before the current chunk's MFMAs.
 #include <algorithm>
+#include <vector>
 
-#include "kernels.h"
+#include "runtime.h"
 
 namespace pdd {
 
@@ -242,6 +243,8 @@ __device__ __attribute__((always_inline)) void tri_apply(double* __restrict__ A,
   __syncthreads();
 }
 
+}  // namespace
+
 // Per-matrix work area of one step (global memory).
 struct LuWork {
   double inv[kOuter / kTB][kTB][kTB];  // inverses of L11's unit-lower diagonal blocks
@@ -250,6 +253,9 @@ struct LuWork {
   int count;
   int pad[63];
 };
+static_assert(sizeof(LuWork) % 8 == 0, "the inverses of U's blocks follow LuWork");
+
+namespace {
 
 // Composes the interchanges (base + t) <-> piv[t], t = 0..cnt-1 in order
 // (cnt <= 128), into one permutation of at most 2 cnt rows: rows[e] receives
@@ -431,26 +437,29 @@ __device__ __attribute__((always_inline)) void factor_subpanel(double* __restric
   __syncthreads();
 }
 
-template <int ROWS, int NB>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void lu_panel_kernel(double* __restrict__ A0, int n, int ld,
-                                                            int64_t stride, int32_t* __restrict__ piv0,
-                                                            int32_t* __restrict__ status,
-                                                            LuWork* __restrict__ work,
-                                                            double* __restrict__ uinv0, int K0) {
-  constexpr int TB = NB < 16 ? 16 : NB;
-  __shared__ union {
-    GemmLds g;
-    TriLds t;
-  } u;
-  __shared__ PanelLds<NB> s_pl;
-  __shared__ int s_piv[kOuter];
-  __shared__ PermLds s_perm;
+// ---------------------------------------------------------------------------
+// Work bodies.  Each acts on one matrix (or one tile of it); the scheduled
+// kernels below pick the matrix and tile from a work list.
 
-  const int m = blockIdx.x;
-  double* A = A0 + (int64_t)m * stride;
-  int32_t* piv = piv0 + (int64_t)m * n;
-  LuWork* W = work + m;
-  double* uinv = uinv0 + (int64_t)m * ((n + kTB - 1) / kTB) * kTB * kTB;
+union MatLds {
+  GemmLds g;
+  TriLds t;
+};
+
+template <int NB>
+struct PanelShared {
+  MatLds u;
+  PanelLds<NB> pl;
+  int piv[kOuter];
+  PermLds perm;
+};
+
+template <int ROWS, int NB>
+__device__ __attribute__((always_inline)) void panel_body(const LuItem& it, int K0, PanelShared<NB>& sh) {
+  constexpr int TB = NB < 16 ? 16 : NB;
+  double* A = it.A;
+  const int n = it.n, ld = it.ld;
+  LuWork* W = it.work;
   const int tid = threadIdx.x;
   const int kb = min(kOuter, n - K0);
   int singular = 0;
@@ -460,62 +469,57 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
     const int gw = min(kTB, K0 + kb - g0);
     for (int k0 = g0; k0 < g0 + gw; k0 += NB) {
       const int pw = min(NB, g0 + gw - k0);
-      factor_subpanel<ROWS, NB>(A, ld, n, k0, pw, K0, s_piv, piv, s_pl, singular);
-      if (tid == 0) compose_perm(s_piv + (k0 - K0), k0, pw, s_perm.rows, s_perm.src, &s_perm.count);
+      factor_subpanel<ROWS, NB>(A, ld, n, k0, pw, K0, sh.piv, it.piv, sh.pl, singular);
+      if (tid == 0) compose_perm(sh.piv + (k0 - K0), k0, pw, sh.perm.rows, sh.perm.src, &sh.perm.count);
       __syncthreads();
       // the sub-panel's interchanges on the rest of the panel
-      apply_perm(A, ld, s_perm, K0, K0 + kb, k0, k0 + pw, &u.g.Lt[0][0]);
+      apply_perm(A, ld, sh.perm, K0, K0 + kb, k0, k0 + pw, &sh.u.g.Lt[0][0]);
       if (k0 + pw < g0 + gw) {
-        tri_inverse<TB, true>(A, ld, k0, pw, u.t);
-        tri_apply<TB>(A, ld, k0, pw, k0 + pw, g0 + gw, u.t);
-        gemm_sub(A, ld, k0 + pw, n, k0 + pw, g0 + gw, k0, k0 + pw, u.g);
+        tri_inverse<TB, true>(A, ld, k0, pw, sh.u.t);
+        tri_apply<TB>(A, ld, k0, pw, k0 + pw, g0 + gw, sh.u.t);
+        gemm_sub(A, ld, k0 + pw, n, k0 + pw, g0 + gw, k0, k0 + pw, sh.u.g);
       }
     }
     // the group's diagonal block is final: keep the inverse of its upper
     // triangle for the back substitution and that of its unit-lower triangle
     // for the U12 tiles
-    tri_inverse<kTB, false>(A, ld, g0, gw, u.t);
-    for (int idx = tid; idx < kTB * kTB; idx += kThreads) uinv[(g0 / kTB) * kTB * kTB + idx] = u.t.inv[idx >> 5][idx & 31];
+    tri_inverse<kTB, false>(A, ld, g0, gw, sh.u.t);
+    for (int idx = tid; idx < kTB * kTB; idx += kThreads)
+      it.uinv[(g0 / kTB) * kTB * kTB + idx] = sh.u.t.inv[idx >> 5][idx & 31];
     __syncthreads();
-    tri_inverse<kTB, true>(A, ld, g0, gw, u.t);
-    for (int idx = tid; idx < kTB * kTB; idx += kThreads) W->inv[b][idx >> 5][idx & 31] = u.t.inv[idx >> 5][idx & 31];
+    tri_inverse<kTB, true>(A, ld, g0, gw, sh.u.t);
+    for (int idx = tid; idx < kTB * kTB; idx += kThreads) W->inv[b][idx >> 5][idx & 31] = sh.u.t.inv[idx >> 5][idx & 31];
     if (g0 + gw < K0 + kb) {
-      tri_apply<kTB>(A, ld, g0, gw, g0 + gw, K0 + kb, u.t);
-      gemm_sub(A, ld, g0 + gw, n, g0 + gw, K0 + kb, g0, g0 + gw, u.g);
+      tri_apply<kTB>(A, ld, g0, gw, g0 + gw, K0 + kb, sh.u.t);
+      gemm_sub(A, ld, g0 + gw, n, g0 + gw, K0 + kb, g0, g0 + gw, sh.u.g);
     }
     __syncthreads();
   }
-  if (tid == 0) compose_perm(s_piv, K0, kb, W->rows, W->src, &W->count);
-  if (tid == 0 && (K0 == 0 || singular)) status[m] = singular;
+  if (tid == 0) compose_perm(sh.piv, K0, kb, W->rows, W->src, &W->count);
+  if (tid == 0 && (K0 == 0 || singular)) *it.status = singular;
 }
 
-// Grid (left + right tiles, count).  Left tiles (columns < K0) only take the
+// Tile t of the step's U-row work: left tiles (columns < K0) only take the
 // interchanges; right tiles (columns >= K0 + kb, right-hand sides included)
 // then become rows [K0, K0 + kb) of U.
-__global__ __launch_bounds__(kThreads) void lu_urow_kernel(double* __restrict__ A0, int n, int ld,
-                                                           int64_t stride, const LuWork* __restrict__ work,
-                                                           int K0) {
-  __shared__ union {
-    GemmLds g;
-    TriLds t;
-  } u;
-  __shared__ PermLds s_perm;
-  const int m = blockIdx.y;
-  double* A = A0 + (int64_t)m * stride;
-  const LuWork* W = work + m;
+__device__ __attribute__((always_inline)) void urow_body(const LuItem& it, int K0, int t, MatLds& u,
+                                                          PermLds& perm) {
+  double* A = it.A;
+  const int n = it.n, ld = it.ld;
+  const LuWork* W = it.work;
   const int tid = threadIdx.x;
   const int kb = min(kOuter, n - K0);
   const int nleft = K0 / kGT;
-  const bool right = (int)blockIdx.x >= nleft;
-  const int c0 = right ? K0 + kb + ((int)blockIdx.x - nleft) * kGT : (int)blockIdx.x * kGT;
+  const bool right = t >= nleft;
+  const int c0 = right ? K0 + kb + (t - nleft) * kGT : t * kGT;
   const int c1 = min(right ? ld : K0, c0 + kGT);
-  if (tid == 0) s_perm.count = W->count;
+  if (tid == 0) perm.count = W->count;
   for (int e = tid; e < 2 * kOuter; e += kThreads) {
-    s_perm.rows[e] = W->rows[e];
-    s_perm.src[e] = W->src[e];
+    perm.rows[e] = W->rows[e];
+    perm.src[e] = W->src[e];
   }
   __syncthreads();
-  apply_perm(A, ld, s_perm, c0, c1, 0, 0, &u.g.Lt[0][0]);
+  apply_perm(A, ld, perm, c0, c1, 0, 0, &u.g.Lt[0][0]);
   if (!right) return;
   for (int b = 0; b * kTB < kb; ++b) {
     const int a = K0 + b * kTB, w = min(kTB, kb - b * kTB);
@@ -526,116 +530,215 @@ __global__ __launch_bounds__(kThreads) void lu_urow_kernel(double* __restrict__ 
   }
 }
 
-// Grid (row tiles x column tiles of the trailing matrix, count).
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void lu_update_kernel(double* __restrict__ A0, int n, int ld,
-                                                             int64_t stride, int K0, int ctiles) {
-  __shared__ GemmLds g;
-  const int m = blockIdx.y;
-  double* A = A0 + (int64_t)m * stride;
+// Tile t (row-major over the trailing tiles) of A22 -= L21 U12.
+__device__ __attribute__((always_inline)) void update_body(const LuItem& it, int K0, int t, GemmLds& g) {
+  const int n = it.n, ld = it.ld;
   const int kb = min(kOuter, n - K0);
   const int r0 = K0 + kb;
-  const int i = (int)blockIdx.x / ctiles, j = (int)blockIdx.x - i * ctiles;
+  const int ct = (ld - r0 + kGT - 1) / kGT;
+  const int i = t / ct, j = t - i * ct;
   const int ra = r0 + i * kGT, ca = r0 + j * kGT;
-  gemm_sub(A, ld, ra, min(n, ra + kGT), ca, min(ld, ca + kGT), K0, K0 + kb, g);
+  gemm_sub(it.A, ld, ra, min(n, ra + kGT), ca, min(ld, ca + kGT), K0, K0 + kb, g);
 }
 
 // Back substitution U W = R' on columns [n, n + nrhs), right-looking from the
-// bottom in blocks of kOuter rows aligned with the factorisation, two
-// launches per block: lu_bdiag_kernel (one workgroup per matrix) solves the
-// diagonal block by its 32-row triangles (stored inverses on MFMA) and MFMA
-// updates inside the block; lu_bupd_kernel (one workgroup per matrix and
-// 128-row tile above the block) removes the block's contribution from the
-// rows above.
-__global__ __launch_bounds__(kThreads) void lu_bdiag_kernel(double* __restrict__ A0, int n, int ld,
-                                                            int nrhs, int64_t stride,
-                                                            const double* __restrict__ uinv0, int k0) {
-  __shared__ union {
-    GemmLds g;
-    TriLds t;
-  } u;
-  double* A = A0 + (int64_t)blockIdx.x * stride;
-  const double* uinv = uinv0 + (int64_t)blockIdx.x * ((n + kTB - 1) / kTB) * kTB * kTB;
+// bottom in blocks of kOuter rows aligned with the factorisation: the
+// diagonal block is solved by its 32-row triangles (stored inverses on MFMA)
+// and MFMA updates inside the block ...
+__device__ __attribute__((always_inline)) void bdiag_body(const LuItem& it, int k0, MatLds& u) {
+  double* A = it.A;
+  const int n = it.n, ld = it.ld, nrhs = it.nrhs;
   const int tid = threadIdx.x;
   const int k1 = min(n, k0 + kOuter);
   for (int a0 = k0 + (k1 - 1 - k0) / kTB * kTB; a0 >= k0; a0 -= kTB) {
     const int b1 = min(k1, a0 + kTB);
     for (int idx = tid; idx < kTB * kTB; idx += kThreads)
-      u.t.inv[idx >> 5][idx & 31] = uinv[(a0 / kTB) * kTB * kTB + idx];
+      u.t.inv[idx >> 5][idx & 31] = it.uinv[(a0 / kTB) * kTB * kTB + idx];
     __syncthreads();
     tri_apply<kTB>(A, ld, a0, b1 - a0, n, n + nrhs, u.t);
     if (a0 > k0) gemm_sub(A, ld, k0, a0, n, n + nrhs, a0, b1, u.g);
   }
 }
 
-// Grid (k0 / kGT row tiles, count).
-__global__ __launch_bounds__(kThreads) void lu_bupd_kernel(
-    double* __restrict__ A0, int n, int ld, int nrhs, int64_t stride, int k0) {
-  __shared__ GemmLds g;
-  double* A = A0 + (int64_t)blockIdx.y * stride;
+// ... and its contribution is removed from the 128-row tile t above it.
+__device__ __attribute__((always_inline)) void bupd_body(const LuItem& it, int k0, int t, GemmLds& g) {
+  const int n = it.n;
   const int k1 = min(n, k0 + kOuter);
-  const int r0 = (int)blockIdx.x * kGT;
-  gemm_sub(A, ld, r0, min(k0, r0 + kGT), n, n + nrhs, k0, k1, g);
+  const int r0 = t * kGT;
+  gemm_sub(it.A, it.ld, r0, min(k0, r0 + kGT), n, n + it.nrhs, k0, k1, g);
+}
+
+// ---------------------------------------------------------------------------
+// Scheduled (persistent) kernels.  A work list is a prefix array pre[count+1]
+// over the batch's matrices: matrix m owns global work indices
+// [pre[m], pre[m+1]).  Each workgroup strides over the list, so one launch
+// serves matrices of every size in the batch.
+
+__device__ __forceinline__ int owner(const int32_t* __restrict__ pre, int count, int g) {
+  int lo = 0, hi = count;                 // last m with pre[m] <= g
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int back_block(const LuItem& it, int step) {
+  return ((it.n + kOuter - 1) / kOuter - 1 - step) * kOuter;
 }
 
 template <int ROWS, int NB>
-int launch_steps(const BucketTables& T, int32_t count, double* A, int64_t stride, int32_t* piv,
-                  int32_t* status, LuWork* work, double* uinv, hipStream_t st) {
-  const int n = T.n, ld = T.ld;
-  int launches = 0;
-  for (int K0 = 0; K0 < n; K0 += kOuter) {
-    const int kb = std::min(kOuter, n - K0);
-    hipLaunchKernelGGL((lu_panel_kernel<ROWS, NB>), dim3(count), dim3(kThreads), 0, st, A, n, ld, stride,
-                       piv, status, work, uinv, K0);
-    ++launches;
-    const int tiles = K0 / kGT + (ld - K0 - kb + kGT - 1) / kGT;
-    if (tiles > 0)
-    {
-      hipLaunchKernelGGL(lu_urow_kernel, dim3(tiles, count), dim3(kThreads), 0, st, A, n, ld, stride,
-                         work, K0);
-      ++launches;
-    }
-    const int rt = (n - K0 - kb + kGT - 1) / kGT, ct = (ld - K0 - kb + kGT - 1) / kGT;
-    if (rt > 0 && ct > 0)
-    {
-      hipLaunchKernelGGL(lu_update_kernel, dim3(rt * ct, count), dim3(kThreads), 0, st, A, n, ld, stride,
-                         K0, ct);
-      ++launches;
-    }
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void lu_panel_kernel(
+    const LuItem* __restrict__ items, const int32_t* __restrict__ pre, int count, int step) {
+  __shared__ PanelShared<NB> sh;
+  const int total = pre[count];
+  for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
+    panel_body<ROWS, NB>(items[owner(pre, count, gi)], step * kOuter, sh);
+    __syncthreads();
   }
-  for (int k0 = (n - 1) / kOuter * kOuter; k0 >= 0; k0 -= kOuter) {
-    hipLaunchKernelGGL(lu_bdiag_kernel, dim3(count), dim3(kThreads), 0, st, A, n, ld, T.nrhs, stride, uinv, k0);
-    ++launches;
-    if (k0 > 0) {
-      hipLaunchKernelGGL(lu_bupd_kernel, dim3(k0 / kGT, count), dim3(kThreads), 0, st, A, n, ld, T.nrhs, stride,
-                         k0);
-      ++launches;
-    }
+}
+
+__global__ __launch_bounds__(kThreads) void lu_urow_kernel(const LuItem* __restrict__ items,
+                                                           const int32_t* __restrict__ pre, int count, int step) {
+  __shared__ MatLds u;
+  __shared__ PermLds perm;
+  const int total = pre[count];
+  for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
+    const int m = owner(pre, count, gi);
+    urow_body(items[m], step * kOuter, gi - pre[m], u, perm);
+    __syncthreads();
   }
-  return launches;
+}
+
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void lu_update_kernel(
+    const LuItem* __restrict__ items, const int32_t* __restrict__ pre, int count, int step) {
+  __shared__ GemmLds g;
+  const int total = pre[count];
+  for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
+    const int m = owner(pre, count, gi);
+    update_body(items[m], step * kOuter, gi - pre[m], g);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void lu_bdiag_kernel(const LuItem* __restrict__ items,
+                                                            const int32_t* __restrict__ pre, int count, int step) {
+  __shared__ MatLds u;
+  const int total = pre[count];
+  for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
+    const LuItem it = items[owner(pre, count, gi)];
+    bdiag_body(it, back_block(it, step), u);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void lu_bupd_kernel(const LuItem* __restrict__ items,
+                                                           const int32_t* __restrict__ pre, int count, int step) {
+  __shared__ GemmLds g;
+  const int total = pre[count];
+  for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
+    const int m = owner(pre, count, gi);
+    const LuItem it = items[m];
+    bupd_body(it, back_block(it, step), gi - pre[m], g);
+  }
 }
 
 }  // namespace
 
-// Work area: count LuWork records, then the inverses of the upper triangles
-// of the 32 x 32 diagonal blocks of U ([count][ceil(n / 32)][32][32]).
-size_t lu_workspace_bytes(int32_t count, int32_t n) {
+// ---------------------------------------------------------------------------
+// Host side.
+
+int lu_panel_class(int n) { return n <= 512 ? 0 : n <= 1024 ? 1 : n <= 2048 ? 2 : 3; }
+
+size_t lu_work_bytes_per_matrix(int32_t n) {
   const size_t nblk = (size_t)(n + kTB - 1) / kTB;
-  return (size_t)count * (sizeof(LuWork) + nblk * kTB * kTB * sizeof(double));
+  return sizeof(LuWork) + nblk * kTB * kTB * sizeof(double);
+}
+
+size_t lu_work_header_bytes() { return sizeof(LuWork); }
+
+size_t lu_workspace_bytes(int32_t count, int32_t n) { return (size_t)count * lu_work_bytes_per_matrix(n); }
+
+int lu_plan_tiles(const LuItem& it, int kind, int step) {
+  const int n = it.n, ld = it.ld;
+  const int nsteps = (n + kOuter - 1) / kOuter;
+  if (step >= nsteps) return 0;
+  const int K0 = step * kOuter, kb = std::min(kOuter, n - K0);
+  switch (kind) {
+    case LU_PANEL0: case LU_PANEL1: case LU_PANEL2: case LU_PANEL3:
+      return it.cls == kind - LU_PANEL0 ? 1 : 0;
+    case LU_UROW: return K0 / kGT + (ld - K0 - kb + kGT - 1) / kGT;
+    case LU_UPDATE: return ((n - K0 - kb + kGT - 1) / kGT) * ((ld - K0 - kb + kGT - 1) / kGT);
+    case LU_BDIAG: return 1;
+    default: return (nsteps - 1 - step);        // LU_BUPD: row tiles above the block
+  }
+}
+
+void LuPlan::build(const std::vector<LuItem>& its) {
+  items = its;
+  count = (int32_t)its.size();
+  nsteps = 0;
+  for (const auto& it : its) nsteps = std::max(nsteps, (it.n + kOuter - 1) / kOuter);
+  pre.assign((size_t)LU_KINDS * nsteps * (count + 1), 0);
+  totals.assign((size_t)LU_KINDS * nsteps, 0);
+  for (int kind = 0; kind < LU_KINDS; ++kind)
+    for (int s = 0; s < nsteps; ++s) {
+      int32_t* p = &pre[((size_t)kind * nsteps + s) * (count + 1)];
+      p[0] = 0;
+      for (int m = 0; m < count; ++m) p[m + 1] = p[m] + lu_plan_tiles(its[m], kind, s);
+      totals[(size_t)kind * nsteps + s] = p[count];
+    }
+  d_items.upload(items);
+  d_pre.upload(pre);
+}
+
+int LuPlan::launch(hipStream_t st, int grid_cap) const {
+  const LuItem* di = d_items.ptr<LuItem>();
+  int launches = 0;
+  auto go = [&](int kind, int s, void (*kern)(const LuItem*, const int32_t*, int, int), bool capped) {
+    const int total = totals[(size_t)kind * nsteps + s];
+    if (total == 0) return;
+    const int32_t* dp = d_pre.ptr<int32_t>() + ((size_t)kind * nsteps + s) * (count + 1);
+    const int grid = capped ? std::min(total, grid_cap) : total;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, di, dp, count, s);
+    ++launches;
+  };
+  for (int s = 0; s < nsteps; ++s) {
+    go(LU_PANEL0, s, lu_panel_kernel<1, 16>, false);
+    go(LU_PANEL1, s, lu_panel_kernel<2, 16>, false);
+    go(LU_PANEL2, s, lu_panel_kernel<4, 16>, false);
+    go(LU_PANEL3, s, lu_panel_kernel<8, 8>, false);
+    go(LU_UROW, s, lu_urow_kernel, true);
+    go(LU_UPDATE, s, lu_update_kernel, true);
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    go(LU_BDIAG, s, lu_bdiag_kernel, false);
+    go(LU_BUPD, s, lu_bupd_kernel, true);
+  }
+  return launches;
 }
 
 int launch_lu_solve(const BucketTables& T, int32_t count, double* A, int64_t mat_stride,
                     int32_t* piv, int32_t* status, void* work, hipStream_t st) {
-  LuWork* w = static_cast<LuWork*>(work);
-  double* uinv = reinterpret_cast<double*>(w + count);
-  const int n = T.n;
-  if (n <= 512)
-    return launch_steps<1, 16>(T, count, A, mat_stride, piv, status, w, uinv, st);
-  else if (n <= 1024)
-    return launch_steps<2, 16>(T, count, A, mat_stride, piv, status, w, uinv, st);
-  else if (n <= 2048)
-    return launch_steps<4, 16>(T, count, A, mat_stride, piv, status, w, uinv, st);
-  else
-    return launch_steps<8, 8>(T, count, A, mat_stride, piv, status, w, uinv, st);
+  std::vector<LuItem> its(count);
+  char* w = static_cast<char*>(work);
+  const size_t per = lu_work_bytes_per_matrix(T.n);
+  for (int m = 0; m < count; ++m) {
+    LuItem& it = its[m];
+    it.A = A + (int64_t)m * mat_stride;
+    it.piv = piv + (int64_t)m * T.n;
+    it.status = status + m;
+    it.work = reinterpret_cast<LuWork*>(w + m * per);
+    it.uinv = reinterpret_cast<double*>(w + m * per + sizeof(LuWork));
+    it.n = T.n;
+    it.ld = T.ld;
+    it.nrhs = T.nrhs;
+    it.cls = lu_panel_class(T.n);
+  }
+  LuPlan plan;
+  plan.build(its);
+  const int launches = plan.launch(st, 1 << 30);
+  PDD_HIP(hipStreamSynchronize(st));     // the plan's device lists are freed on return
+  return launches;
 }
 
 }  // namespace pdd

@@ -84,6 +84,9 @@ struct DeviceCover {
   DevBuf perim_ids, perim_pos, mc_knots, bnd_knots;
   DevBuf rt_rowptr, rt_cols, rt_perm;   // transpose pattern of C (built on first use)
   bool have_transpose = false;
+  bool tuned = false;                   // schedule chosen by the autotuner for this cover
+  bool tuned_mixed = true;
+  int tuned_cap = 0;
   std::vector<std::unique_ptr<BucketData>> buckets;
   void upload(const HostCover& H);
   ChunkDesc chunk(const BucketData& b, int32_t first, int32_t count) const;
@@ -100,6 +103,21 @@ struct BucketFactors {
   DevBuf piv;                  // [count][n]
   DevBuf rowscale;             // [count][n]
   DevBuf status;               // [count]
+};
+
+// A batch of matrices (any mix of sizes) and its work lists: for each launch
+// kind and step, a prefix array over the matrices of their work units.
+struct LuPlan {
+  std::vector<LuItem> items;
+  int32_t count = 0;
+  int nsteps = 0;
+  std::vector<int32_t> pre;      // [kind][step][count + 1]
+  std::vector<int32_t> totals;   // [kind][step]
+  DevBuf d_items, d_pre;
+  void build(const std::vector<LuItem>& its);
+  // Issues the launch sequence on st; grid_cap bounds the workgroups of the
+  // tiled launches (each workgroup strides over the list).  Returns launches.
+  int launch(hipStream_t st, int grid_cap) const;
 };
 
 // Device bytes of one circle's factors in a bucket (matrix, pivots, row

@@ -103,3 +103,38 @@ def test_config2_full_size_sampled():
     circles = rng.choice(fl, size=3, replace=False)
     frac = sampled_parity(prob, ref_cover, cfg["mc"], val, b, circles, pick_mc_knots(ref_cover, rng, 3))
     assert frac > 0.99
+
+
+def test_schedules_are_bitwise_equal():
+    """Every schedule of the floating circles -- mixed-bucket or per-bucket
+    groups, persistent grids of one or two workgroups per compute unit, graph
+    replay, the autotuned choice, small factor budgets that split the work into
+    many groups -- runs the same arithmetic per circle, so C and r are
+    bitwise equal."""
+    pdd = _gpu()
+    import torch
+    _say("[gpu] schedules")
+    for cfg in (workloads.mixed_small(paths=32), workloads.small_variable(paths=32)):
+        prob = cfg["problem"]
+        cv = pdd.Cover(prob["domain"], cfg["cover"])
+        ref = pdd.System(cv, prob, cfg["mc"])
+        rv = ref.copy()
+        keep = pdd.System(cv, prob, cfg["mc"], keep_factors=True)
+        per = keep.stats.factor_bytes // cv.info.n_float
+        variants = [
+            dict(mixed_buckets=False),
+            dict(grid_cap=1),
+            dict(grid_cap=2, use_graph=True),
+            dict(hbm_budget_bytes=int(1.5 * per), use_graph=True),
+            dict(hbm_budget_bytes=int(1.5 * per), mixed_buckets=False, use_graph=True),
+            dict(plan="autotuned"),
+            dict(plan="autotuned", use_graph=True),
+        ]
+        for kw in variants:
+            s = pdd.System(cv, prob, cfg["mc"], **kw)
+            for a, b in zip(rv, s.copy()):
+                assert torch.equal(a, b), (cfg["name"], kw)
+            _say(f"[gpu] {cfg['name']} {kw}: groups {s.stats.n_groups}, graph replays {s.stats.graph_replays}, "
+                 f"mixed {s.stats.mixed_buckets}, cap {s.stats.grid_cap}")
+            if kw.get("hbm_budget_bytes") and cfg["name"] == "small_variable":
+                assert s.stats.n_groups > 1 and s.stats.graph_replays > 0
