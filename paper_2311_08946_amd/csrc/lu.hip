@@ -591,18 +591,26 @@ template <int ROWS, int NB>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void lu_panel_kernel(
     const LuItem* __restrict__ items, const int32_t* __restrict__ pre, int count, int step) {
   __shared__ PanelShared<NB> sh;
-  const int total = pre[count];
-  for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
-    panel_body<ROWS, NB>(items[owner(pre, count, gi)], step * kOuter, sh);
-    __syncthreads();
-  }
+  const int gi = blockIdx.x;                 // one workgroup per matrix
+  if (gi >= pre[count]) return;
+  panel_body<ROWS, NB>(items[owner(pre, count, gi)], step * kOuter, sh);
 }
 
+// PERSISTENT: each workgroup strides over the list; otherwise one workgroup
+// per work unit (no loop, fewer live registers).
+template <bool PERSISTENT>
 __global__ __launch_bounds__(kThreads) void lu_urow_kernel(const LuItem* __restrict__ items,
                                                            const int32_t* __restrict__ pre, int count, int step) {
   __shared__ MatLds u;
   __shared__ PermLds perm;
   const int total = pre[count];
+  if (!PERSISTENT) {
+    const int gi = blockIdx.x;
+    if (gi >= total) return;
+    const int m = owner(pre, count, gi);
+    urow_body(items[m], step * kOuter, gi - pre[m], u, perm);
+    return;
+  }
   for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
     const int m = owner(pre, count, gi);
     urow_body(items[m], step * kOuter, gi - pre[m], u, perm);
@@ -610,10 +618,18 @@ __global__ __launch_bounds__(kThreads) void lu_urow_kernel(const LuItem* __restr
   }
 }
 
+template <bool PERSISTENT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void lu_update_kernel(
     const LuItem* __restrict__ items, const int32_t* __restrict__ pre, int count, int step) {
   __shared__ GemmLds g;
   const int total = pre[count];
+  if (!PERSISTENT) {
+    const int gi = blockIdx.x;
+    if (gi >= total) return;
+    const int m = owner(pre, count, gi);
+    update_body(items[m], step * kOuter, gi - pre[m], g);
+    return;
+  }
   for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
     const int m = owner(pre, count, gi);
     update_body(items[m], step * kOuter, gi - pre[m], g);
@@ -623,18 +639,25 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
 __global__ __launch_bounds__(kThreads) void lu_bdiag_kernel(const LuItem* __restrict__ items,
                                                             const int32_t* __restrict__ pre, int count, int step) {
   __shared__ MatLds u;
-  const int total = pre[count];
-  for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
-    const LuItem it = items[owner(pre, count, gi)];
-    bdiag_body(it, back_block(it, step), u);
-    __syncthreads();
-  }
+  const int gi = blockIdx.x;                 // one workgroup per matrix
+  if (gi >= pre[count]) return;
+  const LuItem it = items[owner(pre, count, gi)];
+  bdiag_body(it, back_block(it, step), u);
 }
 
+template <bool PERSISTENT>
 __global__ __launch_bounds__(kThreads) void lu_bupd_kernel(const LuItem* __restrict__ items,
                                                            const int32_t* __restrict__ pre, int count, int step) {
   __shared__ GemmLds g;
   const int total = pre[count];
+  if (!PERSISTENT) {
+    const int gi = blockIdx.x;
+    if (gi >= total) return;
+    const int m = owner(pre, count, gi);
+    const LuItem it = items[m];
+    bupd_body(it, back_block(it, step), gi - pre[m], g);
+    return;
+  }
   for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
     const int m = owner(pre, count, gi);
     const LuItem it = items[m];
@@ -694,25 +717,29 @@ void LuPlan::build(const std::vector<LuItem>& its) {
 int LuPlan::launch(hipStream_t st, int grid_cap) const {
   const LuItem* di = d_items.ptr<LuItem>();
   int launches = 0;
-  auto go = [&](int kind, int s, void (*kern)(const LuItem*, const int32_t*, int, int), bool capped) {
+  typedef void (*Kern)(const LuItem*, const int32_t*, int, int);
+  // flat: one workgroup per unit; strided: a capped persistent grid
+  auto go = [&](int kind, int s, Kern flat, Kern strided) {
     const int total = totals[(size_t)kind * nsteps + s];
     if (total == 0) return;
     const int32_t* dp = d_pre.ptr<int32_t>() + ((size_t)kind * nsteps + s) * (count + 1);
-    const int grid = capped ? std::min(total, grid_cap) : total;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, di, dp, count, s);
+    if (strided && grid_cap < total)
+      hipLaunchKernelGGL(strided, dim3(grid_cap), dim3(kThreads), 0, st, di, dp, count, s);
+    else
+      hipLaunchKernelGGL(flat, dim3(total), dim3(kThreads), 0, st, di, dp, count, s);
     ++launches;
   };
   for (int s = 0; s < nsteps; ++s) {
-    go(LU_PANEL0, s, lu_panel_kernel<1, 16>, false);
-    go(LU_PANEL1, s, lu_panel_kernel<2, 16>, false);
-    go(LU_PANEL2, s, lu_panel_kernel<4, 16>, false);
-    go(LU_PANEL3, s, lu_panel_kernel<8, 8>, false);
-    go(LU_UROW, s, lu_urow_kernel, true);
-    go(LU_UPDATE, s, lu_update_kernel, true);
+    go(LU_PANEL0, s, lu_panel_kernel<1, 16>, nullptr);
+    go(LU_PANEL1, s, lu_panel_kernel<2, 16>, nullptr);
+    go(LU_PANEL2, s, lu_panel_kernel<4, 16>, nullptr);
+    go(LU_PANEL3, s, lu_panel_kernel<8, 8>, nullptr);
+    go(LU_UROW, s, lu_urow_kernel<false>, lu_urow_kernel<true>);
+    go(LU_UPDATE, s, lu_update_kernel<false>, lu_update_kernel<true>);
   }
   for (int s = 0; s < nsteps; ++s) {
-    go(LU_BDIAG, s, lu_bdiag_kernel, false);
-    go(LU_BUPD, s, lu_bupd_kernel, true);
+    go(LU_BDIAG, s, lu_bdiag_kernel, nullptr);
+    go(LU_BUPD, s, lu_bupd_kernel<false>, lu_bupd_kernel<true>);
   }
   return launches;
 }
