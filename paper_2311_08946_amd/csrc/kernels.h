@@ -60,7 +60,7 @@ struct LuItem {                // one matrix of a batch (device pointers)
   int32_t n, ld, nrhs, cls;    // cls = lu_panel_class(n)
 };
 // launch kinds: the panel kernel per size class, then the tiled kinds
-enum { LU_PANEL0, LU_PANEL1, LU_PANEL2, LU_PANEL3, LU_UROW, LU_UPDATE, LU_BDIAG, LU_BUPD, LU_KINDS };
+enum { LU_PUPD, LU_PANEL0, LU_PANEL1, LU_PANEL2, LU_PANEL3, LU_LSWAP, LU_UROW, LU_BDIAG, LU_BUPD, LU_KINDS };
 int lu_panel_class(int n);
 size_t lu_work_bytes_per_matrix(int32_t n);
 size_t lu_work_header_bytes();   // sizeof(LuWork): the inverses of U's blocks follow

@@ -3,22 +3,27 @@
 // one QR factorisation per circle, here LU with partial pivoting).
 //
 // Each matrix is the augmented array [A_II | R] (n x ld, row-major, R in
-// columns n .. n + nrhs).  Right-looking blocked factorisation in steps of
-// kOuter = 128 columns, three launches per step over the whole batch:
+// columns n .. n + nrhs).  Blocked factorisation in steps of kOuter = 128
+// columns, left-looking (Crout order: the trailing matrix is never updated as
+// a whole; each block is brought up to date with one long-K product when it
+// is reached), four launches per step over the whole batch:
+//   * lu_pupd_kernel (one workgroup per matrix and 128-row tile of the
+//     panel): A[K0:n, K0:K0+128] -= L[K0:n, 0:K0] U[0:K0, K0:K0+128];
 //   * lu_panel_kernel (one workgroup per matrix): factorises the step's panel
-//     A[K0:n, K0:K0+128] by sub-panels of NB columns held in registers
-//     (thread t owns rows k0 + t + 512 s), column by column with a
-//     workgroup-wide pivot search, each followed by its interchanges, its
-//     block row of U and the update of the rest of the panel; it then stores
-//     the step's composed row permutation and the inverses of the 32 x 32
-//     unit-lower diagonal blocks of L11 in a per-matrix work area;
-//   * lu_urow_kernel (one workgroup per matrix and 128-column tile outside
-//     the panel): applies the step's interchanges to the tile and, right of
-//     the panel, forms the tile of U12 = L11^-1 A12 by 32-row blocks (the
-//     stored inverse on MFMA, then an MFMA update of the rows below);
-//   * lu_update_kernel (one workgroup per matrix and 128 x 128 trailing tile):
-//     A22 -= L21 U12 with K = 128 -- the right-hand-side columns are part of
-//     the trailing matrix and are thereby eliminated forward.
+//     by sub-panels of NB columns held in registers (thread t owns rows
+//     k0 + t + 512 s), column by column with a workgroup-wide pivot search,
+//     each followed by its interchanges, its block row of U and the update of
+//     the rest of the panel; it then stores the step's composed row
+//     permutation and the inverses of the 32 x 32 diagonal blocks of L11 and
+//     U11 in a per-matrix work area;
+//   * lu_urow_kernel<LEFT> (one workgroup per matrix and 128-column tile
+//     left of the panel): applies the step's interchanges to L;
+//   * lu_urow_kernel (one workgroup per matrix and 128-column tile right of
+//     the panel): applies the step's interchanges to the tile, brings rows
+//     [K0, K0 + kb) up to date with one long-K product and forms
+//     U12 = L11^-1 A12 by 32-row blocks (the stored inverses on MFMA, then
+//     MFMA updates of the rows below) -- the right-hand-side columns are
+//     among these tiles and are thereby eliminated forward.
 // The back substitution U W = R' then runs from the bottom in 128-row blocks:
 // lu_bdiag_kernel solves a diagonal block (32-row triangles through the
 // inverses of U's diagonal blocks, stored by the panel kernel, and MFMA
@@ -499,9 +504,13 @@ __device__ __attribute__((always_inline)) void panel_body(const LuItem& it, int 
   if (tid == 0 && (K0 == 0 || singular)) *it.status = singular;
 }
 
-// Tile t of the step's U-row work: left tiles (columns < K0) only take the
-// interchanges; right tiles (columns >= K0 + kb, right-hand sides included)
-// then become rows [K0, K0 + kb) of U.
+// Tile t of the step's U-row work.  LEFT: columns [128 t, ..) < K0 of L only
+// take the step's interchanges.  Otherwise: columns K0 + kb + 128 t .. (the
+// right-hand sides included) take the interchanges, are brought up to date
+// with the long-K product against rows [K0, K0 + kb) of L -- which must
+// already carry this step's interchanges, so the left tiles run in an earlier
+// launch -- and become rows [K0, K0 + kb) of U.
+template <bool LEFT>
 __device__ __attribute__((always_inline)) void urow_body(const LuItem& it, int K0, int t, MatLds& u,
                                                           PermLds& perm) {
   double* A = it.A;
@@ -509,10 +518,8 @@ __device__ __attribute__((always_inline)) void urow_body(const LuItem& it, int K
   const LuWork* W = it.work;
   const int tid = threadIdx.x;
   const int kb = min(kOuter, n - K0);
-  const int nleft = K0 / kGT;
-  const bool right = t >= nleft;
-  const int c0 = right ? K0 + kb + (t - nleft) * kGT : t * kGT;
-  const int c1 = min(right ? ld : K0, c0 + kGT);
+  const int c0 = LEFT ? t * kGT : K0 + kb + t * kGT;
+  const int c1 = min(LEFT ? K0 : ld, c0 + kGT);
   if (tid == 0) perm.count = W->count;
   for (int e = tid; e < 2 * kOuter; e += kThreads) {
     perm.rows[e] = W->rows[e];
@@ -520,7 +527,10 @@ __device__ __attribute__((always_inline)) void urow_body(const LuItem& it, int K
   }
   __syncthreads();
   apply_perm(A, ld, perm, c0, c1, 0, 0, &u.g.Lt[0][0]);
-  if (!right) return;
+  if (LEFT) return;
+  // the contributions of all earlier steps to these rows (left-looking: the
+  // trailing matrix is never updated as a whole)
+  if (K0 > 0) gemm_sub(A, ld, K0, K0 + kb, c0, c1, 0, K0, u.g);
   for (int b = 0; b * kTB < kb; ++b) {
     const int a = K0 + b * kTB, w = min(kTB, kb - b * kTB);
     for (int idx = tid; idx < kTB * kTB; idx += kThreads) u.t.inv[idx >> 5][idx & 31] = W->inv[b][idx >> 5][idx & 31];
@@ -530,15 +540,13 @@ __device__ __attribute__((always_inline)) void urow_body(const LuItem& it, int K
   }
 }
 
-// Tile t (row-major over the trailing tiles) of A22 -= L21 U12.
-__device__ __attribute__((always_inline)) void update_body(const LuItem& it, int K0, int t, GemmLds& g) {
-  const int n = it.n, ld = it.ld;
+// Row tile t of the step's panel: the contributions of all earlier steps,
+// A[K0 + 128 t .., K0 : K0 + kb] -= L[.., 0 : K0] U[0 : K0, K0 : K0 + kb].
+__device__ __attribute__((always_inline)) void pupd_body(const LuItem& it, int K0, int t, GemmLds& g) {
+  const int n = it.n;
   const int kb = min(kOuter, n - K0);
-  const int r0 = K0 + kb;
-  const int ct = (ld - r0 + kGT - 1) / kGT;
-  const int i = t / ct, j = t - i * ct;
-  const int ra = r0 + i * kGT, ca = r0 + j * kGT;
-  gemm_sub(it.A, ld, ra, min(n, ra + kGT), ca, min(ld, ca + kGT), K0, K0 + kb, g);
+  const int ra = K0 + t * kGT;
+  gemm_sub(it.A, it.ld, ra, min(n, ra + kGT), K0, K0 + kb, 0, K0, g);
 }
 
 // Back substitution U W = R' on columns [n, n + nrhs), right-looking from the
@@ -583,6 +591,16 @@ __device__ __forceinline__ int owner(const int32_t* __restrict__ pre, int count,
   return lo;
 }
 
+// Work index of this workgroup in a flat launch.  Workgroups are dispatched
+// to the 8 XCDs round-robin (workgroup b runs on XCD b mod 8), each with its
+// own L2; the launch grid is padded to a multiple of 8 and XCD x takes the
+// contiguous index range [x T8, (x + 1) T8), T8 = grid / 8, so the tiles of one
+// matrix -- which share their L21 and U12 operands -- meet in one L2.
+__device__ __forceinline__ int xcd_index() {
+  const int t8 = (int)gridDim.x >> 3;
+  return ((int)blockIdx.x & 7) * t8 + ((int)blockIdx.x >> 3);
+}
+
 __device__ __forceinline__ int back_block(const LuItem& it, int step) {
   return ((it.n + kOuter - 1) / kOuter - 1 - step) * kOuter;
 }
@@ -598,41 +616,41 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
 
 // PERSISTENT: each workgroup strides over the list; otherwise one workgroup
 // per work unit (no loop, fewer live registers).
-template <bool PERSISTENT>
+template <bool PERSISTENT, bool LEFT>
 __global__ __launch_bounds__(kThreads) void lu_urow_kernel(const LuItem* __restrict__ items,
                                                            const int32_t* __restrict__ pre, int count, int step) {
   __shared__ MatLds u;
   __shared__ PermLds perm;
   const int total = pre[count];
   if (!PERSISTENT) {
-    const int gi = blockIdx.x;
+    const int gi = xcd_index();
     if (gi >= total) return;
     const int m = owner(pre, count, gi);
-    urow_body(items[m], step * kOuter, gi - pre[m], u, perm);
+    urow_body<LEFT>(items[m], step * kOuter, gi - pre[m], u, perm);
     return;
   }
   for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
     const int m = owner(pre, count, gi);
-    urow_body(items[m], step * kOuter, gi - pre[m], u, perm);
+    urow_body<LEFT>(items[m], step * kOuter, gi - pre[m], u, perm);
     __syncthreads();
   }
 }
 
 template <bool PERSISTENT>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void lu_update_kernel(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void lu_pupd_kernel(
     const LuItem* __restrict__ items, const int32_t* __restrict__ pre, int count, int step) {
   __shared__ GemmLds g;
   const int total = pre[count];
   if (!PERSISTENT) {
-    const int gi = blockIdx.x;
+    const int gi = xcd_index();
     if (gi >= total) return;
     const int m = owner(pre, count, gi);
-    update_body(items[m], step * kOuter, gi - pre[m], g);
+    pupd_body(items[m], step * kOuter, gi - pre[m], g);
     return;
   }
   for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
     const int m = owner(pre, count, gi);
-    update_body(items[m], step * kOuter, gi - pre[m], g);
+    pupd_body(items[m], step * kOuter, gi - pre[m], g);
   }
 }
 
@@ -651,7 +669,7 @@ __global__ __launch_bounds__(kThreads) void lu_bupd_kernel(const LuItem* __restr
   __shared__ GemmLds g;
   const int total = pre[count];
   if (!PERSISTENT) {
-    const int gi = blockIdx.x;
+    const int gi = xcd_index();
     if (gi >= total) return;
     const int m = owner(pre, count, gi);
     const LuItem it = items[m];
@@ -689,8 +707,9 @@ int lu_plan_tiles(const LuItem& it, int kind, int step) {
   switch (kind) {
     case LU_PANEL0: case LU_PANEL1: case LU_PANEL2: case LU_PANEL3:
       return it.cls == kind - LU_PANEL0 ? 1 : 0;
-    case LU_UROW: return K0 / kGT + (ld - K0 - kb + kGT - 1) / kGT;
-    case LU_UPDATE: return ((n - K0 - kb + kGT - 1) / kGT) * ((ld - K0 - kb + kGT - 1) / kGT);
+    case LU_LSWAP: return K0 / kGT;
+    case LU_UROW: return (ld - K0 - kb + kGT - 1) / kGT;
+    case LU_PUPD: return K0 > 0 ? (n - K0 + kGT - 1) / kGT : 0;
     case LU_BDIAG: return 1;
     default: return (nsteps - 1 - step);        // LU_BUPD: row tiles above the block
   }
@@ -725,17 +744,20 @@ int LuPlan::launch(hipStream_t st, int grid_cap) const {
     const int32_t* dp = d_pre.ptr<int32_t>() + ((size_t)kind * nsteps + s) * (count + 1);
     if (strided && grid_cap < total)
       hipLaunchKernelGGL(strided, dim3(grid_cap), dim3(kThreads), 0, st, di, dp, count, s);
+    else if (strided)   // flat tiled launch: grid padded to a multiple of the 8 XCDs
+      hipLaunchKernelGGL(flat, dim3((total + 7) / 8 * 8), dim3(kThreads), 0, st, di, dp, count, s);
     else
       hipLaunchKernelGGL(flat, dim3(total), dim3(kThreads), 0, st, di, dp, count, s);
     ++launches;
   };
   for (int s = 0; s < nsteps; ++s) {
+    go(LU_PUPD, s, lu_pupd_kernel<false>, lu_pupd_kernel<true>);
     go(LU_PANEL0, s, lu_panel_kernel<1, 16>, nullptr);
     go(LU_PANEL1, s, lu_panel_kernel<2, 16>, nullptr);
     go(LU_PANEL2, s, lu_panel_kernel<4, 16>, nullptr);
     go(LU_PANEL3, s, lu_panel_kernel<8, 8>, nullptr);
-    go(LU_UROW, s, lu_urow_kernel<false>, lu_urow_kernel<true>);
-    go(LU_UPDATE, s, lu_update_kernel<false>, lu_update_kernel<true>);
+    go(LU_LSWAP, s, lu_urow_kernel<false, true>, lu_urow_kernel<true, true>);
+    go(LU_UROW, s, lu_urow_kernel<false, false>, lu_urow_kernel<true, false>);
   }
   for (int s = 0; s < nsteps; ++s) {
     go(LU_BDIAG, s, lu_bdiag_kernel, nullptr);
