@@ -63,23 +63,39 @@ void launch_sample_nodes(const DevProblem* P, const BucketTables& T, const Chunk
 //   a_xx/2 u_xx + a_xy u_xy + a_yy/2 u_yy + b_x u_x + b_y u_y + c u
 // at radius rho = x_jr, angle theta_l, on a circle of radius r, with
 // derivatives taken on the full diameter grid and folded onto the unknowns by
-// u(-rho, theta) = u(rho, theta + pi).
+// u(-rho, theta) = u(rho, theta + pi).  The row is assembled once in LDS (the
+// wavefront's own slice) and then scaled and written with coalesced stores.
+// Without the mixed term (a_xy = 0 and a_xx = a_yy, so u_rho_theta drops out)
+// only the radial line (angle theta_l and its opposite) and the angular ring
+// (radius x_jr) are non-zero: 2 Nr + Ntheta entries instead of n.
+namespace {
+constexpr int kBuildWaves = 4;
+
+// Orders the wavefront's LDS writes before its later LDS reads by other lanes.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+}  // namespace
+
 __global__ __launch_bounds__(256) void colloc_build_kernel(BucketTables T, ChunkDesc C,
                                                            NodeSamples S, double* __restrict__ A,
                                                            int64_t stride,
                                                            double* __restrict__ rowscale) {
-  extern __shared__ double s_ring[];          // [4][Nt] scaled A_IB rows
+  extern __shared__ double s_build[];          // per wavefront: row [n], ring [Nt]
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int n = T.n, Nt = T.Nt, Nc = T.Nc, M = T.M, ld = T.ld;
+  const int n = T.n, Nt = T.Nt, Nc = T.Nc, Nr = T.Nr, M = T.M, ld = T.ld;
+  double* s_row = s_build + (int64_t)w * (n + Nt);
+  double* s_ring = s_row + n;
   const int ci = blockIdx.y;
   const int f = C.fl[ci];
   const int m = C.float_ids[f];
-  const int q = blockIdx.x * 4 + w;
-  const bool active = q < n;
-  const int qq = active ? q : 0;
-  const int jr = qq / Nt + 1;
-  const int l = qq - (jr - 1) * Nt;
-  const int64_t node = C.node_off[f] + qq;
+  const int q = blockIdx.x * kBuildWaves + w;
+  if (q >= n) return;                          // no workgroup barrier below
+  const int jr = q / Nt + 1;
+  const int l = q - (jr - 1) * Nt;
+  const int64_t node = C.node_off[f] + q;
   const double axx = S.s[0][node], axy = S.s[1][node], ayy = S.s[2][node];
   const double bx = S.s[3][node], by = S.s[4][node], cc = S.s[5][node], ff = S.s[6][node];
   const double r = C.rad[m];
@@ -92,65 +108,91 @@ __global__ __launch_bounds__(256) void colloc_build_kernel(BucketTables T, Chunk
   const double ang = 0.5 * axx * ss - axy * sc + 0.5 * ayy * cc2;
   const double c_r = ang / (rho * r2) + (bx * cth + by * sth) / r;
   const double c_tt = ang / (rho * rho * r2);
-  const double c_rt = (-axx * sc + axy * c2s2 + ayy * sc) / (rho * r2);
+  const bool mixed = !(axy == 0.0 && axx == ayy);
+  const double c_rt = mixed ? (-axx * sc + axy * c2s2 + ayy * sc) / (rho * r2) : 0.0;
   const double c_t = (axx * sc - axy * c2s2 - ayy * sc) / (rho * rho * r2) +
                      (-bx * sth + by * cth) / (rho * r);
   const double* Drow = T.Dr + (int64_t)(jr - 1) * (Nc + 1);
   const double* D2row = T.D2r + (int64_t)(jr - 1) * (Nc + 1);
   const int half = Nt / 2;
 
-  // full-grid operator entry at radial index j, angular index lp
-  auto entry = [&](int j, int lp) -> double {
-    int dl = l - lp;
-    if (dl < 0) dl += Nt;
-    const double dj = Drow[j];
-    double v = c_rt * dj * T.d1t[dl];
-    if (lp == l) v += c_rr * D2row[j] + c_r * dj;
-    if (j == jr) v += c_tt * T.d2t[dl] + c_t * T.d1t[dl];
-    return v;
-  };
-  auto interior = [&](int col) -> double {
-    const int k = col / Nt + 1;
-    const int lp = col - (k - 1) * Nt;
-    int lq = lp - half;
-    if (lq < 0) lq += Nt;
-    double v = entry(k, lp) + entry(Nc - k, lq);
-    if (col == qq) v += cc;
-    return v;
-  };
-  auto ring = [&](int lp) -> double {
-    int lq = lp - half;
-    if (lq < 0) lq += Nt;
-    return entry(0, lp) + entry(Nc, lq);
-  };
-
+  if (mixed) {
+    // dense: every full-grid entry, folded
+    auto entry = [&](int j, int lp) -> double {
+      int dl = l - lp;
+      if (dl < 0) dl += Nt;
+      const double dj = Drow[j];
+      double v = c_rt * dj * T.d1t[dl];
+      if (lp == l) v += c_rr * D2row[j] + c_r * dj;
+      if (j == jr) v += c_tt * T.d2t[dl] + c_t * T.d1t[dl];
+      return v;
+    };
+    for (int col = lane; col < n; col += kWave) {
+      const int k = col / Nt + 1;
+      const int lp = col - (k - 1) * Nt;
+      int lq = lp - half;
+      if (lq < 0) lq += Nt;
+      s_row[col] = entry(k, lp) + entry(Nc - k, lq);
+    }
+    for (int lp = lane; lp < Nt; lp += kWave) {
+      int lq = lp - half;
+      if (lq < 0) lq += Nt;
+      s_ring[lp] = entry(0, lp) + entry(Nc, lq);
+    }
+  } else {
+    for (int col = lane; col < n; col += kWave) s_row[col] = 0.0;
+    for (int lp = lane; lp < Nt; lp += kWave) s_ring[lp] = 0.0;
+    wave_sync();
+    // radial line: full-grid index j at angle theta_l; j in [1, Nr] is the
+    // interior node (j, l), j in [Nr + 1, Nc - 1] folds to (Nc - j, l + half),
+    // j = 0 and j = Nc are the ring at l and l + half
+    const int lh = (l + half) % Nt;
+    for (int j = lane; j <= Nc; j += kWave) {
+      const double v = c_rr * D2row[j] + c_r * Drow[j];
+      if (j == 0) s_ring[l] += v;
+      else if (j == Nc) s_ring[lh] += v;
+      else if (j <= Nr) s_row[(j - 1) * Nt + l] += v;
+      else s_row[(Nc - j - 1) * Nt + lh] += v;
+    }
+    wave_sync();
+    // angular ring at radius x_jr (interior row jr only)
+    for (int lp = lane; lp < Nt; lp += kWave) {
+      int dl = l - lp;
+      if (dl < 0) dl += Nt;
+      s_row[(jr - 1) * Nt + lp] += c_tt * T.d2t[dl] + c_t * T.d1t[dl];
+    }
+  }
+  wave_sync();
+  if (lane == 0) s_row[q] += cc;
+  wave_sync();
   double mx = 0.0;
-  for (int col = lane; col < n; col += kWave) mx = fmax(mx, fabs(interior(col)));
+  for (int col = lane; col < n; col += kWave) mx = fmax(mx, fabs(s_row[col]));
   mx = wave_max(mx);
   const double scale = 1.0 / mx;
-  double* row = A + (int64_t)ci * stride + (int64_t)qq * ld;
-  if (active) {
-    if (lane == 0) rowscale[(int64_t)ci * n + q] = scale;
-    for (int col = lane; col < n; col += kWave) row[col] = scale * interior(col);
-    for (int lp = lane; lp < Nt; lp += kWave) s_ring[w * Nt + lp] = scale * ring(lp);
+  double* row = A + (int64_t)ci * stride + (int64_t)q * ld;
+  if (lane == 0) rowscale[(int64_t)ci * n + q] = scale;
+  for (int col = 2 * lane; col < n; col += 2 * kWave) {     // n is even
+    double2 v;
+    v.x = scale * s_row[col];
+    v.y = scale * s_row[col + 1];
+    *reinterpret_cast<double2*>(row + col) = v;
   }
-  __syncthreads();
-  if (active) {
-    for (int j = lane; j < M; j += kWave) {
-      double v = 0.0;
-      for (int lp = 0; lp < Nt; ++lp) v += s_ring[w * Nt + lp] * T.H[(int64_t)lp * M + j];
-      row[n + j] = v;
-    }
-    if (lane == 0) row[n + M] = -scale * ff;
-    for (int col = n + M + 1 + lane; col < ld; col += kWave) row[col] = 0.0;
+  for (int j = lane; j < M; j += kWave) {
+    double v = 0.0;
+    for (int lp = 0; lp < Nt; ++lp) v += s_ring[lp] * T.H[(int64_t)lp * M + j];
+    row[n + j] = scale * v;
   }
+  if (lane == 0) row[n + M] = -scale * ff;
+  for (int col = n + M + 1 + lane; col < ld; col += kWave) row[col] = 0.0;
 }
 
 void launch_colloc_build(const BucketTables& T, const ChunkDesc& C, const NodeSamples& S,
                          double* A, int64_t mat_stride, double* rowscale, hipStream_t st) {
-  dim3 grid((T.n + 3) / 4, C.count);
-  size_t shm = sizeof(double) * 4 * T.Nt;
-  hipLaunchKernelGGL(colloc_build_kernel, grid, dim3(256), shm, st, T, C, S, A, mat_stride,
+  dim3 grid((T.n + kBuildWaves - 1) / kBuildWaves, C.count);
+  size_t shm = sizeof(double) * kBuildWaves * (size_t)(T.n + T.Nt);
+  (void)hipFuncSetAttribute((const void*)colloc_build_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shm);
+  hipLaunchKernelGGL(colloc_build_kernel, grid, dim3(64 * kBuildWaves), shm, st, T, C, S, A, mat_stride,
                      rowscale);
 }
 
