@@ -37,6 +37,7 @@ struct AdjArgs {
 };
 
 // Dynamic LDS layout (doubles): y[n] | wI[n] | wB[Nt] | uX[M] | G[(Nc+1) Nt] | lx[32][Nc+1] | lt[32][Nt]
+//                               | blk[32][33]
 __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(AdjArgs a) {
   extern __shared__ double sh[];
   const BucketTables& T = a.T;
@@ -56,6 +57,7 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(AdjArgs a) {
   double* G = uX + M;
   double* lx = G + (int64_t)Nc1 * Nt;
   double* lt = lx + kAdjKnots * Nc1;
+  double* blk = lt + kAdjKnots * Nt;          // [kTri][kTri + 1] diagonal block
 
   // ---- y = E^T lambda over the assigned knots
   for (int q = tid; q < n; q += kAdjThreads) y[q] = 0.0;
@@ -102,16 +104,22 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(AdjArgs a) {
   }
   __syncthreads();
 
-  // ---- U^T z = y (forward, 32-row blocks: wave 0 solves the diagonal block,
-  //      then all threads update the remaining entries from the block's rows)
+  // ---- U^T z = y (forward, 32-row blocks: the diagonal block is staged in
+  //      LDS, wave 0 solves it, then all threads update the remaining entries
+  //      from the block's rows)
   for (int j0 = 0; j0 < n; j0 += kTri) {
     const int j1 = min(n, j0 + kTri);
+    for (int idx = tid; idx < kTri * kTri; idx += kAdjThreads) {
+      const int i = idx / kTri, j = idx - i * kTri;
+      blk[i * (kTri + 1) + j] = (j0 + i < j1 && j0 + j < j1) ? A[(int64_t)(j0 + i) * ld + j0 + j] : 0.0;
+    }
+    __syncthreads();
     if (w == 0) {
       double yi = (j0 + lane < j1) ? y[j0 + lane] : 0.0;
       for (int j = j0; j < j1; ++j) {
-        const double zj = __shfl(yi, j - j0, 64) / A[(int64_t)j * ld + j];
+        const double zj = __shfl(yi, j - j0, 64) / blk[(j - j0) * (kTri + 1) + (j - j0)];
         if (lane == j - j0) yi = zj;
-        else if (j0 + lane > j && j0 + lane < j1) yi -= A[(int64_t)j * ld + j0 + lane] * zj;
+        else if (j0 + lane > j && j0 + lane < j1) yi -= blk[(j - j0) * (kTri + 1) + lane] * zj;
       }
       if (j0 + lane < j1) y[j0 + lane] = yi;
     }
@@ -123,14 +131,19 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(AdjArgs a) {
     }
     __syncthreads();
   }
-  // ---- L^T x = z (backward, unit diagonal)
+  // ---- L^T x = z (backward, unit diagonal, same blocking)
   for (int j1 = n; j1 > 0; j1 -= kTri) {
     const int j0 = max(0, j1 - kTri);
+    for (int idx = tid; idx < kTri * kTri; idx += kAdjThreads) {
+      const int i = idx / kTri, j = idx - i * kTri;
+      blk[i * (kTri + 1) + j] = (j0 + i < j1 && j0 + j < j1) ? A[(int64_t)(j0 + i) * ld + j0 + j] : 0.0;
+    }
+    __syncthreads();
     if (w == 0) {
       double yi = (j0 + lane < j1) ? y[j0 + lane] : 0.0;
       for (int j = j1 - 1; j >= j0; --j) {
         const double xj = __shfl(yi, j - j0, 64);
-        if (j0 + lane < j) yi -= A[(int64_t)j * ld + j0 + lane] * xj;
+        if (j0 + lane < j) yi -= blk[(j - j0) * (kTri + 1) + lane] * xj;
       }
       if (j0 + lane < j1) y[j0 + lane] = yi;
     }
@@ -255,8 +268,9 @@ pdd_status backward_impl(pdd_system sys, const double* u, const double* lambda, 
     a.lambda = lambda;
     for (int k = 0; k < 7; ++k) a.g[k] = g[k];
     const size_t shm = sizeof(double) * ((size_t)2 * bk.n + bk.Nt + bk.M + (size_t)(bk.Nc + 1) * bk.Nt +
-                                         (size_t)kAdjKnots * (bk.Nc + 1 + bk.Nt));
+                                         (size_t)kAdjKnots * (bk.Nc + 1 + bk.Nt) + (size_t)kTri * (kTri + 1));
     if (shm > 160 * 1024) return fail(PDD_EINVAL, "pdd_assemble_G_backward: bucket too large");
+    (void)hipFuncSetAttribute((const void*)adjoint_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL(adjoint_kernel, dim3(F.count), dim3(kAdjThreads), shm, st, a);
     PDD_HIP(hipGetLastError());
     return PDD_OK;
