@@ -313,9 +313,24 @@ pdd_status solve_impl(pdd_system sys, const double* rhs, double* u, int32_t tran
   const dim3 rb(c.nblocks), vb(c.vblocks);
   hipLaunchKernelGGL(init_kernel, rb, dim3(kThreads), 0, st, c, b, guess ? 1 : 0);
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, st, c, c.nblocks, 0, rtol);
-  double host[S_COUNT];
-  int enq = 0;
-  for (;;) {
+  // Batches of kItersPerSync iterations; the convergence record of batch k is
+  // copied to pinned host memory and read while batch k + 1 already runs (the
+  // iteration kernels return at once after convergence, so a batch enqueued
+  // past it does nothing).
+  struct Pinned {
+    double* p = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    ~Pinned() {
+      if (p) (void)hipHostFree(p);
+      for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    }
+  } pin;
+  PDD_HIP(hipHostMalloc(&pin.p, 2 * S_COUNT * sizeof(double), hipHostMallocDefault));
+  for (int k = 0; k < 2 * S_COUNT; ++k) pin.p[k] = 0.0;
+  for (auto& e : pin.ev) PDD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  int enq = 0, slot = 0;
+  auto enqueue_batch = [&](int sl) {
     const int batch = std::min(kItersPerSync, max_iter - enq);
     for (int k = 0; k < batch; ++k) {
       hipLaunchKernelGGL(update_p_kernel, vb, dim3(kThreads), 0, st, c);
@@ -328,9 +343,28 @@ pdd_status solve_impl(pdd_system sys, const double* rhs, double* u, int32_t tran
     }
     enq += batch;
     PDD_HIP(hipGetLastError());
-    PDD_HIP(hipMemcpyAsync(host, c.sc, sizeof(host), hipMemcpyDeviceToHost, st));
-    PDD_HIP(hipStreamSynchronize(st));
-    if (host[S_DONE] != 0.0 || enq >= max_iter) break;
+    PDD_HIP(hipMemcpyAsync(pin.p + sl * S_COUNT, c.sc, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
+    PDD_HIP(hipEventRecord(pin.ev[sl], st));
+  };
+  enqueue_batch(slot);
+  for (;;) {
+    const bool more = enq < max_iter;
+    if (more) enqueue_batch(slot ^ 1);
+    PDD_HIP(hipEventSynchronize(pin.ev[slot]));
+    const double* h = pin.p + slot * S_COUNT;
+    if (h[S_DONE] != 0.0 || !more) break;
+    slot ^= 1;
+  }
+  PDD_HIP(hipStreamSynchronize(st));
+  // both slots now hold completed records; the more recent one (more
+  // iterations counted; a batch that ran after convergence copies the same
+  // record again) is the final state
+  double host[S_COUNT];
+  {
+    const double* a = pin.p;
+    const double* b2 = pin.p + S_COUNT;
+    const double* h = (b2[S_ITER] > a[S_ITER]) ? b2 : a;
+    for (int k = 0; k < S_COUNT; ++k) host[k] = h[k];
   }
   const bool ok = host[S_DONE] != 0.0 && host[S_FAIL] == 0.0;
   const double bnorm = std::sqrt(host[S_BB]);

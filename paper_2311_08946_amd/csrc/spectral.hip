@@ -203,23 +203,34 @@ void launch_colloc_build(const BucketTables& T, const ChunkDesc& C, const NodeSa
 // weights in rho times Ntheta-point periodic cardinals in theta; folded onto
 // the unknowns they give e (interior) and eps (ring):
 //   C[i, Xi_m] = e^T W[:, :M] - eps^T H,   r_i = e^T W[:, M],   C_ii = 1.
+// Knots go in chunks of 32; for each chunk E W is a (32 x n) (n x (M+1))
+// product: E is formed in LDS 32 columns at a time from the radial and
+// angular weights, W's rows are staged beside it, and the four wavefronts
+// accumulate E W on MFMA (wavefront w: knots 16 (w mod 2) .., every other
+// 16-column block).
 namespace {
-constexpr int kEvalKnots = 32;
-constexpr int kEvalGroups = 8;    // 256 threads = 32 knots x 8 column groups
-constexpr int kEvalQ = 32;
-constexpr int kEvalMaxPer = 17;   // columns per thread: nrhs <= 136
+constexpr int kEK = 32;           // knots per chunk
+constexpr int kEQ = 32;           // interior nodes per staged block
+constexpr int kEMaxCB = 5;        // column blocks per wavefront: nrhs <= 160
+constexpr int kEThreads = 256;
 }
 
-__global__ __launch_bounds__(256) void eval_scatter_kernel(BucketTables T, ChunkDesc C,
-                                                           const double* __restrict__ A0,
-                                                           int64_t stride, double* __restrict__ val,
-                                                           double* __restrict__ bvec) {
+__global__ __launch_bounds__(kEThreads) void eval_scatter_kernel(BucketTables T, ChunkDesc C,
+                                                                 const double* __restrict__ A0,
+                                                                 int64_t stride, double* __restrict__ val,
+                                                                 double* __restrict__ bvec) {
   extern __shared__ double sh[];
   const int Nc1 = T.Nc + 1, Nt = T.Nt, n = T.n, M = T.M, nrhs = T.nrhs, ld = T.ld;
-  double* lx = sh;                                  // [kEvalKnots][Nc+1]
-  double* lt = lx + kEvalKnots * Nc1;               // [kEvalKnots][Nt]
-  double* Ws = lt + kEvalKnots * Nt;                // [kEvalQ][nrhs]
-  const int tid = threadIdx.x;
+  const int NCB = (nrhs + 15) / 16, NC = NCB * 16;
+  const int sx = Nc1 | 1, st = Nt | 1;               // odd strides
+  double* lx = sh;                                    // [kEK][sx]
+  double* lt = lx + kEK * sx;                         // [kEK][st]
+  double* eps = lt + kEK * st;                        // [kEK][st]
+  double* Eb = eps + kEK * st;                        // [kEK][kEQ + 1]
+  double* Wb = Eb + kEK * (kEQ + 1);                  // [kEQ][NC + 1]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int rb = w & 1, cb0 = w >> 1;                 // row block, first column block
   const int ci = blockIdx.x;
   const int f = C.fl[ci];
   const int m = C.float_ids[f];
@@ -227,83 +238,120 @@ __global__ __launch_bounds__(256) void eval_scatter_kernel(BucketTables T, Chunk
   const int64_t klo = C.fk_off[f], khi = C.fk_off[f + 1];
   const double cxm = C.cx[m], cym = C.cy[m], rm = C.rad[m];
   const int half = Nt / 2;
-  const int t = tid & (kEvalKnots - 1), cg = tid / kEvalKnots;
-  for (int64_t base = klo; base < khi; base += kEvalKnots) {
-    const int cnt = (int)min<int64_t>(kEvalKnots, khi - base);
-    if (tid < cnt) {
-      const int i = C.fk_ids[base + tid];
-      const double dx = C.kx[i] - cxm, dy = C.ky[i] - cym;
-      const double rho = sqrt(dx * dx + dy * dy) / rm;
-      const double phi = atan2(dy, dx);
-      int exact = -1;
-      double ssum = 0.0;
-      for (int j = 0; j < Nc1; ++j) {
-        const double d = rho - T.xr[j];
-        if (d == 0.0) exact = j;
-        else ssum += T.bw[j] / d;
-      }
-      for (int j = 0; j < Nc1; ++j)
-        lx[tid * Nc1 + j] = (exact >= 0) ? (j == exact ? 1.0 : 0.0)
-                                         : (T.bw[j] / (rho - T.xr[j])) / ssum;
-      const double hstep = kTwoPiD / Nt;
-      for (int l = 0; l < Nt; ++l) {
-        const double x = 0.5 * (phi - hstep * l);
-        double sx, cx;
-        sincos(x, &sx, &cx);
-        // periodic cardinal sin(Nt x) cos(x) / (Nt sin(x)) at half-angle x
-        lt[tid * Nt + l] = (fabs(sx) < 1e-15) ? 1.0 : sin(Nt * x) * cx / (Nt * sx);
+  typedef double dbl4 __attribute__((ext_vector_type(4)));
+  for (int64_t base = klo; base < khi; base += kEK) {
+    const int cnt = (int)min<int64_t>(kEK, khi - base);
+    // radial weights (one thread per knot) ...
+    if (tid < kEK) {
+      const int t = tid;
+      if (t < cnt) {
+        const int i = C.fk_ids[base + t];
+        const double dx = C.kx[i] - cxm, dy = C.ky[i] - cym;
+        const double rho = sqrt(dx * dx + dy * dy) / rm;
+        int exact = -1;
+        double ssum = 0.0;
+        for (int j = 0; j < Nc1; ++j) {
+          const double d = rho - T.xr[j];
+          if (d == 0.0) exact = j;
+          else ssum += T.bw[j] / d;
+        }
+        for (int j = 0; j < Nc1; ++j)
+          lx[t * sx + j] = (exact >= 0) ? (j == exact ? 1.0 : 0.0) : (T.bw[j] / (rho - T.xr[j])) / ssum;
+      } else {
+        for (int j = 0; j < Nc1; ++j) lx[t * sx + j] = 0.0;
       }
     }
-    __syncthreads();
-    double acc[kEvalMaxPer];
-#pragma unroll
-    for (int u = 0; u < kEvalMaxPer; ++u) acc[u] = 0.0;
-    for (int q0 = 0; q0 < n; q0 += kEvalQ) {
-      const int qn = min(kEvalQ, n - q0);
-      for (int idx = tid; idx < qn * nrhs; idx += 256) {
-        const int qq = idx / nrhs, c = idx - qq * nrhs;
-        Ws[qq * nrhs + c] = A[(int64_t)(q0 + qq) * ld + n + c];
-      }
-      __syncthreads();
+    // ... and angular cardinals (all threads)
+    const double hstep = kTwoPiD / Nt;
+    for (int idx = tid; idx < kEK * Nt; idx += kEThreads) {
+      const int t = idx / Nt, l = idx - t * Nt;
+      double v = 0.0;
       if (t < cnt) {
-        for (int qq = 0; qq < qn; ++qq) {
+        const int i = C.fk_ids[base + t];
+        const double phi = atan2(C.ky[i] - cym, C.kx[i] - cxm);
+        const double x = 0.5 * (phi - hstep * l);
+        double sxx, cxx;
+        sincos(x, &sxx, &cxx);
+        // periodic cardinal sin(Nt x) cos(x) / (Nt sin(x)) at half-angle x
+        v = (fabs(sxx) < 1e-15) ? 1.0 : sin(Nt * x) * cxx / (Nt * sxx);
+      }
+      lt[t * st + l] = v;
+    }
+    __syncthreads();
+    // ring weights eps[t][l]
+    for (int idx = tid; idx < kEK * Nt; idx += kEThreads) {
+      const int t = idx / Nt, l = idx - t * Nt;
+      int lq = l + half;
+      if (lq >= Nt) lq -= Nt;
+      eps[t * st + l] = lx[t * sx] * lt[t * st + l] + lx[t * sx + Nc1 - 1] * lt[t * st + lq];
+    }
+    dbl4 acc[kEMaxCB];
+#pragma unroll
+    for (int u = 0; u < kEMaxCB; ++u) acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int q0 = 0; q0 < n; q0 += kEQ) {
+      const int qn = min(kEQ, n - q0);
+      // E block: e_t(q) = lx[t][k] lt[t][l'] + lx[t][Nc - k] lt[t][l' + Nt/2]
+      for (int idx = tid; idx < kEK * kEQ; idx += kEThreads) {
+        const int t = idx / kEQ, qq = idx - t * kEQ;
+        double e = 0.0;
+        if (qq < qn) {
           const int q = q0 + qq;
           const int k = q / Nt + 1;
           const int lp = q - (k - 1) * Nt;
           int lq = lp + half;
           if (lq >= Nt) lq -= Nt;
-          const double e = lx[t * Nc1 + k] * lt[t * Nt + lp] + lx[t * Nc1 + (Nc1 - 1 - k)] * lt[t * Nt + lq];
+          e = lx[t * sx + k] * lt[t * st + lp] + lx[t * sx + (Nc1 - 1 - k)] * lt[t * st + lq];
+        }
+        Eb[t * (kEQ + 1) + qq] = e;
+      }
+      // W rows q0 .. q0 + qn (columns n .. n + nrhs), zero-padded
+      for (int idx = tid; idx < kEQ * NC; idx += kEThreads) {
+        const int qq = idx / NC, c = idx - qq * NC;
+        Wb[qq * (NC + 1) + c] = (qq < qn && c < nrhs) ? A[(int64_t)(q0 + qq) * ld + n + c] : 0.0;
+      }
+      __syncthreads();
 #pragma unroll
-          for (int u = 0; u < kEvalMaxPer; ++u) {
-            const int c = cg + kEvalGroups * u;
-            if (c < nrhs) acc[u] += e * Ws[qq * nrhs + c];
+      for (int ks = 0; ks < kEQ / 4; ++ks) {
+        const double a = Eb[(16 * rb + li) * (kEQ + 1) + 4 * ks + lk];
+#pragma unroll
+        for (int u = 0; u < kEMaxCB; ++u) {
+          const int cb = cb0 + 2 * u;
+          if (cb < NCB) {
+            const double bb = Wb[(4 * ks + lk) * (NC + 1) + 16 * cb + li];
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[u], 0, 0, 0);
           }
         }
       }
       __syncthreads();
     }
-    if (t < cnt) {
-      for (int l = 0; l < Nt; ++l) {
-        int lq = l + half;
-        if (lq >= Nt) lq -= Nt;
-        const double eps = lx[t * Nc1] * lt[t * Nt + l] + lx[t * Nc1 + Nc1 - 1] * lt[t * Nt + lq];
+    // D layout: acc[u][v] is knot 16 rb + 4 v + lk, column 16 cb + li
 #pragma unroll
-        for (int u = 0; u < kEvalMaxPer; ++u) {
-          const int c = cg + kEvalGroups * u;
-          if (c < M) acc[u] -= eps * T.H[(int64_t)l * M + c];
+    for (int u = 0; u < kEMaxCB; ++u) {
+      const int cb = cb0 + 2 * u;
+      const int c = 16 * cb + li;
+      if (cb < NCB && c < nrhs) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int t = 16 * rb + 4 * v + lk;
+          if (t < cnt) {
+            double x = acc[u][v];
+            const int i = C.fk_ids[base + t];
+            if (c < M) {
+              for (int l = 0; l < Nt; ++l) x -= eps[t * st + l] * T.H[(int64_t)l * M + c];
+              const int64_t lo = C.knot_off[m];
+              const int shift = (i < lo) ? 1 : 0;
+              val[C.rowptr[i] + shift + c] = x;
+            } else {
+              bvec[i] = x;
+            }
+          }
         }
       }
-      const int i = C.fk_ids[base + t];
+    }
+    if (tid < cnt) {
+      const int i = C.fk_ids[base + tid];
       const int64_t lo = C.knot_off[m];
-      const int64_t p = C.rowptr[i];
-      const int shift = (i < lo) ? 1 : 0;
-#pragma unroll
-      for (int u = 0; u < kEvalMaxPer; ++u) {
-        const int c = cg + kEvalGroups * u;
-        if (c < M) val[p + shift + c] = acc[u];
-        else if (c == M) bvec[i] = acc[u];
-      }
-      if (cg == 0) val[p + (shift ? 0 : M)] = 1.0;
+      val[C.rowptr[i] + ((i < lo) ? 0 : M)] = 1.0;
     }
     __syncthreads();
   }
@@ -311,8 +359,12 @@ __global__ __launch_bounds__(256) void eval_scatter_kernel(BucketTables T, Chunk
 
 void launch_eval_scatter(const BucketTables& T, const ChunkDesc& C, const double* A,
                          int64_t mat_stride, double* val, double* b, hipStream_t st) {
-  size_t shm = sizeof(double) * ((size_t)kEvalKnots * (T.Nc + 1 + T.Nt) + (size_t)kEvalQ * T.nrhs);
-  hipLaunchKernelGGL(eval_scatter_kernel, dim3(C.count), dim3(256), shm, st, T, C, A, mat_stride,
+  const int NC = (T.nrhs + 15) / 16 * 16;
+  const size_t shm = sizeof(double) * ((size_t)kEK * ((T.Nc + 1) | 1) + 2 * (size_t)kEK * (T.Nt | 1) +
+                                       (size_t)kEK * (kEQ + 1) + (size_t)kEQ * (NC + 1));
+  (void)hipFuncSetAttribute((const void*)eval_scatter_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shm);
+  hipLaunchKernelGGL(eval_scatter_kernel, dim3(C.count), dim3(kEThreads), shm, st, T, C, A, mat_stride,
                      val, b);
 }
 
