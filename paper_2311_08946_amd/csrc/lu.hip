@@ -155,6 +155,62 @@ __device__ __attribute__((always_inline)) void gemm_sub(double* __restrict__ A, 
   __syncthreads();
 }
 
+// Narrow update A[r0:r1, c0:c1] -= A[r0:r1, k0:k1] A[k0:k1, c0:c1] for
+// k1 - k0 <= 32 and c1 - c0 <= 128 (the updates inside a panel or a 128-row
+// block): the small right factor is staged in LDS once, then every wavefront
+// streams its own 16-row strips -- left factor in the MFMA A layout and the
+// strip of C loaded straight from global memory, no barrier between strips.
+// Ends with a barrier.
+__device__ __attribute__((always_inline)) void strip_update(double* __restrict__ A, int ld, int r0, int r1,
+                                                             int c0, int c1, int k0, int k1,
+                                                             double (*sU)[kGT + kPad]) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int K = k1 - k0, W = c1 - c0;
+  for (int idx = tid; idx < kGK * kGT; idx += kThreads) {
+    const int k = idx / kGT, c = idx - k * kGT;
+    sU[k][c] = (k < K && c < W) ? A[(k0 + k) * ld + c0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int KS = (K + 3) >> 2, CB = (W + 15) >> 4;
+  const int nstrips = (r1 - r0 + 15) >> 4;
+#pragma unroll 1
+  for (int sidx = w; sidx < nstrips; sidx += kThreads / kWave) {
+    const int rs = r0 + 16 * sidx;
+    double a[kGK / 4];
+#pragma unroll
+    for (int ks = 0; ks < kGK / 4; ++ks) {
+      const bool ok = ks < KS && rs + li < r1 && 4 * ks + lk < K;
+      const double v = A[ok ? (rs + li) * ld + k0 + 4 * ks + lk : 0];
+      a[ks] = ok ? -v : 0.0;
+    }
+    dbl4 acc[kGT / 16];
+#pragma unroll
+    for (int cb = 0; cb < kGT / 16; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const bool ok = cb < CB && rs + 4 * v + lk < r1 && 16 * cb + li < W;
+        const double x = A[ok ? (rs + 4 * v + lk) * ld + c0 + 16 * cb + li : 0];
+        acc[cb][v] = ok ? x : 0.0;
+      }
+#pragma unroll
+    for (int ks = 0; ks < kGK / 4; ++ks) {
+      if (ks < KS) {
+#pragma unroll
+        for (int cb = 0; cb < kGT / 16; ++cb)
+          if (cb < CB) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], sU[4 * ks + lk][16 * cb + li], acc[cb], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < kGT / 16; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (cb < CB && rs + 4 * v + lk < r1 && 16 * cb + li < W)
+          A[(rs + 4 * v + lk) * ld + c0 + 16 * cb + li] = acc[cb][v];
+  }
+  __syncthreads();
+}
+
 // Triangular blocks (w <= NB <= 32 rows) are solved through their explicit
 // inverse: one wavefront inverts the w x w diagonal block column by column
 // (lane j forms column j with fully unrolled substitution), then every
@@ -482,7 +538,7 @@ __device__ __attribute__((always_inline)) void panel_body(const LuItem& it, int 
       if (k0 + pw < g0 + gw) {
         tri_inverse<TB, true>(A, ld, k0, pw, sh.u.t);
         tri_apply<TB>(A, ld, k0, pw, k0 + pw, g0 + gw, sh.u.t);
-        gemm_sub(A, ld, k0 + pw, n, k0 + pw, g0 + gw, k0, k0 + pw, sh.u.g);
+        strip_update(A, ld, k0 + pw, n, k0 + pw, g0 + gw, k0, k0 + pw, sh.u.g.Lt);
       }
     }
     // the group's diagonal block is final: keep the inverse of its upper
@@ -496,7 +552,7 @@ __device__ __attribute__((always_inline)) void panel_body(const LuItem& it, int 
     for (int idx = tid; idx < kTB * kTB; idx += kThreads) W->inv[b][idx >> 5][idx & 31] = sh.u.t.inv[idx >> 5][idx & 31];
     if (g0 + gw < K0 + kb) {
       tri_apply<kTB>(A, ld, g0, gw, g0 + gw, K0 + kb, sh.u.t);
-      gemm_sub(A, ld, g0 + gw, n, g0 + gw, K0 + kb, g0, g0 + gw, sh.u.g);
+      strip_update(A, ld, g0 + gw, n, g0 + gw, K0 + kb, g0, g0 + gw, sh.u.g.Lt);
     }
     __syncthreads();
   }

@@ -168,4 +168,9 @@ struct pdd_system_s {
   int32_t plan = 0;
   pdd_system_stats stats{};
   std::vector<double> host_problem_bytes;
+  // solver scratch kept between pdd_solve_G calls on this system (calls on
+  // one system are serialised by the caller's stream order)
+  pdd::DevBuf solve_work, val_t;       // vectors and partial sums; C^T values
+  double* solve_pinned = nullptr;      // 2 convergence records (pinned host memory)
+  ~pdd_system_s() { if (solve_pinned) (void)hipHostFree(solve_pinned); }
 };

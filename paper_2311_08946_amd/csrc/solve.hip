@@ -288,22 +288,23 @@ pdd_status solve_impl(pdd_system sys, const double* rhs, double* u, int32_t tran
   c.val = sys->val.ptr<double>();
   c.N = N;
   c.x = u;
-  DevBuf valT;
   if (transpose) {
     ensure_transpose(sys->cover);
-    valT.alloc(nnz * sizeof(double));
-    hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st,
-                       D.rt_perm.ptr<int64_t>(), c.val, valT.ptr<double>(), nnz);
+    if (sys->val_t.bytes() == 0) {     // C^T values, formed once per system
+      sys->val_t.alloc(nnz * sizeof(double));
+      hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st,
+                         D.rt_perm.ptr<int64_t>(), c.val, sys->val_t.ptr<double>(), nnz);
+    }
     c.rowptr = D.rt_rowptr.ptr<int64_t>();
     c.cols = D.rt_cols.ptr<int32_t>();
-    c.val = valT.ptr<double>();
+    c.val = sys->val_t.ptr<double>();
   }
   const double* b = rhs ? rhs : sys->b.ptr<double>();
   c.nblocks = (int)((N + kRowsPerBlock - 1) / kRowsPerBlock);
   c.vblocks = (int)((N + kThreads - 1) / kThreads);
-  DevBuf work;
-  work.alloc(sizeof(double) * (5 * N + 2 * (int64_t)c.nblocks + S_COUNT));
-  c.r = work.ptr<double>();
+  const size_t wbytes = sizeof(double) * (5 * N + 2 * (int64_t)c.nblocks + S_COUNT);
+  if (sys->solve_work.bytes() < wbytes) sys->solve_work.alloc(wbytes);
+  c.r = sys->solve_work.ptr<double>();
   c.r0 = c.r + N;
   c.p = c.r0 + N;
   c.v = c.p + N;
@@ -321,12 +322,13 @@ pdd_status solve_impl(pdd_system sys, const double* rhs, double* u, int32_t tran
     double* p = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     ~Pinned() {
-      if (p) (void)hipHostFree(p);
       for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
     }
   } pin;
-  PDD_HIP(hipHostMalloc(&pin.p, 2 * S_COUNT * sizeof(double), hipHostMallocDefault));
+  if (!sys->solve_pinned)
+    PDD_HIP(hipHostMalloc(&sys->solve_pinned, 2 * S_COUNT * sizeof(double), hipHostMallocDefault));
+  pin.p = sys->solve_pinned;
   for (int k = 0; k < 2 * S_COUNT; ++k) pin.p[k] = 0.0;
   for (auto& e : pin.ev) PDD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   int enq = 0, slot = 0;
