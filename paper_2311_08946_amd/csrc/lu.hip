@@ -218,6 +218,7 @@ __device__ __attribute__((always_inline)) void strip_update(double* __restrict__
 struct TriLds {
   double blk[32][33];   // the diagonal block, zero-padded
   double inv[32][33];   // its inverse, zero-padded
+  double inv2[32][33];  // tri_inverse_pair: the inverse of its upper triangle
 };
 
 // T = (unit lower triangle of A[a:a+w, a:a+w])^-1 if LOWER, else
@@ -255,6 +256,45 @@ __device__ __attribute__((always_inline)) void tri_inverse(const double* __restr
 #pragma unroll 1
     for (int i = 0; i < NB; ++i)
       if (i >= w || j >= w) t.inv[i][j] = 0.0;
+  }
+  __syncthreads();
+}
+
+// Both inverses of one kTB x kTB diagonal block: t.inv <- (unit lower)^-1 by
+// wavefront 0 and t.inv2 <- (upper with diagonal)^-1 by wavefront 1, at the
+// same time.  Ends with a barrier.
+__device__ __attribute__((always_inline)) void tri_inverse_pair(const double* __restrict__ A, int ld, int a,
+                                                                 int w, TriLds& t) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int idx = tid; idx < kTB * kTB; idx += kThreads) {
+    const int i = idx / kTB, j = idx - i * kTB;
+    t.blk[i][j] = (i < w && j < w) ? A[(a + i) * ld + a + j] : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (wv == 0 && lane < kTB) {
+    const int j = lane;
+#pragma unroll 1
+    for (int i = 0; i < kTB; ++i) {
+      double v = (i == j) ? 1.0 : 0.0;
+#pragma unroll 8
+      for (int k = 0; k < i; ++k) v -= t.blk[i][k] * t.inv[k][j];
+      t.inv[i][j] = v;
+    }
+#pragma unroll 1
+    for (int i = 0; i < kTB; ++i)
+      if (i >= w || j >= w) t.inv[i][j] = 0.0;
+  } else if (wv == 1 && lane < kTB) {
+    const int j = lane;
+#pragma unroll 1
+    for (int i = kTB - 1; i >= 0; --i) {
+      double v = (i == j) ? 1.0 : 0.0;
+#pragma unroll 8
+      for (int k = i + 1; k < kTB; ++k) v -= t.blk[i][k] * t.inv2[k][j];
+      t.inv2[i][j] = v / t.blk[i][i];
+    }
+#pragma unroll 1
+    for (int i = 0; i < kTB; ++i)
+      if (i >= w || j >= w) t.inv2[i][j] = 0.0;
   }
   __syncthreads();
 }
@@ -544,12 +584,11 @@ __device__ __attribute__((always_inline)) void panel_body(const LuItem& it, int 
     // the group's diagonal block is final: keep the inverse of its upper
     // triangle for the back substitution and that of its unit-lower triangle
     // for the U12 tiles
-    tri_inverse<kTB, false>(A, ld, g0, gw, sh.u.t);
-    for (int idx = tid; idx < kTB * kTB; idx += kThreads)
-      it.uinv[(g0 / kTB) * kTB * kTB + idx] = sh.u.t.inv[idx >> 5][idx & 31];
-    __syncthreads();
-    tri_inverse<kTB, true>(A, ld, g0, gw, sh.u.t);
-    for (int idx = tid; idx < kTB * kTB; idx += kThreads) W->inv[b][idx >> 5][idx & 31] = sh.u.t.inv[idx >> 5][idx & 31];
+    tri_inverse_pair(A, ld, g0, gw, sh.u.t);
+    for (int idx = tid; idx < kTB * kTB; idx += kThreads) {
+      it.uinv[(g0 / kTB) * kTB * kTB + idx] = sh.u.t.inv2[idx >> 5][idx & 31];
+      W->inv[b][idx >> 5][idx & 31] = sh.u.t.inv[idx >> 5][idx & 31];
+    }
     if (g0 + gw < K0 + kb) {
       tri_apply<kTB>(A, ld, g0, gw, g0 + gw, K0 + kb, sh.u.t);
       strip_update(A, ld, g0 + gw, n, g0 + gw, K0 + kb, g0, g0 + gw, sh.u.g.Lt);
@@ -592,7 +631,7 @@ __device__ __attribute__((always_inline)) void urow_body(const LuItem& it, int K
     for (int idx = tid; idx < kTB * kTB; idx += kThreads) u.t.inv[idx >> 5][idx & 31] = W->inv[b][idx >> 5][idx & 31];
     __syncthreads();
     tri_apply<kTB>(A, ld, a, w, c0, c1, u.t);
-    if (a + w < K0 + kb) gemm_sub(A, ld, a + w, K0 + kb, c0, c1, a, a + w, u.g);
+    if (a + w < K0 + kb) strip_update(A, ld, a + w, K0 + kb, c0, c1, a, a + w, u.g.Lt);
   }
 }
 
@@ -620,7 +659,10 @@ __device__ __attribute__((always_inline)) void bdiag_body(const LuItem& it, int 
       u.t.inv[idx >> 5][idx & 31] = it.uinv[(a0 / kTB) * kTB * kTB + idx];
     __syncthreads();
     tri_apply<kTB>(A, ld, a0, b1 - a0, n, n + nrhs, u.t);
-    if (a0 > k0) gemm_sub(A, ld, k0, a0, n, n + nrhs, a0, b1, u.g);
+    if (a0 > k0) {
+      if (nrhs <= kGT) strip_update(A, ld, k0, a0, n, n + nrhs, a0, b1, u.g.Lt);
+      else gemm_sub(A, ld, k0, a0, n, n + nrhs, a0, b1, u.g);
+    }
   }
 }
 
