@@ -167,6 +167,7 @@ __device__ __attribute__((always_inline)) void strip_update(double* __restrict__
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int K = k1 - k0, W = c1 - c0;
+#pragma unroll 1
   for (int idx = tid; idx < kGK * kGT; idx += kThreads) {
     const int k = idx / kGT, c = idx - k * kGT;
     sU[k][c] = (k < K && c < W) ? A[(k0 + k) * ld + c0 + c] : 0.0;
@@ -184,29 +185,37 @@ __device__ __attribute__((always_inline)) void strip_update(double* __restrict__
       const double v = A[ok ? (rs + li) * ld + k0 + 4 * ks + lk : 0];
       a[ks] = ok ? -v : 0.0;
     }
-    dbl4 acc[kGT / 16];
+    // two 16-column blocks at a time (keeps the live registers low)
+#pragma unroll 1
+    for (int cq = 0; cq < CB; cq += 2) {
+      dbl4 acc[2];
 #pragma unroll
-    for (int cb = 0; cb < kGT / 16; ++cb)
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const bool ok = cb < CB && rs + 4 * v + lk < r1 && 16 * cb + li < W;
-        const double x = A[ok ? (rs + 4 * v + lk) * ld + c0 + 16 * cb + li : 0];
-        acc[cb][v] = ok ? x : 0.0;
+        for (int v = 0; v < 4; ++v) {
+          const int cb = cq + u;
+          const bool ok = cb < CB && rs + 4 * v + lk < r1 && 16 * cb + li < W;
+          const double x = A[ok ? (rs + 4 * v + lk) * ld + c0 + 16 * cb + li : 0];
+          acc[u][v] = ok ? x : 0.0;
+        }
+#pragma unroll
+      for (int ks = 0; ks < kGK / 4; ++ks) {
+        if (ks < KS) {
+#pragma unroll
+          for (int u = 0; u < 2; ++u)
+            if (cq + u < CB)
+              acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], sU[4 * ks + lk][16 * (cq + u) + li], acc[u], 0, 0, 0);
+        }
       }
 #pragma unroll
-    for (int ks = 0; ks < kGK / 4; ++ks) {
-      if (ks < KS) {
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int cb = 0; cb < kGT / 16; ++cb)
-          if (cb < CB) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], sU[4 * ks + lk][16 * cb + li], acc[cb], 0, 0, 0);
-      }
+        for (int v = 0; v < 4; ++v) {
+          const int cb = cq + u;
+          if (cb < CB && rs + 4 * v + lk < r1 && 16 * cb + li < W)
+            A[(rs + 4 * v + lk) * ld + c0 + 16 * cb + li] = acc[u][v];
+        }
     }
-#pragma unroll
-    for (int cb = 0; cb < kGT / 16; ++cb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        if (cb < CB && rs + 4 * v + lk < r1 && 16 * cb + li < W)
-          A[(rs + 4 * v + lk) * ld + c0 + 16 * cb + li] = acc[cb][v];
   }
   __syncthreads();
 }
