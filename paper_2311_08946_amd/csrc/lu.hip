@@ -712,13 +712,30 @@ __device__ __forceinline__ int back_block(const LuItem& it, int step) {
   return ((it.n + kOuter - 1) / kOuter - 1 - step) * kOuter;
 }
 
+// The panel kernel: four wavefronts per SIMD (two workgroups per CU) where
+// the register sub-panel is small (ROWS <= 2), two where it is not.
+template <int ROWS, int NB>
+__device__ __attribute__((always_inline)) void panel_launch(const LuItem* __restrict__ items,
+                                                            const int32_t* __restrict__ pre, int count, int step,
+                                                            PanelShared<NB>& sh) {
+  const int gi = blockIdx.x;                 // one workgroup per matrix
+  if (gi >= pre[count]) return;
+  panel_body<ROWS, NB>(items[owner(pre, count, gi)], step * kOuter, sh);
+}
+
 template <int ROWS, int NB>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void lu_panel_kernel(
     const LuItem* __restrict__ items, const int32_t* __restrict__ pre, int count, int step) {
   __shared__ PanelShared<NB> sh;
-  const int gi = blockIdx.x;                 // one workgroup per matrix
-  if (gi >= pre[count]) return;
-  panel_body<ROWS, NB>(items[owner(pre, count, gi)], step * kOuter, sh);
+  panel_launch<ROWS, NB>(items, pre, count, step, sh);
+}
+
+template <int ROWS, int NB>
+__global__ __launch_bounds__(kThreads) void lu_panel_wide_kernel(const LuItem* __restrict__ items,
+                                                                 const int32_t* __restrict__ pre, int count,
+                                                                 int step) {
+  __shared__ PanelShared<NB> sh;
+  panel_launch<ROWS, NB>(items, pre, count, step, sh);
 }
 
 // PERSISTENT: each workgroup strides over the list; otherwise one workgroup
@@ -744,7 +761,7 @@ __global__ __launch_bounds__(kThreads) void lu_urow_kernel(const LuItem* __restr
 }
 
 template <bool PERSISTENT>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void lu_pupd_kernel(
+__global__ __launch_bounds__(kThreads) void lu_pupd_kernel(
     const LuItem* __restrict__ items, const int32_t* __restrict__ pre, int count, int step) {
   __shared__ GemmLds g;
   const int total = pre[count];
@@ -861,8 +878,8 @@ int LuPlan::launch(hipStream_t st, int grid_cap) const {
     go(LU_PUPD, s, lu_pupd_kernel<false>, lu_pupd_kernel<true>);
     go(LU_PANEL0, s, lu_panel_kernel<1, 16>, nullptr);
     go(LU_PANEL1, s, lu_panel_kernel<2, 16>, nullptr);
-    go(LU_PANEL2, s, lu_panel_kernel<4, 16>, nullptr);
-    go(LU_PANEL3, s, lu_panel_kernel<8, 8>, nullptr);
+    go(LU_PANEL2, s, lu_panel_wide_kernel<4, 16>, nullptr);
+    go(LU_PANEL3, s, lu_panel_wide_kernel<8, 8>, nullptr);
     go(LU_LSWAP, s, lu_urow_kernel<false, true>, lu_urow_kernel<true, true>);
     go(LU_UROW, s, lu_urow_kernel<false, false>, lu_urow_kernel<true, false>);
   }
