@@ -17,13 +17,14 @@
 //     permutation and the inverses of the 32 x 32 diagonal blocks of L11 and
 //     U11 in a per-matrix work area;
 //   * lu_urow_kernel<LEFT> (one workgroup per matrix and 128-column tile
-//     left of the panel): applies the step's interchanges to L;
+//     left of the panel): applies the step's interchanges to L; one more
+//     workgroup per matrix forms L11^-1 from the inverses of its 32 x 32
+//     diagonal blocks;
 //   * lu_urow_kernel (one workgroup per matrix and 128-column tile right of
 //     the panel): applies the step's interchanges to the tile, brings rows
 //     [K0, K0 + kb) up to date with one long-K product and forms
-//     U12 = L11^-1 A12 by 32-row blocks (the stored inverses on MFMA, then
-//     MFMA updates of the rows below) -- the right-hand-side columns are
-//     among these tiles and are thereby eliminated forward.
+//     U12 = L11^-1 A12 with a second MFMA product -- the right-hand-side
+//     columns are among these tiles and are thereby eliminated forward.
 // The back substitution U W = R' then runs from the bottom in 128-row blocks:
 // lu_bdiag_kernel solves a diagonal block (32-row triangles through the
 // inverses of U's diagonal blocks, stored by the panel kernel, and MFMA
@@ -61,8 +62,13 @@ struct GemmLds {
 // disjoint.  Called by all threads of the workgroup; ends with a barrier.
 // Addresses are one per-lane base pointer plus workgroup-uniform offsets, and
 // the edge tests are per-lane bit masks, to keep register use low.
-__device__ __attribute__((always_inline)) void gemm_sub(double* __restrict__ A, int ld, int r0, int r1, int c0, int c1,
-                                                         int k0, int k1, GemmLds& s) {
+// SET: A[r0:r1, c0:c1] = Lb[r - lro, k - lko] A[k0:k1, c0:c1] with a separate
+// left factor Lb (leading dimension ldl); the right factor may be the output
+// block itself (every read precedes the final barrier, every write follows it).
+template <bool SET>
+__device__ __attribute__((always_inline)) void gemm_op(double* __restrict__ A, int ld, int r0, int r1, int c0, int c1,
+                                                        int k0, int k1, const double* Lb, int ldl, int lro, int lko,
+                                                        GemmLds& s) {
   // element offsets from A fit in 32 bits (n * ld < 2^31)
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = w >> 1, wc = w & 1;       // 4 x 2 wavefronts: 32 rows x 64 columns each
@@ -92,11 +98,15 @@ __device__ __attribute__((always_inline)) void gemm_sub(double* __restrict__ A, 
         for (int v = 0; v < 4; ++v)
 #pragma unroll
           for (int bj = 0; bj < 4; ++bj) {
-            const bool ok = ((rmask >> (4 * bi + v)) & (cmask >> bj) & 1u) != 0;
-            const double cv = A[ok ? coff + (16 * bi + 4 * v) * ld + 16 * bj : 0];
-            acc[bi][bj][v] = ok ? cv : 0.0;
+            if (SET) {
+              acc[bi][bj][v] = 0.0;
+            } else {
+              const bool ok = ((rmask >> (4 * bi + v)) & (cmask >> bj) & 1u) != 0;
+              const double cv = A[ok ? coff + (16 * bi + 4 * v) * ld + 16 * bj : 0];
+              acc[bi][bj][v] = ok ? cv : 0.0;
+            }
           }
-      const int loff = (rt + lrow) * ld + lcol;
+      const int loff = (rt - lro + lrow) * ldl + lcol - lko;
       const int uoff = urow * ld + ct + ucol;
       unsigned lmask = 0;
 #pragma unroll
@@ -110,7 +120,7 @@ __device__ __attribute__((always_inline)) void gemm_sub(double* __restrict__ A, 
         for (int it = 0; it < 8; ++it) {
           const bool okl = lk_ok && ((lmask >> it) & 1u);
           const bool oku = ucol_ok && kc + urow + 4 * it < k1;
-          const double vl = A[okl ? loff + 16 * it * ld + kc : 0];
+          const double vl = Lb[okl ? loff + 16 * it * ldl + kc : 0];
           const double vu = A[oku ? uoff + (kc + 4 * it) * ld : 0];
           pl[it] = okl ? vl : 0.0;
           pu[it] = oku ? vu : 0.0;
@@ -121,7 +131,7 @@ __device__ __attribute__((always_inline)) void gemm_sub(double* __restrict__ A, 
       for (int kc = k0; kc < k1; kc += kGK) {
 #pragma unroll
         for (int it = 0; it < 8; ++it) {
-          lt_st[16 * it] = -pl[it];
+          lt_st[16 * it] = SET ? pl[it] : -pl[it];
           ut_st[4 * it * (kGT + kPad)] = pu[it];
         }
         __syncthreads();
@@ -153,6 +163,11 @@ __device__ __attribute__((always_inline)) void gemm_sub(double* __restrict__ A, 
     }
   }
   __syncthreads();
+}
+
+__device__ __attribute__((always_inline)) void gemm_sub(double* __restrict__ A, int ld, int r0, int r1, int c0, int c1,
+                                                         int k0, int k1, GemmLds& s) {
+  gemm_op<false>(A, ld, r0, r1, c0, c1, k0, k1, A, ld, 0, 0, s);
 }
 
 // Narrow update A[r0:r1, c0:c1] -= A[r0:r1, k0:k1] A[k0:k1, c0:c1] for
@@ -310,18 +325,14 @@ __device__ __attribute__((always_inline)) void tri_inverse_pair(const double* __
 
 // Rows [a, a+w) of columns [c0, c1) <- T (rows), T = t.inv (w <= NB).  Each
 // wavefront takes 16-column blocks; the block's w rows are loaded in the MFMA
-// B layout, multiplied, and written back in place.  Ends with a barrier.
+// B layout, multiplied by T read from LDS as the products need it (few live
+// registers), and written back in place.  Ends with a barrier.
 template <int NB>
 __device__ __attribute__((always_inline)) void tri_apply(double* __restrict__ A, int ld, int a, int w,
                                                           int c0, int c1, const TriLds& t) {
   constexpr int BI = NB / 16, KS = NB / 4;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  double ta[BI][KS];
-#pragma unroll
-  for (int bi = 0; bi < BI; ++bi)
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) ta[bi][ks] = t.inv[16 * bi + li][4 * ks + lk];
   const int roff = (a + lk) * ld;
 #pragma unroll 1
   for (int cb = c0 + 16 * wv; cb < c1; cb += 16 * (kThreads / kWave)) {
@@ -341,7 +352,7 @@ __device__ __attribute__((always_inline)) void tri_apply(double* __restrict__ A,
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int bi = 0; bi < BI; ++bi)
-        acc[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[bi][ks], xb[ks], acc[bi], 0, 0, 0);
+        acc[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(t.inv[16 * bi + li][4 * ks + lk], xb[ks], acc[bi], 0, 0, 0);
 #pragma unroll
     for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
@@ -357,6 +368,7 @@ __device__ __attribute__((always_inline)) void tri_apply(double* __restrict__ A,
 
 // Per-matrix work area of one step (global memory).
 struct LuWork {
+  double linv[kOuter][kOuter];         // L11^-1 (unit lower), zero-padded
   double inv[kOuter / kTB][kTB][kTB];  // inverses of L11's unit-lower diagonal blocks
   int rows[2 * kOuter];                // rows touched by the step's interchanges
   int src[2 * kOuter];                 // slot whose old contents end up in each slot's row
@@ -433,6 +445,31 @@ __device__ __attribute__((always_inline)) void apply_perm(double* __restrict__ A
   }
 }
 
+// Wavefront maximum of a double: DPP exchanges inside each row of 16 lanes
+// (quad permutations, half-row and row mirrors), then the four row maxima
+// read from lanes 0, 16, 32, 48.  fmax drops NaN operands.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_f64<0xb1>(v));    // quad_perm [1, 0, 3, 2]
+  v = fmax(v, dpp_f64<0x4e>(v));    // quad_perm [2, 3, 0, 1]
+  v = fmax(v, dpp_f64<0x141>(v));   // row_half_mirror
+  v = fmax(v, dpp_f64<0x140>(v));   // row_mirror
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+
 // LDS of the sub-panel factorisation: per column, each wavefront's best pivot
 // candidate (value, row index, full sub-panel row) and the current row kk,
 // double-buffered by column parity so that one barrier per column suffices.
@@ -466,19 +503,25 @@ __device__ __attribute__((always_inline)) void factor_subpanel(double* __restric
   for (int c = 0; c < NB; ++c) {
     if (c < pw) {                            // uniform
       const int kk = k0 + c, buf = c & 1;
+      // the wavefront's largest magnitude (NaN never wins), then the lowest
+      // of its rows holding it: both wavefront-uniform
+      double lv = -1.0;
+#pragma unroll
+      for (int s = 0; s < ROWS; ++s) {
+        const int row = k0 + tid + kThreads * s;
+        if (row >= kk && row < n) lv = fmax(lv, fabs(P[s][c]));
+      }
+      const double wmax = wave_max(lv);
       double bv = -1.0;
       int bi = 0x7fffffff;
 #pragma unroll
       for (int s = 0; s < ROWS; ++s) {
         const int row = k0 + tid + kThreads * s;
-        const double v = fabs(P[s][c]);
-        if (row >= kk && row < n && v > bv) { bv = v; bi = row; }
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(bv, off, kWave);
-        const int oi = __shfl_xor(bi, off, kWave);
-        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        const unsigned long long m = __ballot(row >= kk && row < n && fabs(P[s][c]) == wmax);
+        if (bi == 0x7fffffff && m != 0ull) {
+          bi = k0 + kWave * w + __builtin_ctzll(m) + kThreads * s;
+          bv = wmax;
+        }
       }
 #pragma unroll
       for (int s = 0; s < ROWS; ++s) {
@@ -556,9 +599,16 @@ union MatLds {
   TriLds t;
 };
 
+// The panel kernel's LDS (about 38 KB, so that LDS never limits it below
+// the two workgroups per CU its registers allow).
+union PanelScratch {
+  double sU[kGK][kGT + kPad];   // strip_update's right factor, apply_perm's staging
+  TriLds t;
+};
+
 template <int NB>
 struct PanelShared {
-  MatLds u;
+  PanelScratch u;
   PanelLds<NB> pl;
   int piv[kOuter];
   PermLds perm;
@@ -583,11 +633,11 @@ __device__ __attribute__((always_inline)) void panel_body(const LuItem& it, int 
       if (tid == 0) compose_perm(sh.piv + (k0 - K0), k0, pw, sh.perm.rows, sh.perm.src, &sh.perm.count);
       __syncthreads();
       // the sub-panel's interchanges on the rest of the panel
-      apply_perm(A, ld, sh.perm, K0, K0 + kb, k0, k0 + pw, &sh.u.g.Lt[0][0]);
+      apply_perm(A, ld, sh.perm, K0, K0 + kb, k0, k0 + pw, &sh.u.sU[0][0]);
       if (k0 + pw < g0 + gw) {
         tri_inverse<TB, true>(A, ld, k0, pw, sh.u.t);
         tri_apply<TB>(A, ld, k0, pw, k0 + pw, g0 + gw, sh.u.t);
-        strip_update(A, ld, k0 + pw, n, k0 + pw, g0 + gw, k0, k0 + pw, sh.u.g.Lt);
+        strip_update(A, ld, k0 + pw, n, k0 + pw, g0 + gw, k0, k0 + pw, sh.u.sU);
       }
     }
     // the group's diagonal block is final: keep the inverse of its upper
@@ -600,12 +650,116 @@ __device__ __attribute__((always_inline)) void panel_body(const LuItem& it, int 
     }
     if (g0 + gw < K0 + kb) {
       tri_apply<kTB>(A, ld, g0, gw, g0 + gw, K0 + kb, sh.u.t);
-      strip_update(A, ld, g0 + gw, n, g0 + gw, K0 + kb, g0, g0 + gw, sh.u.g.Lt);
+      strip_update(A, ld, g0 + gw, n, g0 + gw, K0 + kb, g0, g0 + gw, sh.u.sU);
     }
     __syncthreads();
   }
   if (tid == 0) compose_perm(sh.piv, K0, kb, W->rows, W->src, &W->count);
   if (tid == 0 && (K0 == 0 || singular)) *it.status = singular;
+}
+
+// One 16 x 16 output tile of alpha P Q (inner dimension K) by one wavefront
+// on MFMA, operands read straight from global memory in the MFMA layouts:
+// P(i, k) = p[i ld + k] for i < rows and k < cols, zero elsewhere (likewise
+// Q).  p itself may point past the matrix: lanes outside the bounds read the
+// valid address `safe` instead, so that every load is issued before the
+// first product.  The tile is stored to c (leading dimension lc).
+struct Opnd {
+  const double* p;
+  int ld, rows, cols;
+};
+
+template <int K>
+__device__ __attribute__((always_inline)) void wave_tile(Opnd P, Opnd Q, double alpha, double* c, int lc,
+                                                          const double* safe) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  double a[K / 4], b[K / 4];
+#pragma unroll
+  for (int ks = 0; ks < K / 4; ++ks) {
+    const int k = 4 * ks + lk;
+    const bool pa = li < P.rows && k < P.cols, qa = k < Q.rows && li < Q.cols;
+    const double va = *(pa ? P.p + li * P.ld + k : safe);
+    const double vb = *(qa ? Q.p + k * Q.ld + li : safe);
+    a[ks] = pa ? va : 0.0;
+    b[ks] = qa ? vb : 0.0;
+  }
+  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ks = 0; ks < K / 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[ks], acc, 0, 0, 0);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) c[(4 * v + lk) * lc + li] = alpha * acc[v];
+}
+
+// L11^-1 for the step's diagonal block (unit lower, kb x kb, zero-padded to
+// kOuter x kOuter) from the stored inverses D_b of its 32 x 32 diagonal
+// blocks, by doubling: a 2 x 2 block lower triangle [[P, 0], [C, Q]] has the
+// inverse [[P^-1, 0], [-Q^-1 C P^-1, Q^-1]].  Five phases of MFMA tiles, the
+// strictly upper blocks of the 128 x 128 result serving as scratch and
+// cleared at the end:
+//   0: X_bb = D_b, X_01 = X_23 = 0;   1: T_02 = L_10 D_0, T_03 = L_32 D_2;
+//   2: X_10 = -D_1 T_02, X_32 = -D_3 T_03;
+//   3: P = L[2:4, 0:2] X[0:2, 0:2] into X[0:2, 2:4];
+//   4: X[2:4, 0:2] = -X[2:4, 2:4] P;   5: X[0:2, 2:4] = 0.
+// Ends with a barrier.
+__device__ __attribute__((always_inline)) void linv_body(const LuItem& it, int K0) {
+  const int n = it.n, ld = it.ld;
+  LuWork* W = it.work;
+  double* __restrict__ X = &W->linv[0][0];
+  const int tid = threadIdx.x, w = tid >> 6;
+  const int kb = min(kOuter, n - K0);
+  auto L = [&](int a, int b) {            // block (a, b), a > b, of L11
+    return Opnd{it.A + (size_t)(K0 + kTB * a) * ld + K0 + kTB * b, ld, kb - kTB * a, kb - kTB * b};
+  };
+  auto D = [&](int b) {
+    const int e = kTB * b < kb ? kTB : 0;
+    return Opnd{&W->inv[b][0][0], kTB, e, e};
+  };
+  auto Xo = [&](int a, int b, int rows, int cols) {
+    return Opnd{X + kTB * a * kOuter + kTB * b, kOuter, rows, cols};
+  };
+  auto at = [&](int a, int b) { return X + kTB * a * kOuter + kTB * b; };
+  auto sub = [](Opnd o, int i, int k) {   // the 16 x 16 sub-tile (i, k) of an operand
+    return Opnd{o.p + 16 * i * o.ld + 16 * k, o.ld, o.rows - 16 * i, o.cols - 16 * k};
+  };
+  // phase 0
+  for (int idx = tid; idx < 4 * kTB * kTB; idx += kThreads) {
+    const int b = idx >> 10, i = (idx >> 5) & 31, j = idx & 31;
+    at(b, b)[i * kOuter + j] = kTB * b < kb ? W->inv[b][i][j] : 0.0;
+  }
+  for (int idx = tid; idx < 2 * kTB * kTB; idx += kThreads) {
+    const int b = idx >> 10, i = (idx >> 5) & 31, j = idx & 31;
+    at(2 * b, 2 * b + 1)[i * kOuter + j] = 0.0;
+  }
+  // phase 1: wavefront w takes product w / 4, output tile w % 4
+  {
+    const int pr = w >> 2, ti = (w >> 1) & 1, tj = w & 1;
+    const Opnd Pm = pr ? L(3, 2) : L(1, 0), Qm = D(2 * pr);
+    wave_tile<kTB>(sub(Pm, ti, 0), sub(Qm, 0, tj), 1.0, at(0, 2 + pr) + 16 * ti * kOuter + 16 * tj, kOuter, X);
+  }
+  __syncthreads();
+  {
+    const int pr = w >> 2, ti = (w >> 1) & 1, tj = w & 1;
+    const Opnd Pm = D(2 * pr + 1), Qm = Xo(0, 2 + pr, kTB, kTB);
+    wave_tile<kTB>(sub(Pm, ti, 0), sub(Qm, 0, tj), -1.0, at(2 * pr + 1, 2 * pr) + 16 * ti * kOuter + 16 * tj, kOuter,
+                   X);
+  }
+  __syncthreads();
+  // phases 3 and 4: 16 output tiles of 64 x 64, two per wavefront
+  const Opnd L64 = Opnd{it.A + (size_t)(K0 + 2 * kTB) * ld + K0, ld, kb - 2 * kTB, kb};
+  for (int t = w; t < 16; t += kThreads / kWave) {
+    const int ti = t >> 2, tj = t & 3;
+    wave_tile<2 * kTB>(sub(L64, ti, 0), sub(Xo(0, 0, 2 * kTB, 2 * kTB), 0, tj), 1.0,
+                       at(0, 2) + 16 * ti * kOuter + 16 * tj, kOuter, X);
+  }
+  __syncthreads();
+  for (int t = w; t < 16; t += kThreads / kWave) {
+    const int ti = t >> 2, tj = t & 3;
+    wave_tile<2 * kTB>(sub(Xo(2, 2, 2 * kTB, 2 * kTB), ti, 0), sub(Xo(0, 2, 2 * kTB, 2 * kTB), 0, tj), -1.0,
+                       at(2, 0) + 16 * ti * kOuter + 16 * tj, kOuter, X);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < 2 * kTB * 2 * kTB; idx += kThreads) at(0, 2)[(idx >> 6) * kOuter + (idx & 63)] = 0.0;
+  __syncthreads();
 }
 
 // Tile t of the step's U-row work.  LEFT: columns [128 t, ..) < K0 of L only
@@ -622,6 +776,10 @@ __device__ __attribute__((always_inline)) void urow_body(const LuItem& it, int K
   const LuWork* W = it.work;
   const int tid = threadIdx.x;
   const int kb = min(kOuter, n - K0);
+  if (LEFT && t == K0 / kGT) {           // the last unit of the LEFT launch
+    linv_body(it, K0);
+    return;
+  }
   const int c0 = LEFT ? t * kGT : K0 + kb + t * kGT;
   const int c1 = min(LEFT ? K0 : ld, c0 + kGT);
   if (tid == 0) perm.count = W->count;
@@ -635,13 +793,8 @@ __device__ __attribute__((always_inline)) void urow_body(const LuItem& it, int K
   // the contributions of all earlier steps to these rows (left-looking: the
   // trailing matrix is never updated as a whole)
   if (K0 > 0) gemm_sub(A, ld, K0, K0 + kb, c0, c1, 0, K0, u.g);
-  for (int b = 0; b * kTB < kb; ++b) {
-    const int a = K0 + b * kTB, w = min(kTB, kb - b * kTB);
-    for (int idx = tid; idx < kTB * kTB; idx += kThreads) u.t.inv[idx >> 5][idx & 31] = W->inv[b][idx >> 5][idx & 31];
-    __syncthreads();
-    tri_apply<kTB>(A, ld, a, w, c0, c1, u.t);
-    if (a + w < K0 + kb) strip_update(A, ld, a + w, K0 + kb, c0, c1, a, a + w, u.g.Lt);
-  }
+  // U12 = L11^-1 A12 as one MFMA product with the inverse the LEFT launch formed
+  gemm_op<true>(A, ld, K0, K0 + kb, c0, c1, K0, K0 + kb, &W->linv[0][0], kOuter, K0, K0, u.g);
 }
 
 // Row tile t of the step's panel: the contributions of all earlier steps,
@@ -831,7 +984,7 @@ int lu_plan_tiles(const LuItem& it, int kind, int step) {
   switch (kind) {
     case LU_PANEL0: case LU_PANEL1: case LU_PANEL2: case LU_PANEL3:
       return it.cls == kind - LU_PANEL0 ? 1 : 0;
-    case LU_LSWAP: return K0 / kGT;
+    case LU_LSWAP: return K0 / kGT + 1;     // the left tiles, then L11^-1
     case LU_UROW: return (ld - K0 - kb + kGT - 1) / kGT;
     case LU_PUPD: return K0 > 0 ? (n - K0 + kGT - 1) / kGT : 0;
     case LU_BDIAG: return 1;
