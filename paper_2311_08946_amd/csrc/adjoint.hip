@@ -36,9 +36,18 @@ struct AdjArgs {
   double* g[7];              // axx, axy, ayy, bx, by, c, f (node layout), may be null
 };
 
-// Dynamic LDS layout (doubles): y[n] | wI[n] | wB[Nt] | uX[M] | G[(Nc+1) Nt] | lx[32][Nc+1] | lt[32][Nt]
-//                               | blk[32][33]
-__global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(AdjArgs a) {
+// Lane l's value of a double, l wavefront-uniform.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Dynamic LDS layout (doubles): y[n] | wI[n] | wB[Nt] | uX[M] | one region shared by the phases:
+//   knots: lx[32][Nc+1] | lt[32][Nt] | per-knot rho, phi, lambda, weight sum (4 x 32) | exact index
+//   interchanges: piv (n ints);  gradients: G[(Nc+1) Nt]
+// (about 39 KB at n = 1024: four workgroups per CU)
+__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))) void adjoint_kernel(AdjArgs a) {
   extern __shared__ double sh[];
   const BucketTables& T = a.T;
   const int n = T.n, Nt = T.Nt, Nr = T.Nr, Nc = T.Nc, Nc1 = T.Nc + 1, M = T.M, ld = T.ld;
@@ -54,10 +63,16 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(AdjArgs a) {
   double* wI = y + n;
   double* wB = wI + n;
   double* uX = wB + Nt;
-  double* G = uX + M;
-  double* lx = G + (int64_t)Nc1 * Nt;
+  double* reg = uX + M;
+  double* G = reg;
+  double* lx = reg;
   double* lt = lx + kAdjKnots * Nc1;
-  double* blk = lt + kAdjKnots * Nt;          // [kTri][kTri + 1] diagonal block
+  double* kr = lt + kAdjKnots * Nt;           // per-knot rho, phi, lambda, weight sum, exact
+  double* kp = kr + kAdjKnots;
+  double* kw = kp + kAdjKnots;
+  double* kq = kw + kAdjKnots;
+  int* ke = reinterpret_cast<int*>(kq + kAdjKnots);
+  int* spiv = reinterpret_cast<int*>(reg);
 
   // ---- y = E^T lambda over the assigned knots
   for (int q = tid; q < n; q += kAdjThreads) y[q] = 0.0;
@@ -70,8 +85,6 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(AdjArgs a) {
       const int i = a.C.fk_ids[base + tid];
       const double dx = a.C.kx[i] - cxm, dy = a.C.ky[i] - cym;
       const double rho = sqrt(dx * dx + dy * dy) / rm;
-      const double phi = atan2(dy, dx);
-      const double lam = a.lambda[i];
       int exact = -1;
       double ssum = 0.0;
       for (int j = 0; j < Nc1; ++j) {
@@ -79,17 +92,27 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(AdjArgs a) {
         if (d == 0.0) exact = j;
         else ssum += T.bw[j] / d;
       }
-      // lambda is folded into the radial weights
-      for (int j = 0; j < Nc1; ++j)
-        lx[tid * Nc1 + j] = lam * ((exact >= 0) ? (j == exact ? 1.0 : 0.0)
-                                                : (T.bw[j] / (rho - T.xr[j])) / ssum);
-      const double hstep = kTwoPiD / Nt;
-      for (int l = 0; l < Nt; ++l) {
-        const double x = 0.5 * (phi - hstep * l);
-        double sx, cx;
-        sincos(x, &sx, &cx);
-        lt[tid * Nt + l] = (fabs(sx) < 1e-15) ? 1.0 : sin(Nt * x) * cx / (Nt * sx);
-      }
+      kr[tid] = rho;
+      kp[tid] = atan2(dy, dx);
+      kw[tid] = a.lambda[i];
+      ke[tid] = exact;
+      kq[tid] = ssum;
+    }
+    __syncthreads();
+    // lambda is folded into the radial weights; one (knot, node) entry per thread
+    for (int idx = tid; idx < cnt * Nc1; idx += kAdjThreads) {
+      const int t = idx / Nc1, j = idx - t * Nc1;
+      const int exact = ke[t];
+      lx[idx] = kw[t] * ((exact >= 0) ? (j == exact ? 1.0 : 0.0)
+                                      : (T.bw[j] / (kr[t] - T.xr[j])) / kq[t]);
+    }
+    const double hstep = kTwoPiD / Nt;
+    for (int idx = tid; idx < cnt * Nt; idx += kAdjThreads) {
+      const int t = idx / Nt, l = idx - t * Nt;
+      const double x = 0.5 * (kp[t] - hstep * l);
+      double sx, cx;
+      sincos(x, &sx, &cx);
+      lt[idx] = (fabs(sx) < 1e-15) ? 1.0 : sin(Nt * x) * cx / (Nt * sx);
     }
     __syncthreads();
     for (int q = tid; q < n; q += kAdjThreads) {
@@ -104,70 +127,114 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(AdjArgs a) {
   }
   __syncthreads();
 
-  // ---- U^T z = y (forward, 32-row blocks: the diagonal block is staged in
-  //      LDS, wave 0 solves it, then all threads update the remaining entries
-  //      from the block's rows)
+  // ---- U^T z = y (forward, 32-row blocks: wavefront 0 solves the diagonal
+  //      block from its rows held in registers (lane l holds column l), then
+  //      every thread removes the block's contribution from its later
+  //      entries, all 32 loads of an entry issued at once)
   for (int j0 = 0; j0 < n; j0 += kTri) {
-    const int j1 = min(n, j0 + kTri);
-    for (int idx = tid; idx < kTri * kTri; idx += kAdjThreads) {
-      const int i = idx / kTri, j = idx - i * kTri;
-      blk[i * (kTri + 1) + j] = (j0 + i < j1 && j0 + j < j1) ? A[(int64_t)(j0 + i) * ld + j0 + j] : 0.0;
-    }
-    __syncthreads();
+    const int bw = min(kTri, n - j0), j1 = j0 + bw;
     if (w == 0) {
-      double yi = (j0 + lane < j1) ? y[j0 + lane] : 0.0;
-      for (int j = j0; j < j1; ++j) {
-        const double zj = __shfl(yi, j - j0, 64) / blk[(j - j0) * (kTri + 1) + (j - j0)];
-        if (lane == j - j0) yi = zj;
-        else if (j0 + lane > j && j0 + lane < j1) yi -= blk[(j - j0) * (kTri + 1) + lane] * zj;
+      double row[kTri];
+#pragma unroll
+      for (int j = 0; j < kTri; ++j) {
+        const bool ok = j < bw && lane < bw;
+        const double v = A[ok ? (int64_t)(j0 + j) * ld + j0 + lane : 0];
+        row[j] = ok ? v : 0.0;
       }
-      if (j0 + lane < j1) y[j0 + lane] = yi;
+      double yi = (lane < bw) ? y[j0 + lane] : 0.0;
+#pragma unroll
+      for (int j = 0; j < kTri; ++j) {
+        if (j < bw) {
+          const double zj = readlane_f64(yi, j) / readlane_f64(row[j], j);
+          if (lane == j) yi = zj;
+          else if (lane > j) yi -= row[j] * zj;
+        }
+      }
+      if (lane < bw) y[j0 + lane] = yi;
     }
     __syncthreads();
     for (int i = j1 + tid; i < n; i += kAdjThreads) {
       double acc = 0.0;
-      for (int j = j0; j < j1; ++j) acc += A[(int64_t)j * ld + i] * y[j];
+#pragma unroll
+      for (int h = 0; h < kTri; h += kTri / 2) {
+        double v[kTri / 2];
+#pragma unroll
+        for (int j = 0; j < kTri / 2; ++j) {
+          const double x = A[h + j < bw ? (int64_t)(j0 + h + j) * ld + i : 0];
+          v[j] = h + j < bw ? x : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kTri / 2; ++j)
+          if (h + j < bw) acc += v[j] * y[j0 + h + j];
+      }
       y[i] -= acc;
     }
     __syncthreads();
   }
   // ---- L^T x = z (backward, unit diagonal, same blocking)
   for (int j1 = n; j1 > 0; j1 -= kTri) {
-    const int j0 = max(0, j1 - kTri);
-    for (int idx = tid; idx < kTri * kTri; idx += kAdjThreads) {
-      const int i = idx / kTri, j = idx - i * kTri;
-      blk[i * (kTri + 1) + j] = (j0 + i < j1 && j0 + j < j1) ? A[(int64_t)(j0 + i) * ld + j0 + j] : 0.0;
-    }
-    __syncthreads();
+    const int j0 = max(0, j1 - kTri), bw = j1 - j0;
     if (w == 0) {
-      double yi = (j0 + lane < j1) ? y[j0 + lane] : 0.0;
-      for (int j = j1 - 1; j >= j0; --j) {
-        const double xj = __shfl(yi, j - j0, 64);
-        if (j0 + lane < j) yi -= blk[(j - j0) * (kTri + 1) + lane] * xj;
+      double row[kTri];
+#pragma unroll
+      for (int j = 0; j < kTri; ++j) {
+        const bool ok = j < bw && lane < bw;
+        const double v = A[ok ? (int64_t)(j0 + j) * ld + j0 + lane : 0];
+        row[j] = ok ? v : 0.0;
       }
-      if (j0 + lane < j1) y[j0 + lane] = yi;
+      double yi = (lane < bw) ? y[j0 + lane] : 0.0;
+#pragma unroll
+      for (int j = kTri - 1; j >= 0; --j) {
+        if (j < bw) {
+          const double xj = readlane_f64(yi, j);
+          if (lane < j) yi -= row[j] * xj;
+        }
+      }
+      if (lane < bw) y[j0 + lane] = yi;
     }
     __syncthreads();
     for (int i = tid; i < j0; i += kAdjThreads) {
       double acc = 0.0;
-      for (int j = j0; j < j1; ++j) acc += A[(int64_t)j * ld + i] * y[j];
+#pragma unroll
+      for (int h = 0; h < kTri; h += kTri / 2) {
+        double v[kTri / 2];
+#pragma unroll
+        for (int j = 0; j < kTri / 2; ++j) {
+          const double x = A[h + j < bw ? (int64_t)(j0 + h + j) * ld + i : 0];
+          v[j] = h + j < bw ? x : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kTri / 2; ++j)
+          if (h + j < bw) acc += v[j] * y[j0 + h + j];
+      }
       y[i] -= acc;
     }
     __syncthreads();
   }
-  // ---- undo the row interchanges (P^T), then mu = S nu
-  if (tid == 0) {
+  // ---- undo the row interchanges (P^T: the swaps kk <-> piv[kk] for kk
+  //      descending): every thread follows its own entries through the swap
+  //      sequence and writes each to its final slot; then mu = S nu
+  for (int q = tid; q < n; q += kAdjThreads) spiv[q] = piv[q];
+  __syncthreads();
+  for (int b0 = 0; b0 < n; b0 += 8 * kAdjThreads) {
+    int pos[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) pos[e] = b0 + tid + kAdjThreads * e;
+#pragma unroll 4
     for (int kk = n - 1; kk >= 0; --kk) {
-      const int p = piv[kk];
-      if (p != kk) {
-        const double t = y[kk];
-        y[kk] = y[p];
-        y[p] = t;
-      }
+      const int p = spiv[kk];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) pos[e] = (pos[e] == kk) ? p : (pos[e] == p ? kk : pos[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int i = b0 + tid + kAdjThreads * e;
+      if (i < n) wI[pos[e]] = y[i];
     }
   }
   __syncthreads();
-  for (int q = tid; q < n; q += kAdjThreads) y[q] *= sc[q];
+  for (int q = tid; q < n; q += kAdjThreads) y[q] = wI[q] * sc[q];
+  __syncthreads();
 
   // ---- local solution at u: w_B = H u_Xi, w_I = W[:, M] - W[:, :M] u_Xi
   const int64_t slo = a.C.knot_off[m];
@@ -267,8 +334,9 @@ pdd_status backward_impl(pdd_system sys, const double* u, const double* lambda, 
     a.u = u;
     a.lambda = lambda;
     for (int k = 0; k < 7; ++k) a.g[k] = g[k];
-    const size_t shm = sizeof(double) * ((size_t)2 * bk.n + bk.Nt + bk.M + (size_t)(bk.Nc + 1) * bk.Nt +
-                                         (size_t)kAdjKnots * (bk.Nc + 1 + bk.Nt) + (size_t)kTri * (kTri + 1));
+    const size_t region = std::max({(size_t)kAdjKnots * (bk.Nc + 1 + bk.Nt) + 4 * kAdjKnots + kAdjKnots / 2,
+                                    (size_t)(bk.Nc + 1) * bk.Nt, ((size_t)bk.n + 1) / 2});
+    const size_t shm = sizeof(double) * ((size_t)2 * bk.n + bk.Nt + bk.M + region);
     if (shm > 160 * 1024) return fail(PDD_EINVAL, "pdd_assemble_G_backward: bucket too large");
     (void)hipFuncSetAttribute((const void*)adjoint_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL(adjoint_kernel, dim3(F.count), dim3(kAdjThreads), shm, st, a);
