@@ -59,8 +59,11 @@ struct LuItem {                // one matrix of a batch (device pointers)
   double* uinv;                //   the inverses of U's 32 x 32 diagonal blocks
   int32_t n, ld, nrhs, cls;    // cls = lu_panel_class(n)
 };
-// launch kinds: the panel kernel per size class, then the tiled kinds
-enum { LU_PUPD, LU_PANEL0, LU_PANEL1, LU_PANEL2, LU_PANEL3, LU_LSWAP, LU_UROW, LU_BDIAG, LU_BUPD, LU_KINDS };
+// launch kinds: the panel kernel per size class, then the tiled kinds (the
+// U-row tiles split into the first tile of each matrix and the rest)
+enum {
+  LU_PUPD, LU_PANEL0, LU_PANEL1, LU_PANEL2, LU_PANEL3, LU_LSWAP, LU_UROW0, LU_UREST, LU_BDIAG, LU_BUPD, LU_KINDS
+};
 int lu_panel_class(int n);
 size_t lu_work_bytes_per_matrix(int32_t n);
 size_t lu_work_header_bytes();   // sizeof(LuWork): the inverses of U's blocks follow

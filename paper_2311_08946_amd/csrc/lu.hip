@@ -25,6 +25,10 @@
 //     [K0, K0 + kb) up to date with one long-K product and forms
 //     U12 = L11^-1 A12 with a second MFMA product -- the right-hand-side
 //     columns are among these tiles and are thereby eliminated forward.
+// Look-ahead: the first U-row tile of step s (the columns of panel s + 1) is a
+// launch of its own; the remaining tiles run on a second stream beside the
+// pre-update, panel and interchanges of step s + 1, which touch other
+// columns (the interchange record and L11^-1 are kept per step parity).
 // The back substitution U W = R' then runs from the bottom in 128-row blocks:
 // lu_bdiag_kernel solves a diagonal block (32-row triangles through the
 // inverses of U's diagonal blocks, stored by the panel kernel, and MFMA
@@ -367,13 +371,15 @@ __device__ __attribute__((always_inline)) void tri_apply(double* __restrict__ A,
 }  // namespace
 
 // Per-matrix work area of one step (global memory).
+// The records read by the U-row tiles are kept for two steps (index: step
+// parity), since the tiles of step s run beside the panel of step s + 1.
 struct LuWork {
-  double linv[kOuter][kOuter];         // L11^-1 (unit lower), zero-padded
+  double linv[2][kOuter][kOuter];      // L11^-1 (unit lower), zero-padded
   double inv[kOuter / kTB][kTB][kTB];  // inverses of L11's unit-lower diagonal blocks
-  int rows[2 * kOuter];                // rows touched by the step's interchanges
-  int src[2 * kOuter];                 // slot whose old contents end up in each slot's row
-  int count;
-  int pad[63];
+  int rows[2][2 * kOuter];             // rows touched by the step's interchanges
+  int src[2][2 * kOuter];              // slot whose old contents end up in each slot's row
+  int count[2];
+  int pad[62];
 };
 static_assert(sizeof(LuWork) % 8 == 0, "the inverses of U's blocks follow LuWork");
 
@@ -654,7 +660,8 @@ __device__ __attribute__((always_inline)) void panel_body(const LuItem& it, int 
     }
     __syncthreads();
   }
-  if (tid == 0) compose_perm(sh.piv, K0, kb, W->rows, W->src, &W->count);
+  const int par = (K0 / kOuter) & 1;
+  if (tid == 0) compose_perm(sh.piv, K0, kb, W->rows[par], W->src[par], &W->count[par]);
   if (tid == 0 && (K0 == 0 || singular)) *it.status = singular;
 }
 
@@ -704,7 +711,7 @@ __device__ __attribute__((always_inline)) void wave_tile(Opnd P, Opnd Q, double 
 __device__ __attribute__((always_inline)) void linv_body(const LuItem& it, int K0) {
   const int n = it.n, ld = it.ld;
   LuWork* W = it.work;
-  double* __restrict__ X = &W->linv[0][0];
+  double* __restrict__ X = &W->linv[(K0 / kOuter) & 1][0][0];
   const int tid = threadIdx.x, w = tid >> 6;
   const int kb = min(kOuter, n - K0);
   auto L = [&](int a, int b) {            // block (a, b), a > b, of L11
@@ -782,10 +789,11 @@ __device__ __attribute__((always_inline)) void urow_body(const LuItem& it, int K
   }
   const int c0 = LEFT ? t * kGT : K0 + kb + t * kGT;
   const int c1 = min(LEFT ? K0 : ld, c0 + kGT);
-  if (tid == 0) perm.count = W->count;
+  const int par = (K0 / kOuter) & 1;
+  if (tid == 0) perm.count = W->count[par];
   for (int e = tid; e < 2 * kOuter; e += kThreads) {
-    perm.rows[e] = W->rows[e];
-    perm.src[e] = W->src[e];
+    perm.rows[e] = W->rows[par][e];
+    perm.src[e] = W->src[par][e];
   }
   __syncthreads();
   apply_perm(A, ld, perm, c0, c1, 0, 0, &u.g.Lt[0][0]);
@@ -794,7 +802,7 @@ __device__ __attribute__((always_inline)) void urow_body(const LuItem& it, int K
   // trailing matrix is never updated as a whole)
   if (K0 > 0) gemm_sub(A, ld, K0, K0 + kb, c0, c1, 0, K0, u.g);
   // U12 = L11^-1 A12 as one MFMA product with the inverse the LEFT launch formed
-  gemm_op<true>(A, ld, K0, K0 + kb, c0, c1, K0, K0 + kb, &W->linv[0][0], kOuter, K0, K0, u.g);
+  gemm_op<true>(A, ld, K0, K0 + kb, c0, c1, K0, K0 + kb, &W->linv[par][0][0], kOuter, K0, K0, u.g);
 }
 
 // Row tile t of the step's panel: the contributions of all earlier steps,
@@ -893,7 +901,9 @@ __global__ __launch_bounds__(kThreads) void lu_panel_wide_kernel(const LuItem* _
 
 // PERSISTENT: each workgroup strides over the list; otherwise one workgroup
 // per work unit (no loop, fewer live registers).
-template <bool PERSISTENT, bool LEFT>
+// OFF: the list's first unit is tile OFF of the matrix (the first tile and
+// the rest of a step's U-row tiles are separate launches).
+template <bool PERSISTENT, bool LEFT, int OFF = 0>
 __global__ __launch_bounds__(kThreads) void lu_urow_kernel(const LuItem* __restrict__ items,
                                                            const int32_t* __restrict__ pre, int count, int step) {
   __shared__ MatLds u;
@@ -903,12 +913,12 @@ __global__ __launch_bounds__(kThreads) void lu_urow_kernel(const LuItem* __restr
     const int gi = xcd_index();
     if (gi >= total) return;
     const int m = owner(pre, count, gi);
-    urow_body<LEFT>(items[m], step * kOuter, gi - pre[m], u, perm);
+    urow_body<LEFT>(items[m], step * kOuter, gi - pre[m] + OFF, u, perm);
     return;
   }
   for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
     const int m = owner(pre, count, gi);
-    urow_body<LEFT>(items[m], step * kOuter, gi - pre[m], u, perm);
+    urow_body<LEFT>(items[m], step * kOuter, gi - pre[m] + OFF, u, perm);
     __syncthreads();
   }
 }
@@ -985,11 +995,18 @@ int lu_plan_tiles(const LuItem& it, int kind, int step) {
     case LU_PANEL0: case LU_PANEL1: case LU_PANEL2: case LU_PANEL3:
       return it.cls == kind - LU_PANEL0 ? 1 : 0;
     case LU_LSWAP: return K0 / kGT + 1;     // the left tiles, then L11^-1
-    case LU_UROW: return (ld - K0 - kb + kGT - 1) / kGT;
+    case LU_UROW0: return (ld - K0 - kb + kGT - 1) / kGT > 0 ? 1 : 0;
+    case LU_UREST: return std::max(0, (ld - K0 - kb + kGT - 1) / kGT - 1);
     case LU_PUPD: return K0 > 0 ? (n - K0 + kGT - 1) / kGT : 0;
     case LU_BDIAG: return 1;
     default: return (nsteps - 1 - step);        // LU_BUPD: row tiles above the block
   }
+}
+
+LuPlan::~LuPlan() {
+  for (auto e : ev_main) (void)hipEventDestroy(e);
+  for (auto e : ev_rest) (void)hipEventDestroy(e);
+  if (side) (void)hipStreamDestroy(side);
 }
 
 void LuPlan::build(const std::vector<LuItem>& its) {
@@ -1008,6 +1025,14 @@ void LuPlan::build(const std::vector<LuItem>& its) {
     }
   d_items.upload(items);
   d_pre.upload(pre);
+  if (!side) PDD_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+  while ((int)ev_main.size() < nsteps) {
+    hipEvent_t a, b;
+    PDD_HIP(hipEventCreateWithFlags(&a, hipEventDisableTiming));
+    PDD_HIP(hipEventCreateWithFlags(&b, hipEventDisableTiming));
+    ev_main.push_back(a);
+    ev_rest.push_back(b);
+  }
 }
 
 int LuPlan::launch(hipStream_t st, int grid_cap) const {
@@ -1015,30 +1040,46 @@ int LuPlan::launch(hipStream_t st, int grid_cap) const {
   int launches = 0;
   typedef void (*Kern)(const LuItem*, const int32_t*, int, int);
   // flat: one workgroup per unit; strided: a capped persistent grid
-  auto go = [&](int kind, int s, Kern flat, Kern strided) {
+  auto go = [&](int kind, int s, Kern flat, Kern strided, hipStream_t q) {
     const int total = totals[(size_t)kind * nsteps + s];
     if (total == 0) return;
     const int32_t* dp = d_pre.ptr<int32_t>() + ((size_t)kind * nsteps + s) * (count + 1);
     if (strided && grid_cap < total)
-      hipLaunchKernelGGL(strided, dim3(grid_cap), dim3(kThreads), 0, st, di, dp, count, s);
+      hipLaunchKernelGGL(strided, dim3(grid_cap), dim3(kThreads), 0, q, di, dp, count, s);
     else if (strided)   // flat tiled launch: grid padded to a multiple of the 8 XCDs
-      hipLaunchKernelGGL(flat, dim3((total + 7) / 8 * 8), dim3(kThreads), 0, st, di, dp, count, s);
+      hipLaunchKernelGGL(flat, dim3((total + 7) / 8 * 8), dim3(kThreads), 0, q, di, dp, count, s);
     else
-      hipLaunchKernelGGL(flat, dim3(total), dim3(kThreads), 0, st, di, dp, count, s);
+      hipLaunchKernelGGL(flat, dim3(total), dim3(kThreads), 0, q, di, dp, count, s);
     ++launches;
   };
+  // Look-ahead: the first U-row tile of step s (the columns of panel s + 1)
+  // runs in order on st; the rest of the step's tiles run on the second stream
+  // beside panel s + 1 and its pre-update and interchanges, which touch
+  // other columns.  The first tile of step s + 1 waits for them (it covers
+  // columns they bring up to date).
+  int rest = -1;
   for (int s = 0; s < nsteps; ++s) {
-    go(LU_PUPD, s, lu_pupd_kernel<false>, lu_pupd_kernel<true>);
-    go(LU_PANEL0, s, lu_panel_kernel<1, 16>, nullptr);
-    go(LU_PANEL1, s, lu_panel_kernel<2, 16>, nullptr);
-    go(LU_PANEL2, s, lu_panel_wide_kernel<4, 16>, nullptr);
-    go(LU_PANEL3, s, lu_panel_wide_kernel<8, 8>, nullptr);
-    go(LU_LSWAP, s, lu_urow_kernel<false, true>, lu_urow_kernel<true, true>);
-    go(LU_UROW, s, lu_urow_kernel<false, false>, lu_urow_kernel<true, false>);
+    go(LU_PUPD, s, lu_pupd_kernel<false>, lu_pupd_kernel<true>, st);
+    go(LU_PANEL0, s, lu_panel_kernel<1, 16>, nullptr, st);
+    go(LU_PANEL1, s, lu_panel_kernel<2, 16>, nullptr, st);
+    go(LU_PANEL2, s, lu_panel_wide_kernel<4, 16>, nullptr, st);
+    go(LU_PANEL3, s, lu_panel_wide_kernel<8, 8>, nullptr, st);
+    go(LU_LSWAP, s, lu_urow_kernel<false, true>, lu_urow_kernel<true, true>, st);
+    if (rest >= 0) PDD_HIP(hipStreamWaitEvent(st, ev_rest[rest], 0));
+    rest = -1;
+    go(LU_UROW0, s, lu_urow_kernel<false, false, 0>, lu_urow_kernel<true, false, 0>, st);
+    if (totals[(size_t)LU_UREST * nsteps + s] > 0) {
+      PDD_HIP(hipEventRecord(ev_main[s], st));
+      PDD_HIP(hipStreamWaitEvent(side, ev_main[s], 0));
+      go(LU_UREST, s, lu_urow_kernel<false, false, 1>, lu_urow_kernel<true, false, 1>, side);
+      PDD_HIP(hipEventRecord(ev_rest[s], side));
+      rest = s;
+    }
   }
+  if (rest >= 0) PDD_HIP(hipStreamWaitEvent(st, ev_rest[rest], 0));
   for (int s = 0; s < nsteps; ++s) {
-    go(LU_BDIAG, s, lu_bdiag_kernel, nullptr);
-    go(LU_BUPD, s, lu_bupd_kernel<false>, lu_bupd_kernel<true>);
+    go(LU_BDIAG, s, lu_bdiag_kernel, nullptr, st);
+    go(LU_BUPD, s, lu_bupd_kernel<false>, lu_bupd_kernel<true>, st);
   }
   return launches;
 }

@@ -114,9 +114,18 @@ struct LuPlan {
   std::vector<int32_t> pre;      // [kind][step][count + 1]
   std::vector<int32_t> totals;   // [kind][step]
   DevBuf d_items, d_pre;
+  // the second stream of the look-ahead and its per-step events
+  hipStream_t side = nullptr;
+  std::vector<hipEvent_t> ev_main, ev_rest;
+  LuPlan() = default;
+  LuPlan(const LuPlan&) = delete;
+  LuPlan& operator=(const LuPlan&) = delete;
+  ~LuPlan();
   void build(const std::vector<LuItem>& its);
-  // Issues the launch sequence on st; grid_cap bounds the workgroups of the
-  // tiled launches (each workgroup strides over the list).  Returns launches.
+  // Issues the launch sequence on st (and the plan's second stream, joined
+  // back into st before the back substitution); grid_cap bounds the
+  // workgroups of the tiled launches (each workgroup strides over the list).
+  // Returns launches.
   int launch(hipStream_t st, int grid_cap) const;
 };
 
