@@ -177,10 +177,23 @@ __global__ __launch_bounds__(256) void colloc_build_kernel(BucketTables T, Chunk
     v.y = scale * s_row[col + 1];
     *reinterpret_cast<double2*>(row + col) = v;
   }
-  for (int j = lane; j < M; j += kWave) {
-    double v = 0.0;
-    for (int lp = 0; lp < Nt; ++lp) v += s_ring[lp] * T.H[(int64_t)lp * M + j];
-    row[n + j] = scale * v;
+  if (mixed) {
+    for (int j = lane; j < M; j += kWave) {
+      double v = 0.0;
+      for (int lp = 0; lp < Nt; ++lp) v += s_ring[lp] * T.H[(int64_t)lp * M + j];
+      row[n + j] = scale * v;
+    }
+  } else {
+    // the ring holds two entries, at l and l + half: the same two products,
+    // in the same order, as the dense sum
+    const int lh = (l + half) % Nt;
+    const int a = min(l, lh), b = max(l, lh);
+    const double ra = s_ring[a], rb = s_ring[b];
+    for (int j = lane; j < M; j += kWave) {
+      double v = ra * T.H[(int64_t)a * M + j];
+      v += rb * T.H[(int64_t)b * M + j];
+      row[n + j] = scale * v;
+    }
   }
   if (lane == 0) row[n + M] = -scale * ff;
   for (int col = n + M + 1 + lane; col < ld; col += kWave) row[col] = 0.0;
