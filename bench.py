@@ -31,6 +31,13 @@ PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
+# HBM bytes of one LU phase (all LU launches of a step), from two rocprofv3 --pmc passes
+# (FETCH_SIZE, WRITE_SIZE) over this script, each scaled by what the counter reads for a
+# copy of known size: profiles/hbm_traffic_lu_32x32_n1024.md.  Valid for the kernels the
+# counters were taken on; a changed LU kernel needs a new pass (else None).
+LU_TRAFFIC_BYTES = {"config2": 1.081e11}
+
+
 def lu_flops(n, nrhs):
     """Algorithmic flops of one unit (one circle) of the LU launch: factorisation
     of the n x n collocation matrix (2/3 n^3), forward elimination of its nrhs
@@ -220,12 +227,12 @@ def main():
     path_steps = st[-1].path_steps
     flops = spectral_flops(cover, cfg)
     achieved = flops / (ms_lu * 1e-3) / 1e12
+    kernels = "lu_pupd/lu_panel/lu_urow (interchanges + L11^-1, first tile, other tiles)/lu_bdiag/lu_bupd kernels"
     if args.workload == "config2":
         kernel = ("batched LU + triangular solves of 900 circles (n=1024, 65 right-hand sides): "
-                  "lu_panel/lu_urow/lu_update/lu_bdiag/lu_bupd kernels, 38 launches")
+                  + kernels + ", 53 launches per step on two streams")
     else:
-        kernel = (f"batched LU + triangular solves of {n_float} circles: "
-                  "lu_panel/lu_urow/lu_update/lu_bdiag/lu_bupd kernels")
+        kernel = f"batched LU + triangular solves of {n_float} circles: " + kernels
     out = {
         "metric": "G assembly circles/s + MC path-steps/s at fixed error; fwd+adjoint seconds",
         "value": n_circles / dt,
@@ -259,7 +266,9 @@ def main():
             "bound": "mfma",
             "kernel": kernel,
             "achieved": achieved, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_MFMA_TFLOPS, "traffic": None,
+            "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
+            "traffic": LU_TRAFFIC_BYTES.get(args.workload),
+            "traffic_unit": "HBM bytes per LU phase (one step), rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0",
         },
     }
     if with_adj:
