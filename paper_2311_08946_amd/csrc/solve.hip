@@ -4,15 +4,18 @@
 // 42-45); C has a unit diagonal, and plain BiCGStab converges in tens of
 // iterations on the covers here.
 //
-// One iteration: p = r + beta (p - omega v); v = C p with per-block partial
-// sums of (r0, v); t = C s with s = r - alpha v formed on the fly and partial
-// sums of (t, s), (t, t); the x and r updates with partial sums of (r, r) and
-// (r0, r).  After each reducing kernel a one-workgroup kernel adds the
-// partials in a fixed order and updates the scalars (alpha, omega, beta, the
-// stopping test), so results are bitwise reproducible.  Every kernel returns at
-// once after the stopping test has fired, which lets the host enqueue several
-// iterations per status read.  Sparse rows are handled by 16-lane groups (four
-// rows per wavefront).
+// One iteration is four launches: p = r + beta (p - omega v); v = C p with
+// per-workgroup partial sums of (r0, v); t = C s with s = r - alpha v formed on
+// the fly and partial sums of (t, s), (t, t); the x and r updates with partial
+// sums of (r, r) and (r0, r).  Each kernel's workgroups first add the partial
+// sums of the kernel before it -- every workgroup the same partials in the
+// same fixed order, so all derive the same scalars (alpha, omega, beta, the
+// stopping test) and results are bitwise reproducible without a separate
+// reduction launch; workgroup 0 records them.  Every kernel returns at once
+// after the stopping test has fired, which lets the host enqueue several
+// iterations per status read; a one-workgroup status kernel per batch adds
+// the last partials for the host.  Sparse rows are handled by 16-lane groups
+// (64 rows per 1024-thread workgroup, so that few partial sums are re-added).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,13 +28,14 @@ namespace pdd {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kRowsPerBlock = 16;   // 16 lanes per row, 4 rows per wavefront
+constexpr int kThreads = 256;        // vector kernels: one entry per thread
+constexpr int kSpThreads = 1024;     // sparse kernels: 16 lanes per row
+constexpr int kRowsPerBlock = kSpThreads / 16;
 constexpr int kItersPerSync = 8;
 
 enum {
   S_RHO = 0, S_ALPHA, S_OMEGA, S_BETA, S_RV, S_TS, S_TT, S_RR, S_BB, S_TOL2, S_DONE, S_FAIL,
-  S_ITER, S_COUNT
+  S_ITER, S_RHO_PREV, S_COUNT
 };
 
 struct SolveCtx {
@@ -45,10 +49,14 @@ struct SolveCtx {
   double* p;
   double* v;
   double* t;
-  double* part;        // [2][nblocks] per-block partial sums
-  int nblocks;         // grid of the row kernels (one block per 16 rows)
-  int vblocks;         // grid of the element kernels (one block per 256 entries)
-  double* sc;          // scalars
+  double* part_i;      // [2][nblocks] init: (b, b), (r, r)
+  double* part_v;      // [nblocks]    spmv_v: (r0, v)
+  double* part_t;      // [2][nblocks] spmv_t: (t, s), (t, t)
+  double* part_x;      // [2][vblocks] update_xr: (r, r), (r0, r)
+  int nblocks;         // grid of the sparse kernels (one workgroup per 64 rows)
+  int vblocks;         // grid of the vector kernels (one workgroup per 256 entries)
+  double* sc;          // scalars, written by workgroup 0 of the kernel that derives them
+  double* status;      // the host's record: the state after the last finished iteration
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -56,14 +64,26 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Block sum in a fixed order (wave sums, then the four wave totals in order).
-__device__ __forceinline__ double block_sum(double v, double* s4) {
+// Workgroup sum in a fixed order (wave sums, then the wave totals in order).
+template <int NW>
+__device__ __forceinline__ double block_sum(double v, double* s) {
   v = wave_sum(v);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __syncthreads();
-  if (lane == 0) s4[w] = v;
+  if (lane == 0) s[w] = v;
   __syncthreads();
-  return s4[0] + s4[1] + s4[2] + s4[3];
+  double t = 0.0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) t += s[k];
+  return t;
+}
+
+// Sum of part[0:n) in a fixed order (the same in every workgroup of a grid).
+template <int NW>
+__device__ __forceinline__ double sum_parts(const double* __restrict__ part, int n, double* s) {
+  double a = 0.0;
+  for (int i = threadIdx.x; i < n; i += 64 * NW) a += part[i];
+  return block_sum<NW>(a, s);
 }
 
 // Row of a 16-lane group: sum_k val[k] (y - beta z)[cols[k]], reduced inside the group.
@@ -81,9 +101,9 @@ __device__ __forceinline__ double row16(const SolveCtx& c, int64_t row, const do
   return acc;
 }
 
-__global__ __launch_bounds__(kThreads) void init_kernel(SolveCtx c, const double* __restrict__ b,
-                                                        int use_guess) {
-  __shared__ double s4[4];
+__global__ __launch_bounds__(kSpThreads) void init_kernel(SolveCtx c, const double* __restrict__ b,
+                                                          int use_guess) {
+  __shared__ double s16[16];
   const int sub = threadIdx.x & 15;
   const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 4);
   // r = b - C x (x = 0 unless a guess is given)
@@ -99,85 +119,88 @@ __global__ __launch_bounds__(kThreads) void init_kernel(SolveCtx c, const double
     pbb = b[row] * b[row];
     prr = ri * ri;
   }
-  const double sbb = block_sum(pbb, s4);
-  __syncthreads();
-  const double srr = block_sum(prr, s4);
+  const double sbb = block_sum<16>(pbb, s16);
+  const double srr = block_sum<16>(prr, s16);
   if (threadIdx.x == 0) {
-    c.part[blockIdx.x] = sbb;
-    c.part[c.nblocks + blockIdx.x] = srr;
+    c.part_i[blockIdx.x] = sbb;
+    c.part_i[c.nblocks + blockIdx.x] = srr;
   }
 }
 
-// Adds the partial sums of the previous kernel (fixed order) and updates the
-// scalars: stage 0 after init, 1 after v = C p, 2 after t = C s, 3 after the
-// x and r updates.
-__global__ __launch_bounds__(1024) void finalize_kernel(SolveCtx c, int nparts, int stage, double rtol) {
-  __shared__ double s16[16];
-  double* sc = c.sc;
-  if (stage != 0 && sc[S_DONE] != 0.0) return;
-  double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += 1024) {
-    a += c.part[i];
-    b += c.part[nparts + i];
+// The scalars after an x, r update (or after init when FIRST): the stopping
+// test and beta.  Run by every thread of every workgroup of the caller on the
+// same partials; returns true if the iteration goes on.  REC: record them
+// (workgroup 0 of update_p writes sc; the status kernel writes the host's
+// record and leaves sc alone).
+struct Next {
+  double rr, rho, beta, bb, tol2, iter;
+  bool done, fail;
+};
+
+template <int NW>
+__device__ Next next_state(const SolveCtx& c, bool first, double rtol, double* s) {
+  const double* sc = c.sc;
+  Next z{};
+  if (first) {
+    z.bb = sum_parts<NW>(c.part_i, c.nblocks, s);
+    z.rr = sum_parts<NW>(c.part_i + c.nblocks, c.nblocks, s);
+    z.rho = z.rr;                    // (r0, r) with r0 = r
+    z.beta = 0.0;
+    z.tol2 = rtol * rtol * z.bb;
+    z.iter = 0.0;
+    z.done = z.rr <= z.tol2;
+    z.fail = false;
+    return z;
   }
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  a = wave_sum(a);
-  b = wave_sum(b);
-  if (lane == 0) s16[w] = a;
-  __syncthreads();
-  double sa = 0.0;
-  for (int t = 0; t < 16; ++t) sa += s16[t];
-  __syncthreads();
-  if (lane == 0) s16[w] = b;
-  __syncthreads();
-  double sb = 0.0;
-  for (int t = 0; t < 16; ++t) sb += s16[t];
-  if (threadIdx.x != 0) return;
-  if (stage == 0) {
-    sc[S_BB] = sa;
-    sc[S_RR] = sb;
-    sc[S_RHO] = sb;           // (r0, r) with r0 = r
-    sc[S_ALPHA] = 1.0;
-    sc[S_OMEGA] = 1.0;
-    sc[S_BETA] = 0.0;
-    sc[S_TOL2] = rtol * rtol * sa;
-    sc[S_DONE] = (sb <= sc[S_TOL2]) ? 1.0 : 0.0;
-    sc[S_FAIL] = 0.0;
-    sc[S_ITER] = 0.0;
-  } else if (stage == 1) {
-    sc[S_RV] = sa;
-    sc[S_ALPHA] = sc[S_RHO] / sa;
-  } else if (stage == 2) {
-    sc[S_TS] = sa;
-    sc[S_TT] = sb;
-    sc[S_OMEGA] = (sb > 0.0) ? sa / sb : 0.0;
-  } else {
-    const double rr = sa, rho = sb;
-    sc[S_BETA] = (rho / sc[S_RHO]) * (sc[S_ALPHA] / sc[S_OMEGA]);
-    sc[S_RHO] = rho;
-    sc[S_RR] = rr;
-    sc[S_ITER] += 1.0;
-    const bool bad = !(rr == rr) || !isfinite(sc[S_BETA]) || sc[S_OMEGA] == 0.0 || rho == 0.0;
-    if (rr <= sc[S_TOL2]) {
-      sc[S_DONE] = 1.0;
-    } else if (bad) {
-      sc[S_DONE] = 1.0;
-      sc[S_FAIL] = 1.0;
-    }
+  z.rr = sum_parts<NW>(c.part_x, c.vblocks, s);
+  z.rho = sum_parts<NW>(c.part_x + c.vblocks, c.vblocks, s);
+  z.bb = sc[S_BB];
+  z.tol2 = sc[S_TOL2];
+  z.beta = (z.rho / sc[S_RHO_PREV]) * (sc[S_ALPHA] / sc[S_OMEGA]);
+  z.iter = sc[S_ITER] + 1.0;
+  const bool bad = !(z.rr == z.rr) || !isfinite(z.beta) || sc[S_OMEGA] == 0.0 || z.rho == 0.0;
+  z.done = z.rr <= z.tol2 || bad;
+  z.fail = !(z.rr <= z.tol2) && bad;
+  return z;
+}
+
+__device__ void record(double* rec, const Next& z, bool first) {
+  rec[S_RR] = z.rr;
+  rec[S_ITER] = z.iter;
+  rec[S_DONE] = z.done ? 1.0 : 0.0;
+  rec[S_FAIL] = z.fail ? 1.0 : 0.0;
+  if (first) {
+    rec[S_BB] = z.bb;
+    rec[S_TOL2] = z.tol2;
+    rec[S_ALPHA] = 1.0;
+    rec[S_OMEGA] = 1.0;
+  }
+  if (!z.done) {
+    rec[S_RHO] = z.rho;
+    rec[S_BETA] = z.beta;
   }
 }
 
-__global__ __launch_bounds__(kThreads) void update_p_kernel(SolveCtx c) {
-  if (c.sc[S_DONE] != 0.0) return;
+// p = r + beta (p - omega v), after the scalars of the previous x, r update.
+__global__ __launch_bounds__(kThreads) void update_p_kernel(SolveCtx c, int first, double rtol) {
+  __shared__ double s4[4];
+  __shared__ int stop;
+  // workgroup 0 may set S_DONE while others start: read it once per workgroup
+  if (threadIdx.x == 0) stop = (!first && c.sc[S_DONE] != 0.0) ? 1 : 0;
+  __syncthreads();
+  if (stop) return;
+  const Next z = next_state<4>(c, first != 0, rtol, s4);
+  if (blockIdx.x == 0 && threadIdx.x == 0) record(c.sc, z, first != 0);
+  if (z.done) return;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= c.N) return;
-  const double beta = c.sc[S_BETA], omega = c.sc[S_OMEGA];
-  c.p[i] = c.r[i] + beta * (c.p[i] - omega * c.v[i]);
+  const double omega = first ? 1.0 : c.sc[S_OMEGA];
+  c.p[i] = c.r[i] + z.beta * (c.p[i] - omega * c.v[i]);
 }
 
 // v = C p, partial sums of (r0, v)
-__global__ __launch_bounds__(kThreads) void spmv_v_kernel(SolveCtx c) {
-  __shared__ double s4[4];
+__global__ __launch_bounds__(kSpThreads) void spmv_v_kernel(SolveCtx c) {
+  __shared__ double s16[16];
   if (c.sc[S_DONE] != 0.0) return;
   const int sub = threadIdx.x & 15;
   const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 4);
@@ -187,18 +210,20 @@ __global__ __launch_bounds__(kThreads) void spmv_v_kernel(SolveCtx c) {
     c.v[row] = vi;
     prv = c.r0[row] * vi;
   }
-  const double s = block_sum(prv, s4);
-  if (threadIdx.x == 0) {
-    c.part[blockIdx.x] = s;
-    c.part[c.nblocks + blockIdx.x] = 0.0;
-  }
+  const double sv = block_sum<16>(prv, s16);
+  if (threadIdx.x == 0) c.part_v[blockIdx.x] = sv;
 }
 
-// t = C s with s = r - alpha v, partial sums of (t, s) and (t, t)
-__global__ __launch_bounds__(kThreads) void spmv_t_kernel(SolveCtx c) {
-  __shared__ double s4[4];
+// alpha = rho / (r0, v); t = C s with s = r - alpha v, partial sums of (t, s) and (t, t)
+__global__ __launch_bounds__(kSpThreads) void spmv_t_kernel(SolveCtx c) {
+  __shared__ double s16[16];
   if (c.sc[S_DONE] != 0.0) return;
-  const double alpha = c.sc[S_ALPHA];
+  const double rv = sum_parts<16>(c.part_v, c.nblocks, s16);
+  const double alpha = c.sc[S_RHO] / rv;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c.sc[S_RV] = rv;
+    c.sc[S_ALPHA] = alpha;
+  }
   const int sub = threadIdx.x & 15;
   const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 4);
   const double ti = row16(c, row, c.r, c.v, alpha, sub);
@@ -209,20 +234,29 @@ __global__ __launch_bounds__(kThreads) void spmv_t_kernel(SolveCtx c) {
     pts = ti * si;
     ptt = ti * ti;
   }
-  const double sts = block_sum(pts, s4);
-  __syncthreads();
-  const double stt = block_sum(ptt, s4);
+  const double sts = block_sum<16>(pts, s16);
+  const double stt = block_sum<16>(ptt, s16);
   if (threadIdx.x == 0) {
-    c.part[blockIdx.x] = sts;
-    c.part[c.nblocks + blockIdx.x] = stt;
+    c.part_t[blockIdx.x] = sts;
+    c.part_t[c.nblocks + blockIdx.x] = stt;
   }
 }
 
-// x += alpha p + omega s; r = s - omega t; partial sums of (r, r) and (r0, r)
+// omega = (t, s) / (t, t); x += alpha p + omega s; r = s - omega t; partial
+// sums of (r, r) and (r0, r)
 __global__ __launch_bounds__(kThreads) void update_xr_kernel(SolveCtx c) {
   __shared__ double s4[4];
   if (c.sc[S_DONE] != 0.0) return;
-  const double alpha = c.sc[S_ALPHA], omega = c.sc[S_OMEGA];
+  const double ts = sum_parts<4>(c.part_t, c.nblocks, s4);
+  const double tt = sum_parts<4>(c.part_t + c.nblocks, c.nblocks, s4);
+  const double omega = (tt > 0.0) ? ts / tt : 0.0;
+  const double alpha = c.sc[S_ALPHA];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c.sc[S_TS] = ts;
+    c.sc[S_TT] = tt;
+    c.sc[S_OMEGA] = omega;
+    c.sc[S_RHO_PREV] = c.sc[S_RHO];    // update_p replaces S_RHO while its workgroups read this
+  }
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   double prr = 0.0, prho = 0.0;
   if (i < c.N) {
@@ -233,12 +267,26 @@ __global__ __launch_bounds__(kThreads) void update_xr_kernel(SolveCtx c) {
     prr = ri * ri;
     prho = c.r0[i] * ri;
   }
-  const double srr = block_sum(prr, s4);
-  __syncthreads();
-  const double srho = block_sum(prho, s4);
+  const double srr = block_sum<4>(prr, s4);
+  const double srho = block_sum<4>(prho, s4);
   if (threadIdx.x == 0) {
-    c.part[blockIdx.x] = srr;
-    c.part[c.vblocks + blockIdx.x] = srho;
+    c.part_x[blockIdx.x] = srr;
+    c.part_x[c.vblocks + blockIdx.x] = srho;
+  }
+}
+
+// The host's record after a batch: the state sc holds once stopped, else the
+// one the next update_p would derive (sc is not touched).
+__global__ __launch_bounds__(kThreads) void status_kernel(SolveCtx c, int first, double rtol) {
+  __shared__ double s4[4];
+  if (!first && c.sc[S_DONE] != 0.0) {
+    if (threadIdx.x < S_COUNT) c.status[threadIdx.x] = c.sc[threadIdx.x];
+    return;
+  }
+  const Next z = next_state<4>(c, first != 0, rtol, s4);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < S_COUNT; ++k) c.status[k] = c.sc[k];
+    record(c.status, z, first != 0);
   }
 }
 
@@ -302,18 +350,21 @@ pdd_status solve_impl(pdd_system sys, const double* rhs, double* u, int32_t tran
   const double* b = rhs ? rhs : sys->b.ptr<double>();
   c.nblocks = (int)((N + kRowsPerBlock - 1) / kRowsPerBlock);
   c.vblocks = (int)((N + kThreads - 1) / kThreads);
-  const size_t wbytes = sizeof(double) * (5 * N + 2 * (int64_t)c.nblocks + S_COUNT);
+  const size_t wbytes = sizeof(double) * (5 * N + 5 * (int64_t)c.nblocks + 2 * (int64_t)c.vblocks + 2 * S_COUNT);
   if (sys->solve_work.bytes() < wbytes) sys->solve_work.alloc(wbytes);
   c.r = sys->solve_work.ptr<double>();
   c.r0 = c.r + N;
   c.p = c.r0 + N;
   c.v = c.p + N;
   c.t = c.v + N;
-  c.part = c.t + N;
-  c.sc = c.part + 2 * (int64_t)c.nblocks;
+  c.part_i = c.t + N;
+  c.part_v = c.part_i + 2 * (int64_t)c.nblocks;
+  c.part_t = c.part_v + c.nblocks;
+  c.part_x = c.part_t + 2 * (int64_t)c.nblocks;
+  c.sc = c.part_x + 2 * (int64_t)c.vblocks;
+  c.status = c.sc + S_COUNT;
   const dim3 rb(c.nblocks), vb(c.vblocks);
-  hipLaunchKernelGGL(init_kernel, rb, dim3(kThreads), 0, st, c, b, guess ? 1 : 0);
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, st, c, c.nblocks, 0, rtol);
+  hipLaunchKernelGGL(init_kernel, rb, dim3(kSpThreads), 0, st, c, b, guess ? 1 : 0);
   // Batches of kItersPerSync iterations; the convergence record of batch k is
   // copied to pinned host memory and read while batch k + 1 already runs (the
   // iteration kernels return at once after convergence, so a batch enqueued
@@ -335,17 +386,15 @@ pdd_status solve_impl(pdd_system sys, const double* rhs, double* u, int32_t tran
   auto enqueue_batch = [&](int sl) {
     const int batch = std::min(kItersPerSync, max_iter - enq);
     for (int k = 0; k < batch; ++k) {
-      hipLaunchKernelGGL(update_p_kernel, vb, dim3(kThreads), 0, st, c);
-      hipLaunchKernelGGL(spmv_v_kernel, rb, dim3(kThreads), 0, st, c);
-      hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, st, c, c.nblocks, 1, rtol);
-      hipLaunchKernelGGL(spmv_t_kernel, rb, dim3(kThreads), 0, st, c);
-      hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, st, c, c.nblocks, 2, rtol);
+      hipLaunchKernelGGL(update_p_kernel, vb, dim3(kThreads), 0, st, c, enq + k == 0 ? 1 : 0, rtol);
+      hipLaunchKernelGGL(spmv_v_kernel, rb, dim3(kSpThreads), 0, st, c);
+      hipLaunchKernelGGL(spmv_t_kernel, rb, dim3(kSpThreads), 0, st, c);
       hipLaunchKernelGGL(update_xr_kernel, vb, dim3(kThreads), 0, st, c);
-      hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, st, c, c.vblocks, 3, rtol);
     }
     enq += batch;
+    hipLaunchKernelGGL(status_kernel, dim3(1), dim3(kThreads), 0, st, c, enq == 0 ? 1 : 0, rtol);
     PDD_HIP(hipGetLastError());
-    PDD_HIP(hipMemcpyAsync(pin.p + sl * S_COUNT, c.sc, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
+    PDD_HIP(hipMemcpyAsync(pin.p + sl * S_COUNT, c.status, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
     PDD_HIP(hipEventRecord(pin.ev[sl], st));
   };
   enqueue_batch(slot);
