@@ -64,7 +64,8 @@ def run_gpu(cfg, steps, warmup, with_adjoint=True, budget=0, plan="batched"):
     xy_d = torch.tensor(xy, dtype=torch.float64, device=dev)
     noise = workloads.target_noise({"noise_seed": cfg.get("noise_seed", 20),
                                     "noise_std": cfg.get("noise_std", 1e-3)}, cover.N)
-    target = pdd.eval_field(prob, "u", xy_d) + torch.tensor(noise, dtype=torch.float64, device=dev)
+    exact = pdd.eval_field(prob, "u", xy_d)
+    target = exact + torch.tensor(noise, dtype=torch.float64, device=dev)
 
     def step():
         sysm = pdd.System(cover, prob, cfg["mc"], keep_factors=with_adjoint, hbm_budget_bytes=budget,
@@ -75,7 +76,8 @@ def run_gpu(cfg, steps, warmup, with_adjoint=True, budget=0, plan="batched"):
             g = 2.0 * (u - target)
             lam, si_t = sysm.solve(rhs=g, transpose=True)
             grads = sysm.backward(u, lam)
-            res.update(iters=si.iterations, iters_t=si_t.iterations, rel=si.rel_residual)
+            res.update(iters=si.iterations, iters_t=si_t.iterations, rel=si.rel_residual,
+                       rms=float(torch.sqrt(torch.mean((u - exact) ** 2))))
         return res
 
     for _ in range(warmup):
@@ -150,6 +152,10 @@ WORKLOADS = {
     "config5": dict(adjoint=True, budget=8 << 30,
                     label="Laplace on a 128x128 cover, M=64, Ntheta=48, Nr=12 (n=576), 1e5 paths/knot, "
                           "h=1e-5; LU factors recomputed in chunks under an 8 GiB budget"),
+    "paper50": dict(adjoint=True, budget=0,
+                    label="Section 4 test problem: Poisson with the exact solution of eq. 46 on [-50,50]^2, "
+                          "10x10 circles r in [8.55, 9.43], M=Ntheta=44, Nr=22 (n=968), c^2=1.5, "
+                          "5000 paths/perimeter knot, h=0.015 (plain Euler)"),
 }
 
 
@@ -274,6 +280,7 @@ def main():
     if with_adj:
         out["solve_iterations"] = results[-1]["iters"]
         out["solve_iterations_transpose"] = results[-1]["iters_t"]
+        out["rms_error_vs_exact"] = results[-1]["rms"]
     if args.per_circle:
         out["per_circle_vs_batched"] = per_circle_comparison(max(1, min(args.steps, 2)))
     if not args.no_cpu_baseline:

@@ -78,7 +78,10 @@ enum {
   PDD_FIELD_SINSUM = 1,    /* base + sum_q a_q sin(2 pi (b_q x + c_q y) + d_q),
                               then min(., 0) if clip_nonpos                           */
   PDD_FIELD_CPOLY_RE = 2,  /* Re sum_k (a_k + i b_k) (x + i y)^k, k < n_terms        */
-  PDD_FIELD_DERIVED_F = 3  /* f = -(L u + c u) for the problem's manufactured u      */
+  PDD_FIELD_DERIVED_F = 3, /* f = -(L u + c u) for the problem's manufactured u      */
+  PDD_FIELD_EQ46 = 4       /* the manufactured solution of Section 4 (eq. 46), no
+                              parameters: 3 + sin(sqrt(1 + x^2/100 + y^2/50))/3
+                              + tanh(sin(3x/25 + y/20) + sin(x/20 - 3y/25))/3       */
 };
 #define PDD_MAX_TERMS 16
 
@@ -97,7 +100,7 @@ typedef struct pdd_field {
 } pdd_field;
 
 /* The model problem of eq. 1.  `u` is the manufactured solution used by
- * PDD_FIELD_DERIVED_F (SINSUM or CPOLY_RE); otherwise it is ignored. */
+ * PDD_FIELD_DERIVED_F (SINSUM, CPOLY_RE or EQ46); otherwise it is ignored. */
 typedef struct pdd_problem {
   pdd_domain domain;
   pdd_field axx, axy, ayy, bx, by, c, f, g, u;

@@ -37,6 +37,42 @@ def _cpoly(fd, z):
     return p, dp, d2p
 
 
+def _eq46(x, y):
+    """The manufactured solution of Section 4, eq. 46, with its first and
+    second derivatives (chain rule on rho = sqrt(1 + x^2/100 + y^2/50) and on
+    s = sin(3x/25 + y/20) + sin(x/20 - 3y/25)):
+    u = 3 + sin(rho)/3 + tanh(s)/3."""
+    q = 1.0 + x * x / 100.0 + y * y / 50.0
+    rho = np.sqrt(q)
+    # derivatives of q, then of rho = q^(1/2)
+    qx, qy, qxx, qyy = x / 50.0, y / 25.0, 1.0 / 50.0, 1.0 / 25.0
+    rx, ry = qx / (2.0 * rho), qy / (2.0 * rho)
+    rxx = qxx / (2.0 * rho) - qx * qx / (4.0 * rho ** 3)
+    ryy = qyy / (2.0 * rho) - qy * qy / (4.0 * rho ** 3)
+    rxy = -qx * qy / (4.0 * rho ** 3)
+    # s and its derivatives: d(alpha) = (3/25, 1/20), d(beta) = (1/20, -3/25)
+    a1, a2 = 3.0 / 25.0, 1.0 / 20.0
+    b1, b2 = 1.0 / 20.0, -3.0 / 25.0
+    alpha = a1 * x + a2 * y
+    beta = b1 * x + b2 * y
+    s = np.sin(alpha) + np.sin(beta)
+    sx = a1 * np.cos(alpha) + b1 * np.cos(beta)
+    sy = a2 * np.cos(alpha) + b2 * np.cos(beta)
+    sxx = -a1 * a1 * np.sin(alpha) - b1 * b1 * np.sin(beta)
+    syy = -a2 * a2 * np.sin(alpha) - b2 * b2 * np.sin(beta)
+    sxy = -a1 * a2 * np.sin(alpha) - b1 * b2 * np.sin(beta)
+    t = np.tanh(s)
+    dt = 1.0 - t * t              # tanh'
+    d2t = -2.0 * t * dt           # tanh''
+    u = 3.0 + (np.sin(rho) + t) / 3.0
+    ux = (np.cos(rho) * rx + dt * sx) / 3.0
+    uy = (np.cos(rho) * ry + dt * sy) / 3.0
+    uxx = (-np.sin(rho) * rx * rx + np.cos(rho) * rxx + d2t * sx * sx + dt * sxx) / 3.0
+    uxy = (-np.sin(rho) * rx * ry + np.cos(rho) * rxy + d2t * sx * sy + dt * sxy) / 3.0
+    uyy = (-np.sin(rho) * ry * ry + np.cos(rho) * ryy + d2t * sy * sy + dt * syy) / 3.0
+    return u, ux, uy, uxx, uxy, uyy
+
+
 def value(fd, x, y, problem=None):
     """Field value at points (x, y)."""
     x = np.asarray(x, dtype=np.float64)
@@ -52,6 +88,8 @@ def value(fd, x, y, problem=None):
     if kind == "cpoly_re":
         p, _, _ = _cpoly(fd, x + 1j * y)
         return p.real
+    if kind == "eq46":
+        return _eq46(x, y)[0]
     if kind == "derived_f":
         if problem is None:
             raise ValueError("derived_f needs the problem's coefficient fields")
@@ -82,6 +120,8 @@ def jet(fd, x, y):
         # u_xx = Re p'', u_xy = -Im p'', u_yy = -Re p''.
         p, dp, d2p = _cpoly(fd, x + 1j * y)
         return p.real, dp.real, -dp.imag, d2p.real, -d2p.imag, -d2p.real
+    if kind == "eq46":
+        return _eq46(x, y)
     if kind == "const":
         z = np.zeros(np.broadcast(x, y).shape)
         return z + fd["value"], z, z, z, z, z

@@ -189,6 +189,8 @@ def _field(fd, keep):
         f.a, f.b = (_dptr(a) for a in arrs)
     elif kind == "derived_f":
         f.kind = 3
+    elif kind == "eq46":
+        f.kind = 4
     else:
         raise ValueError(kind)
     if f.n_terms > MAX_TERMS:

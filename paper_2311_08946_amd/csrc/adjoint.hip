@@ -109,7 +109,10 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))
     const double hstep = kTwoPiD / Nt;
     for (int idx = tid; idx < cnt * Nt; idx += kAdjThreads) {
       const int t = idx / Nt, l = idx - t * Nt;
-      const double x = 0.5 * (kp[t] - hstep * l);
+      // angle difference reduced to [-pi, pi] (the cardinal is 2 pi-periodic)
+      double d = kp[t] - hstep * l;
+      d -= kTwoPiD * rint(d / kTwoPiD);
+      const double x = 0.5 * d;
       double sx, cx;
       sincos(x, &sx, &cx);
       lt[idx] = (fabs(sx) < 1e-15) ? 1.0 : sin(Nt * x) * cx / (Nt * sx);

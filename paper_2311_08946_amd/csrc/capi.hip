@@ -160,7 +160,7 @@ static pdd_status to_dev_field(const pdd_field& f, DevField& d, const char* name
   d.n = f.n_terms;
   d.clip = f.clip_nonpos;
   d.base = f.base;
-  if (f.kind < PDD_FIELD_CONST || f.kind > PDD_FIELD_DERIVED_F)
+  if (f.kind < PDD_FIELD_CONST || f.kind > PDD_FIELD_EQ46)
     return fail(PDD_EINVAL, std::string("unknown field kind for ") + name);
   if (f.kind == PDD_FIELD_SINSUM || f.kind == PDD_FIELD_CPOLY_RE) {
     if (f.n_terms < 0 || f.n_terms > PDD_MAX_TERMS)

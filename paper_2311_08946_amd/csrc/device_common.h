@@ -51,9 +51,44 @@ __device__ __forceinline__ void cpoly_jet(const DevField& F, double x, double y,
   }
 }
 
+// The manufactured solution of Section 4 (eq. 46) and its derivatives up to
+// second order: u = 3 + sin(rho)/3 + tanh(s)/3 with rho = sqrt(1 + x^2/100 +
+// y^2/50) and s = sin(3x/25 + y/20) + sin(x/20 - 3y/25).
+__device__ __forceinline__ void eq46_jet(double x, double y, double* j) {
+  const double rho = sqrt(1.0 + x * x / 100.0 + y * y / 50.0);
+  const double rx = x / (100.0 * rho), ry = y / (50.0 * rho);
+  const double r3 = rho * rho * rho;
+  const double rxx = 1.0 / (100.0 * rho) - x * x / (10000.0 * r3);
+  const double ryy = 1.0 / (50.0 * rho) - y * y / (2500.0 * r3);
+  const double rxy = -x * y / (5000.0 * r3);
+  double sr, cr;
+  sincos(rho, &sr, &cr);
+  const double al = 3.0 * x / 25.0 + y / 20.0, be = x / 20.0 - 3.0 * y / 25.0;
+  double sa, ca, sb, cb;
+  sincos(al, &sa, &ca);
+  sincos(be, &sb, &cb);
+  const double s = sa + sb;
+  const double sx = 0.12 * ca + 0.05 * cb, sy = 0.05 * ca - 0.12 * cb;
+  const double sxx = -0.0144 * sa - 0.0025 * sb, syy = -0.0025 * sa - 0.0144 * sb;
+  const double sxy = -0.006 * sa + 0.006 * sb;
+  const double T = tanh(s), T1 = 1.0 - T * T, T2 = -2.0 * T * T1;
+  const double third = 1.0 / 3.0;
+  j[0] = 3.0 + third * (sr + T);
+  j[1] = third * (cr * rx + T1 * sx);
+  j[2] = third * (cr * ry + T1 * sy);
+  j[3] = third * (-sr * rx * rx + cr * rxx + T2 * sx * sx + T1 * sxx);
+  j[4] = third * (-sr * rx * ry + cr * rxy + T2 * sx * sy + T1 * sxy);
+  j[5] = third * (-sr * ry * ry + cr * ryy + T2 * sy * sy + T1 * syy);
+}
+
 __device__ __forceinline__ double field_plain(const DevField& F, double x, double y) {
   if (F.kind == PDD_FIELD_CONST) return F.base;
   if (F.kind == PDD_FIELD_SINSUM) return sinsum_value(F, x, y);
+  if (F.kind == PDD_FIELD_EQ46) {
+    double j[6];
+    eq46_jet(x, y, j);
+    return j[0];
+  }
   double pr, pi, a, b, c, d;
   cpoly_jet(F, x, y, pr, pi, a, b, c, d);
   return pr;
@@ -75,6 +110,8 @@ __device__ __forceinline__ void field_jet(const DevField& F, double x, double y,
       uyy -= A * ky * ky * s;
     }
     j[0] = u; j[1] = ux; j[2] = uy; j[3] = uxx; j[4] = uxy; j[5] = uyy;
+  } else if (F.kind == PDD_FIELD_EQ46) {
+    eq46_jet(x, y, j);
   } else if (F.kind == PDD_FIELD_CPOLY_RE) {
     double pr, pi, d1r, d1i, d2r, d2i;
     cpoly_jet(F, x, y, pr, pi, d1r, d1i, d2r, d2i);

@@ -282,7 +282,12 @@ __global__ __launch_bounds__(kEThreads) void eval_scatter_kernel(BucketTables T,
       if (t < cnt) {
         const int i = C.fk_ids[base + t];
         const double phi = atan2(C.ky[i] - cym, C.kx[i] - cxm);
-        const double x = 0.5 * (phi - hstep * l);
+        // the cardinal is 2 pi-periodic in the angle difference: reduce it to
+        // [-pi, pi] first, so that Nt x stays small wherever sin(x) is (else a
+        // knot at angle -pi next to the node at +pi loses all digits)
+        double d = phi - hstep * l;
+        d -= kTwoPiD * rint(d / kTwoPiD);
+        const double x = 0.5 * d;
         double sxx, cxx;
         sincos(x, &sxx, &cxx);
         // periodic cardinal sin(Nt x) cos(x) / (Nt sin(x)) at half-angle x

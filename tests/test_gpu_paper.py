@@ -1,0 +1,86 @@
+"""GPU checks of Section 4's test problem: Poisson's equation with the exact
+solution of eq. 46 on [-50, 50]^2 (100 circles, 44 knots, 44 x 22 nodes,
+c^2 = 1.5).  The device field against the oracle's, sampled assembly parity at
+a reduced path count, and the solution error with Section 4's paths and step."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from helpers_parity import _gpu_system, pick_mc_knots, sampled_parity
+from oracle import fields, geometry, spectral
+from oracle.geometry import ROW_SPECTRAL
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2311_08946_amd.binding as pdd
+    pdd.lib()
+    return pdd, torch
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def test_eq46_fields_on_the_device_match_the_oracle():
+    pdd, torch = _gpu()
+    prob = workloads.paper_poisson()["problem"]
+    xy = np.random.default_rng(460).uniform(-50.0, 50.0, size=(2000, 2))
+    xy_d = torch.tensor(xy, dtype=torch.float64, device="cuda")
+    _say("[gpu] eq. 46 fields on the device")
+    for which in ("g", "f", "u"):
+        got = pdd.eval_field(prob, which, xy_d).cpu().numpy()
+        fd = prob["u_exact"] if which == "u" else prob[which]
+        want = fields.value(fd, xy[:, 0], xy[:, 1], prob)
+        assert np.max(np.abs(got - want)) <= 1e-13 * max(1.0, float(np.max(np.abs(want)))), which
+
+
+def test_section4_assembly_parity_sampled():
+    pdd, torch = _gpu()
+    cfg = workloads.paper_poisson(paths=64)
+    prob = cfg["problem"]
+    _say("[gpu] Section 4 workload, 64 paths per knot")
+    cv, sysm, val, b, se, se_b = _gpu_system(pdd, cfg)
+    assert sysm.stats.breakdowns == 0 and sysm.stats.capped_paths == 0
+    ref_cover = geometry.build_cover(prob["domain"], cfg["cover"])
+    assert ref_cover.N == cv.N and ref_cover.rowptr[-1] == cv.nnz
+    rng = np.random.default_rng(461)
+    circles = set(int(m) for m in rng.choice(np.nonzero(ref_cover.floating)[0], size=2, replace=False))
+    # and every floating circle with an assigned knot at angle +-pi from its
+    # centre: the angular cardinal's wrap (-pi next to the node at +pi)
+    wrap = set()
+    for i in np.nonzero(ref_cover.row_class == ROW_SPECTRAL)[0]:
+        m = int(ref_cover.assigned[i])
+        _, phi = spectral.knot_polar(ref_cover, m, i)
+        if abs(abs(phi) - np.pi) < 1e-9:
+            wrap.add(m)
+    circles |= set(int(m) for m in rng.choice(sorted(wrap), size=min(4, len(wrap)), replace=False))
+    _say(f"[gpu] checking floating circles {sorted(circles)}")
+    frac = sampled_parity(prob, ref_cover, cfg["mc"], val, b, sorted(circles), pick_mc_knots(ref_cover, rng, 3))
+    assert frac > 0.6
+
+
+def test_section4_solution_error():
+    # Section 4's paths per knot (5000) and step (0.015).  Table 1 reports an
+    # RMS error of 3.7e-5 on its [-50, 50]^2 cover with Gobet-Menozzi steps and
+    # variance reduction; plain Euler has an O(sqrt(h)) exit bias, so the bar
+    # here is the size of that bias, not the paper's figure.
+    pdd, torch = _gpu()
+    cfg = workloads.paper_poisson()
+    prob = cfg["problem"]
+    cv = pdd.Cover(prob["domain"], cfg["cover"])
+    sysm = pdd.System(cv, prob, cfg["mc"])
+    u, info = sysm.solve(rtol=1e-12)
+    assert info.converged
+    xy = cv.knots()[0]
+    ue = fields.value(prob["u_exact"], xy[:, 0], xy[:, 1])
+    rms = float(np.sqrt(np.mean((u.cpu().numpy() - ue) ** 2)))
+    _say(f"[gpu] Section 4 cover: N = {cv.N}, nnz = {cv.nnz}, {info.iterations} BiCGStab iterations, "
+         f"RMS error {rms:.3e}, assembly {sysm.stats.ms_total:.1f} ms")
+    assert rms < 1e-2

@@ -267,7 +267,37 @@ def mixed_small(paths=64, h=1e-3, seed=8):
     return cfg
 
 
+def eq46():
+    """The manufactured solution of Section 4 (eq. 46), evaluated by the library."""
+    return {"kind": "eq46"}
+
+
+def paper_poisson(half=50.0, paths=5000, h=0.015, seed=46):
+    """Section 4's test problem: Poisson's equation with the exact solution of
+    eq. 46 and Dirichlet data equal to it, on the square [-half, half]^2.
+    Circles on a square lattice of spacing 10 (100 circles at half = 50, as in
+    Table 1; Figure 5's exact layout is not available), radii drawn uniformly
+    in [8.55, 9.43], 44 knots and 44 x 22 collocation nodes per circle (n = 968),
+    c^2 = 1.5, paths per perimeter knot and h as in Section 4 (plain Euler
+    here instead of Gobet-Menozzi with variance reduction)."""
+    rng = np.random.default_rng(seed)
+    n_side = int(round(2.0 * half / 10.0))
+    centres = lattice_centres(n_side, n_side, -half, half, -half, half)
+    radii = rng.uniform(8.55, 9.43, size=len(centres))
+    u = eq46()
+    prob = {
+        "domain": box(-half, half, -half, half),
+        "axx": const(2.0), "axy": const(0.0), "ayy": const(2.0),
+        "bx": const(0.0), "by": const(0.0), "c": const(0.0),
+        "f": derived_f(u), "g": u, "u_exact": u,
+    }
+    cover = _cover(centres, radii, 44, 44, 22, rbf_c2=1.5)
+    return {"name": f"paper_poisson_{int(half)}", "problem": prob, "cover": cover,
+            "mc": mc_opts(paths, h, seed=seed)}
+
+
 CONFIGS = {
     "config1": config1, "config2": config2, "config3": config3,
     "config4": config4, "config5": config5,
+    "paper50": paper_poisson,
 }
