@@ -54,6 +54,27 @@ def test_small_configs_match_oracle(name):
     _say(f"[gpu] {name}: worst spectral row diff {worst:.2e}, MC r_i within 1e-9: {frac:.4f}")
 
 
+@pytest.mark.parametrize("kind", ["no_floating", "one_floating"])
+def test_degenerate_covers_match_oracle(kind):
+    # no floating circle at all (no LU launches) and a single one (a batch of one)
+    pdd = _gpu()
+    cfg = workloads.degenerate(kind)
+    prob = cfg["problem"]
+    _say(f"[gpu] assemble {kind}")
+    cv, sysm, val, b, se, se_b = _gpu_system(pdd, cfg)
+    ref_cover = geometry.build_cover(prob["domain"], cfg["cover"])
+    assert cv.N == ref_cover.N and int(cv.info.n_float) == int(np.sum(ref_cover.floating))
+    ref = assemble.assemble(prob, ref_cover, cfg["mc"])
+    spec = np.nonzero(ref_cover.row_class == ROW_SPECTRAL)[0]
+    mcr = np.nonzero(ref_cover.row_class == ROW_MC)[0]
+    if len(spec):
+        _check_spectral_rows(ref_cover, ref.val, ref.b, val, b, spec, prob)
+        _check_rhs(ref_cover, ref.b, b, spec, _fscale(prob, ref_cover, np.nonzero(ref_cover.floating)[0]))
+    assert _check_mc_rows(ref_cover, ref.val, ref.se, ref.b, ref.se_b, val, b, mcr) > 0.99
+    u, info = sysm.solve(rtol=1e-12)
+    assert info.converged
+
+
 def test_per_circle_plan_is_bitwise_equal_to_batched():
     pdd = _gpu()
     cfg = workloads.small_variable(paths=64)

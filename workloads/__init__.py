@@ -267,6 +267,27 @@ def mixed_small(paths=64, h=1e-3, seed=8):
     return cfg
 
 
+def degenerate(kind, paths=64, h=1e-3, seed=11):
+    """Edge covers of the unit square (Laplace, g = Re p with a random cubic):
+    "no_floating" -- 2 x 2 circles of radius 0.4, all crossing the boundary
+    (no spectral rows, no LU); "one_floating" -- 3 x 3 circles of radius 0.26
+    at {0.15, 0.5, 0.85}^2, only the centre one floating (an LU batch of one).
+    M = Ntheta = 16, Nr = 6."""
+    rng = np.random.default_rng(seed)
+    g = _random_cpoly(rng, 3)
+    prob = laplace_problem(box(), g)
+    if kind == "no_floating":
+        xs, r = np.array([0.25, 0.75]), 0.4
+    elif kind == "one_floating":
+        xs, r = np.array([0.15, 0.5, 0.85]), 0.26
+    else:
+        raise ValueError(kind)
+    X, Y = np.meshgrid(xs, xs)
+    centres = np.stack([X.ravel(), Y.ravel()], axis=1)
+    cover = _cover(centres, np.full(len(centres), r), 16, 16, 6)
+    return {"name": kind, "problem": prob, "cover": cover, "mc": mc_opts(paths, h, seed=seed)}
+
+
 def eq46():
     """The manufactured solution of Section 4 (eq. 46), evaluated by the library."""
     return {"kind": "eq46"}
