@@ -212,8 +212,9 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": a.numel() * 8, "launches": 4}), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the assembly would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; the "
+              "assembly would shard by spatial blocks of circles with a halo exchange in the solve.",
+              file=sys.stderr)
         sys.exit(2)
 
     import workloads
