@@ -20,7 +20,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
-from . import assemble, spectral
+from . import assemble, geometry, spectral
 
 COEFS = ("axx", "axy", "ayy", "bx", "by", "c")
 
@@ -67,10 +67,16 @@ def loss_sq(u, target):
 
 def gradient(problem, cover, system, samples, target):
     """Loss sum (u - target)^2, its gradient w.r.t. every floating circle's
-    node samples, and lambda = C^-T dL/du (= dL/dr)."""
+    node samples, and lambda = C^-T dL/du (= dL/dr).  Under rule AVERAGED
+    (eqs. 38-39) row i is the sum of its pair rows, so each pair (knot i,
+    circle m) enters circle m's terms with the multiplier lambda_i."""
     u = assemble.solve(system)
     lam = assemble.solve(system, rhs=2.0 * (u - target), transpose=True)
-    grads = {m: circle_gradient(cover, m, samples[m], u, lam)
+    rows, lam_rows = cover, lam
+    if cover.containers is not None:
+        rows, pknot = geometry.pair_cover(cover)
+        lam_rows = lam[pknot]
+    grads = {m: circle_gradient(rows, m, samples[m], u, lam_rows)
              for m in np.nonzero(cover.floating)[0]}
     return loss_sq(u, target), grads, lam, u
 

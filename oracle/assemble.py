@@ -48,6 +48,8 @@ def assemble(problem, cover, mc, samples=None, with_mc=True, circles=None):
     """Assemble C (CSR) and r.  ``samples`` optionally maps floating circle index
     to its seven node samples; otherwise the fields are sampled at the nodes.
     ``circles`` restricts the floating circles processed (others left zero)."""
+    if cover.containers is not None:
+        return _assemble_averaged(problem, cover, mc, samples, with_mc, circles)
     N = cover.N
     val = np.zeros(len(cover.cols))
     se = np.zeros(len(cover.cols))
@@ -98,3 +100,62 @@ def diagnostics(system, u=None, u_exact=None):
     if u is not None and u_exact is not None:
         out["rms_error"] = float(np.sqrt(np.mean((u - u_exact) ** 2)))
     return out
+
+
+def _assemble_averaged(problem, cover, mc, samples, with_mc, circles):
+    """Rule AVERAGED (eqs. 38-39): every pair (knot i, circle m containing it)
+    is the row circle m alone gives at x_i -- spectral for a floating m, Monte
+    Carlo (with the pair's own random stream: the pair index is the knot word
+    of the Philox counter) for a perimeter m; row i is C_ii = #Pi_i and the
+    pairs' stencil entries side by side, r_i the sum of the pairs' r in pair
+    order, standard errors added in quadrature."""
+    pc, pknot = geometry.pair_cover(cover)
+    P = pc.N
+    prow = [None] * P          # stencil entries of each pair
+    pse = [None] * P
+    pb = np.zeros(P)
+    pse_b = np.zeros(P)
+    float_ids = np.nonzero(cover.floating)[0] if circles is None else np.asarray(circles)
+    for m in float_ids:
+        s = None if samples is None else samples[m]
+        knots, Crows, rv = spectral.floating_rows(problem, pc, m, s)
+        for t, p in enumerate(knots):
+            prow[p] = Crows[t]
+            pb[p] = rv[t]
+    steps = 0
+    if with_mc:
+        knots, rows, ses, r, se_r, steps = montecarlo.mc_rows(problem, pc, mc)
+        for t, p in enumerate(knots):
+            prow[p] = rows[t]
+            pse[p] = ses[t]
+            pb[p] = r[t]
+            pse_b[p] = se_r[t]
+    N = cover.N
+    val = np.zeros(len(cover.cols))
+    se = np.zeros(len(cover.cols))
+    b = np.zeros(N)
+    se_b2 = np.zeros(N)
+    for p in range(P):
+        i, m = int(pknot[p]), int(pc.assigned[p])
+        lo, hi = cover.rowptr[i], cover.rowptr[i + 1]
+        cols = cover.cols[lo:hi]
+        off = cover.knot_off[m]
+        seg = lo + int(np.searchsorted(cols, off))
+        if prow[p] is not None:
+            val[seg:seg + len(prow[p])] = prow[p]
+            if pse[p] is not None:
+                se[seg:seg + len(pse[p])] = pse[p]
+        b[i] += pb[p]
+        se_b2[i] += pse_b[p] ** 2
+    for i in range(N):
+        if cover.row_class[i] == ROW_BOUNDARY:
+            continue
+        lo, hi = cover.rowptr[i], cover.rowptr[i + 1]
+        d = lo + int(np.searchsorted(cover.cols[lo:hi], i))
+        val[d] = float(len(cover.containers[i]))
+    bnd = np.nonzero(cover.row_class == ROW_BOUNDARY)[0]
+    for i in bnd:
+        val[cover.rowptr[i]] = 1.0
+    if len(bnd):
+        b[bnd] = fields.value(problem["g"], cover.knot_xy[bnd, 0], cover.knot_xy[bnd, 1], problem)
+    return System(cover, val, b, se, np.sqrt(se_b2), steps)

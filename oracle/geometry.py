@@ -22,6 +22,10 @@ Readings taken where the paper leaves details open:
   replaces the current one only if it is deeper by more than 1e-12 r, so
   exact ties go to the lower circle index.  Rule MAX_DEPTH ignores the
   floating/perimeter preference.
+* Rule AVERAGED (eqs. 38-39): row i sums the expectations of every circle that
+  contains the knot strictly (the same depth test), and C_ii is their number.
+  ``containers[i]`` lists them by circle index; ``assigned`` still names the
+  circle the default rule would choose.
 """
 from __future__ import annotations
 
@@ -34,6 +38,8 @@ from scipy.spatial import cKDTree
 ROW_SPECTRAL = 0
 ROW_MC = 1
 ROW_BOUNDARY = 2
+
+RULE_AVERAGED = 2
 
 TWO_PI = 2.0 * math.pi
 
@@ -153,6 +159,7 @@ class Cover:
     rbf_c2: np.ndarray                   # (m,) IMQ shape parameter per perimeter circle
     rowptr: np.ndarray = field(default=None)
     cols: np.ndarray = field(default=None)
+    containers: list = field(default=None)   # rule AVERAGED: circles containing each knot
 
     @property
     def N(self):
@@ -225,6 +232,7 @@ def build_cover(dom, cov):
     assigned = np.full(N, -1, dtype=np.int64)
     row_class = np.full(N, ROW_BOUNDARY, dtype=np.int64)
     cand_lists = tree.query_ball_point(knot_xy, rmax * (1.0 + 1e-9))
+    containers = [[] for _ in range(N)] if rule == RULE_AVERAGED else None
     for i in range(N):
         if bnd[i]:
             continue
@@ -237,7 +245,9 @@ def build_cover(dom, cov):
             depth = radii[m] - math.sqrt(dx * dx + dy * dy)
             if depth <= 1e-9 * radii[m]:
                 continue
-            key = bool(floating[m]) if rule == 0 else True
+            if containers is not None:
+                containers[i].append(m)
+            key = bool(floating[m]) if rule != 1 else True
             bm, bd = best[key]
             if bm < 0 or depth > bd + 1e-12 * radii[m]:
                 best[key] = (m, depth)
@@ -254,19 +264,25 @@ def build_cover(dom, cov):
                     floating=floating, arc=arc,
                     knot_off=np.array(knot_off, dtype=np.int64), knot_xy=knot_xy,
                     knot_theta=np.array(th), knot_owner=own, knot_boundary=bnd,
-                    assigned=assigned, row_class=row_class, rbf_c2=c2)
+                    assigned=assigned, row_class=row_class, rbf_c2=c2, containers=containers)
     _csr_pattern(cov_obj)
     return cov_obj
 
 
 def _csr_pattern(cv):
     """Row i holds the diagonal and, for non-boundary rows, the stencil of the
-    chosen circle (eq. 29), with columns in increasing order."""
+    chosen circle (eq. 29) -- of every containing circle under rule AVERAGED
+    (eq. 38) -- with columns in increasing order."""
     rowptr = [0]
     cols = []
     for i in range(cv.N):
         if cv.row_class[i] == ROW_BOUNDARY:
             c = [i]
+        elif cv.containers is not None:
+            c = [i]
+            for m in cv.containers[i]:
+                c += list(range(cv.knot_off[m], cv.knot_off[m + 1]))
+            c = sorted(c)
         else:
             m = cv.assigned[i]
             c = sorted([i] + list(range(cv.knot_off[m], cv.knot_off[m + 1])))
@@ -274,3 +290,33 @@ def _csr_pattern(cv):
         rowptr.append(len(cols))
     cv.rowptr = np.array(rowptr, dtype=np.int64)
     cv.cols = np.array(cols, dtype=np.int64)
+
+
+def pair_cover(cv):
+    """Rule AVERAGED: a cover whose rows are the pairs (knot i, containing
+    circle m), in knot order then circle order, each the row circle m alone
+    would give at x_i (eq. 29 for that subdomain) -- stencil columns only, no
+    diagonal.  Stencils (knot_off, knot_theta) are those of cv.  Returns the
+    cover and the knot of every pair."""
+    pk, pm = [], []
+    for i in range(cv.N):
+        if cv.row_class[i] == ROW_BOUNDARY:
+            continue
+        for m in cv.containers[i]:
+            pk.append(i)
+            pm.append(m)
+    pk = np.array(pk, dtype=np.int64)
+    pm = np.array(pm, dtype=np.int64)
+    pc = Cover(centres=cv.centres, radii=cv.radii, M=cv.M, Ntheta=cv.Ntheta, Nr=cv.Nr,
+               floating=cv.floating, arc=cv.arc, knot_off=cv.knot_off,
+               knot_xy=cv.knot_xy[pk], knot_theta=cv.knot_theta, knot_owner=cv.knot_owner[pk],
+               knot_boundary=np.zeros(len(pk), dtype=bool), assigned=pm,
+               row_class=np.where(cv.floating[pm], ROW_SPECTRAL, ROW_MC), rbf_c2=cv.rbf_c2)
+    rowptr = [0]
+    cols = []
+    for m in pm:
+        cols.extend(range(cv.knot_off[m], cv.knot_off[m + 1]))
+        rowptr.append(len(cols))
+    pc.rowptr = np.array(rowptr, dtype=np.int64)
+    pc.cols = np.array(cols, dtype=np.int64)
+    return pc, pk
