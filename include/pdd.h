@@ -123,7 +123,10 @@ pdd_status pdd_eval_field(const pdd_problem* problem, int32_t which, const doubl
 
 /* ------------------------------------------------------------------ cover */
 
-enum { PDD_RULE_FLOAT_FIRST_MAX_DEPTH = 0, PDD_RULE_MAX_DEPTH = 1 };
+/* Row choice: the deepest floating circle containing the knot (else the deepest
+ * perimeter one); the deepest of any kind; or (AVERAGED, eqs. 38-39) the sum of
+ * the expectations of every containing circle, C_ii = their number. */
+enum { PDD_RULE_FLOAT_FIRST_MAX_DEPTH = 0, PDD_RULE_MAX_DEPTH = 1, PDD_RULE_AVERAGED = 2 };
 
 typedef struct pdd_cover_opts {
   int32_t rule;            /* row choice of Section 3.2 (see pdd_build_cover)         */
@@ -145,9 +148,14 @@ typedef struct pdd_cover_opts {
  * arc (keeping dtheta/4 away from its ends) plus one junction knot at each
  * end.  Knots are numbered circle by circle in increasing local angle.  Row
  * rule FLOAT_FIRST_MAX_DEPTH: the deepest floating circle strictly containing
- * the knot, else the deepest perimeter one; MAX_DEPTH: the deepest of all.
- * Errors: PDD_EINVAL, PDD_ECOVER (uncovered knot, multi-arc interface,
- * circle outside Omega), PDD_ENOMEM.  No device work is done.
+ * the knot, else the deepest perimeter one; MAX_DEPTH: the deepest of all;
+ * AVERAGED (eqs. 38-39): every circle strictly containing the knot, each
+ * contributing its own row (the pairs (knot, circle) are numbered knot-major,
+ * circles by index); row_class and assigned of pdd_cover_knots still report
+ * the FLOAT_FIRST_MAX_DEPTH choice.
+ * Errors: PDD_EINVAL (also an unknown rule), PDD_ECOVER (uncovered knot,
+ * multi-arc interface, circle outside Omega), PDD_ENOMEM.  No device work is
+ * done.
  */
 pdd_status pdd_build_cover(const pdd_domain* domain, int32_t n_circles,
                            const double* centres, const double* radii,
@@ -173,7 +181,8 @@ pdd_status pdd_cover_knots(pdd_cover cover, double* xy, int32_t* row_class,
                            int32_t* assigned, int32_t* owner);
 
 /* CSR pattern of C (host outputs): rowptr [N+1], cols [nnz]; columns of each
- * row increase; row i holds i and, unless boundary, the stencil of its circle. */
+ * row increase; row i holds i and, unless boundary, the stencil of its circle
+ * (of every containing circle under rule AVERAGED). */
 pdd_status pdd_cover_pattern(pdd_cover cover, int64_t* rowptr, int32_t* cols);
 
 /* Collocation nodes of the floating circles (host outputs): xy [2*sum_n],
@@ -246,7 +255,11 @@ typedef struct pdd_assemble_opts {
  * sides [A_IB H | -F] (eqs. 32, 35, 41), and the solutions are interpolated at
  * the knots assigned to the circle.  Perimeter rows: `mc->paths` Euler paths
  * per knot; step k of path p from knot i draws Philox4x32-10 at counter
- * (k, p, i, 0).  Boundary rows: C_ii = 1, r_i = g(x_i).
+ * (k, p, i, 0).  Boundary rows: C_ii = 1, r_i = g(x_i).  Rule AVERAGED: each
+ * pair (knot i, circle m) is assembled as the row circle m gives at x_i (the
+ * pair's index takes the place of i in the Philox counter), then row i is
+ * C_ii = number of pairs, the pairs' stencil entries, r_i = sum of the
+ * pairs' r in pair order, standard error of r_i their quadrature sum.
  *   samples  may be NULL (all sampled on the device)
  *   out      receives a system handle owning the device results
  * Errors: PDD_EINVAL, PDD_ENOMEM, PDD_EDEVICE, PDD_EBREAKDOWN, PDD_EPATHCAP.

@@ -320,11 +320,36 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))
 
 }  // namespace
 
+// Rule AVERAGED: the multiplier of each pair row is that of its knot's row.
+__global__ void gather_pairs_kernel(int64_t np, const int32_t* __restrict__ pair_knot,
+                                    const double* __restrict__ x, double* __restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < np) out[q] = x[pair_knot[q]];
+}
+
 pdd_status backward_impl(pdd_system sys, const double* u, const double* lambda, double* const g[7],
                          hipStream_t st) {
-  const DeviceCover& D = sys->cover->D;
+  const bool avg = sys->cover->H.pairs != nullptr;
+  const DeviceCover& D = avg ? sys->cover->DP : sys->cover->D;
   if (sys->factors.empty() && !sys->recompute && !sys->cover->H.float_ids.empty())
     return fail(PDD_EINVAL, "pdd_assemble_G_backward: assemble with keep_factors to differentiate");
+  // Row i of C is the sum of its pair rows, so the gradient is that of the
+  // pair rows with every pair taking its knot's multiplier.
+  DevBuf pair_lambda;
+  struct SyncOnExit {
+    hipStream_t s;
+    bool on;
+    ~SyncOnExit() { if (on) (void)hipStreamSynchronize(s); }   // before pair_lambda is freed
+  } sync_guard{st, avg};
+  if (avg) {
+    const int64_t np = sys->cover->H.pairs->N();
+    pair_lambda.alloc(std::max<int64_t>(1, np) * sizeof(double));
+    if (np > 0)
+      hipLaunchKernelGGL(gather_pairs_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, np,
+                         D.pair_knot.ptr<int32_t>(), lambda, pair_lambda.ptr<double>());
+    PDD_HIP(hipGetLastError());
+    lambda = pair_lambda.ptr<double>();
+  }
   auto run = [&](const BucketFactors& F) -> pdd_status {
     const BucketData& bk = *D.buckets[F.bucket];
     AdjArgs a{};

@@ -30,6 +30,45 @@ __global__ void reduce_u64_kernel(const uint64_t* __restrict__ a, int64_t n, uin
   if (threadIdx.x == 0) out[0] = s[0];
 }
 
+// Rule AVERAGED (eqs. 38-39): row i of C is the rows of its pairs (knot i,
+// circle m containing x_i) side by side, C_ii the number of pairs, r_i the sum
+// of the pairs' r in pair order and its standard error their quadrature sum.
+// One wavefront per knot; a pair row holds its diagonal slot first when the
+// pair index is below the stencil's first knot, else last.
+__global__ void __launch_bounds__(256) average_rows_kernel(
+    int64_t N, const int64_t* __restrict__ pair_off, const int64_t* __restrict__ diag_pos,
+    const int64_t* __restrict__ pair_seg, const int64_t* __restrict__ prowptr,
+    const int32_t* __restrict__ passigned, const int64_t* __restrict__ knot_off,
+    const double* __restrict__ pval, const double* __restrict__ pse, const double* __restrict__ pb,
+    const double* __restrict__ pse_b, double* __restrict__ val, double* __restrict__ se,
+    double* __restrict__ b, double* __restrict__ se_b) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= N) return;
+  const int64_t p0 = pair_off[i], p1 = pair_off[i + 1];
+  if (p0 == p1) return;   // boundary row, written by its own kernel
+  double bs = 0.0, v2 = 0.0;
+  for (int64_t p = p0; p < p1; ++p) {
+    const int m = passigned[p];
+    const int64_t lo = knot_off[m];
+    const int M = (int)(knot_off[m + 1] - lo);
+    const int64_t src = prowptr[p] + (p < lo ? 1 : 0);
+    const int64_t dst = pair_seg[p];
+    for (int c = lane; c < M; c += 64) {
+      val[dst + c] = pval[src + c];
+      se[dst + c] = pse[src + c];
+    }
+    bs += pb[p];
+    v2 += pse_b[p] * pse_b[p];
+  }
+  if (lane == 0) {
+    val[diag_pos[i]] = (double)(p1 - p0);
+    se[diag_pos[i]] = 0.0;
+    b[i] = bs;
+    se_b[i] = sqrt(v2);
+  }
+}
+
 __global__ void reduce_i32_kernel(const int32_t* __restrict__ a, int64_t n, uint64_t* out) {
   __shared__ uint64_t s[256];
   uint64_t v = 0;
@@ -410,7 +449,9 @@ void autotune(const DeviceCover& D, const NodeSamples& S, int64_t budget, hipStr
 pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_samples* samples,
                          const pdd_mc_opts* mc, const pdd_assemble_opts* opts, hipStream_t st,
                          pdd_system* out) {
-  const HostCover& H = cover->H;
+  const HostCover& H0 = cover->H;
+  const bool avg = H0.pairs != nullptr;
+  const HostCover& H = avg ? *H0.pairs : H0;   // the rows the kernels assemble
   if (!H.mc_knots.empty()) {
     if (!mc) return fail(PDD_EINVAL, "pdd_assemble_G: Monte Carlo options are required");
     if (mc->paths < 2 || !(mc->h > 0.0) || mc->n_batches < 2 || mc->n_batches > 63 ||
@@ -423,20 +464,43 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
   }
   int dev = 0;
   PDD_HIP(hipGetDevice(&dev));
-  DeviceCover& D = cover->D;
-  if (!D.ready || D.device != dev) {
+  DeviceCover& D0 = cover->D;
+  if (!D0.ready || D0.device != dev) {
+    D0.upload(H0);
+    D0.device = dev;
+  }
+  DeviceCover& D = avg ? cover->DP : D0;
+  if (avg && (!D.ready || D.device != dev)) {
     D.upload(H);
     D.device = dev;
   }
   auto sys = std::make_unique<pdd_system_s>();
   sys->cover = cover;
-  const int64_t N = H.N(), nnz = H.rowptr.back();
-  sys->val.alloc(nnz * sizeof(double));
-  sys->se.alloc(nnz * sizeof(double));
-  sys->b.alloc(N * sizeof(double));
-  sys->se_b.alloc(N * sizeof(double));
-  PDD_HIP(hipMemsetAsync(sys->se.ptr<void>(), 0, nnz * sizeof(double), st));
-  PDD_HIP(hipMemsetAsync(sys->se_b.ptr<void>(), 0, N * sizeof(double), st));
+  const int64_t N0 = H0.N(), nnz0 = H0.rowptr.back();
+  sys->val.alloc(nnz0 * sizeof(double));
+  sys->se.alloc(nnz0 * sizeof(double));
+  sys->b.alloc(N0 * sizeof(double));
+  sys->se_b.alloc(N0 * sizeof(double));
+  PDD_HIP(hipMemsetAsync(sys->se.ptr<void>(), 0, nnz0 * sizeof(double), st));
+  PDD_HIP(hipMemsetAsync(sys->se_b.ptr<void>(), 0, N0 * sizeof(double), st));
+  // the rows the kernels write: those of C, or under rule AVERAGED the pair
+  // rows, combined into C at the end
+  DevBuf pair_val, pair_se, pair_b, pair_se_b;
+  double *val = sys->val.ptr<double>(), *se = sys->se.ptr<double>();
+  double *bv = sys->b.ptr<double>(), *se_b = sys->se_b.ptr<double>();
+  if (avg) {
+    const int64_t np = H.N(), nnzp = H.rowptr.back();
+    pair_val.alloc(std::max<int64_t>(1, nnzp) * sizeof(double));
+    pair_se.alloc(std::max<int64_t>(1, nnzp) * sizeof(double));
+    pair_b.alloc(std::max<int64_t>(1, np) * sizeof(double));
+    pair_se_b.alloc(std::max<int64_t>(1, np) * sizeof(double));
+    PDD_HIP(hipMemsetAsync(pair_se.ptr<void>(), 0, std::max<int64_t>(1, nnzp) * sizeof(double), st));
+    PDD_HIP(hipMemsetAsync(pair_se_b.ptr<void>(), 0, std::max<int64_t>(1, np) * sizeof(double), st));
+    val = pair_val.ptr<double>();
+    se = pair_se.ptr<double>();
+    bv = pair_b.ptr<double>();
+    se_b = pair_se_b.ptr<double>();
+  }
 
   DevProblem dp;
   pdd_status ps = make_dev_problem(*problem, dp);
@@ -565,8 +629,7 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
     a.out_capped = out_capped.ptr<uint64_t>();
     launch_mc_paths(P, dp.const_coef != 0, a, side);
     launch_gram_cholesky(a, (int32_t)n_perim, gram.ptr<double>(), gram_status.ptr<int32_t>(), side);
-    launch_mc_finalize(a, (int32_t)n_mc, H.max_arc, gram.ptr<double>(), sys->val.ptr<double>(),
-                       sys->se.ptr<double>(), sys->b.ptr<double>(), sys->se_b.ptr<double>(), side);
+    launch_mc_finalize(a, (int32_t)n_mc, H.max_arc, gram.ptr<double>(), val, se, bv, se_b, side);
     PDD_HIP(hipGetLastError());
     hipLaunchKernelGGL(reduce_u64_kernel, dim3(1), dim3(256), 0, side, out_steps.ptr<uint64_t>(),
                        a.n_units, lu_fail.ptr<uint64_t>() + 1);
@@ -578,8 +641,8 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
     n_launch_mc = 3;
     timer.end(e);
   }
-  launch_boundary_rows(P, D.bnd_knots.ptr<int32_t>(), (int32_t)H.bnd_knots.size(), D.kx.ptr<double>(),
-                       D.ky.ptr<double>(), D.rowptr.ptr<int64_t>(), sys->val.ptr<double>(),
+  launch_boundary_rows(P, D0.bnd_knots.ptr<int32_t>(), (int32_t)H0.bnd_knots.size(), D0.kx.ptr<double>(),
+                       D0.ky.ptr<double>(), D0.rowptr.ptr<int64_t>(), sys->val.ptr<double>(),
                        sys->se.ptr<double>(), sys->b.ptr<double>(), sys->se_b.ptr<double>(), side);
   PDD_HIP(hipGetLastError());
   PDD_HIP(hipEventRecord(ev_join, side));
@@ -608,12 +671,19 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
         fs[k]->count = sl.cnt;
       }
     }
-    n_launch_spectral += run.group(grp, fs, S, &timer, sys->val.ptr<double>(), sys->b.ptr<double>(),
-                                   lu_fail.ptr<uint64_t>());
+    n_launch_spectral += run.group(grp, fs, S, &timer, val, bv, lu_fail.ptr<uint64_t>());
   }
   run.finish();
 
   PDD_HIP(hipStreamWaitEvent(st, ev_join, 0));
+  if (avg && N0 > 0) {
+    hipLaunchKernelGGL(average_rows_kernel, dim3((unsigned)((N0 + 3) / 4)), dim3(256), 0, st, N0,
+                       D0.pair_off.ptr<int64_t>(), D0.diag_pos.ptr<int64_t>(),
+                       D.pair_seg.ptr<int64_t>(), D.rowptr.ptr<int64_t>(), D.assigned.ptr<int32_t>(),
+                       D.knot_off.ptr<int64_t>(), val, se, bv, se_b, sys->val.ptr<double>(),
+                       sys->se.ptr<double>(), sys->b.ptr<double>(), sys->se_b.ptr<double>());
+    PDD_HIP(hipGetLastError());
+  }
   timer.end(t_all);
 
   uint64_t flags[4] = {0, 0, 0, 0};

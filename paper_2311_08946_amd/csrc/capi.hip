@@ -128,6 +128,8 @@ void DeviceCover::upload(const HostCover& Hc) {
   assigned.upload(Hc.assigned); float_ids.upload(Hc.float_ids); node_off.upload(Hc.node_off);
   fk_off.upload(Hc.fk_off); fk_ids.upload(Hc.fk_ids); perim_ids.upload(Hc.perim_ids);
   perim_pos.upload(Hc.perim_pos); mc_knots.upload(Hc.mc_knots); bnd_knots.upload(Hc.bnd_knots);
+  pair_off.upload(Hc.pair_off); diag_pos.upload(Hc.diag_pos);
+  pair_knot.upload(Hc.pair_knot); pair_seg.upload(Hc.pair_seg);
   have_transpose = false;
   buckets.clear();
   for (const Bucket& b : Hc.buckets) {
@@ -215,9 +217,11 @@ pdd_status pdd_build_cover(const pdd_domain* domain, int32_t n_circles, const do
     return fail(PDD_EINVAL, "pdd_build_cover: unknown domain kind");
   if (domain->kind == PDD_DOMAIN_DISK && (domain->n_holes < 0 || domain->n_holes > PDD_MAX_HOLES))
     return fail(PDD_EINVAL, "pdd_build_cover: too many holes");
+  const int32_t rule = opts ? opts->rule : PDD_RULE_FLOAT_FIRST_MAX_DEPTH;
+  if (rule < PDD_RULE_FLOAT_FIRST_MAX_DEPTH || rule > PDD_RULE_AVERAGED)
+    return fail(PDD_EINVAL, "pdd_build_cover: unknown row rule");
   try {
     auto cv = std::make_unique<pdd_cover_s>();
-    const int32_t rule = opts ? opts->rule : PDD_RULE_FLOAT_FIRST_MAX_DEPTH;
     const double c2 = opts ? opts->rbf_c2 : 0.0;
     std::string err = build_host_cover(*domain, n_circles, centres, radii, M, Ntheta, Nr, rule, c2,
                                        cv->H);

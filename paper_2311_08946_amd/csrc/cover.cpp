@@ -117,10 +117,67 @@ double signed_distance(const pdd_domain& d, double x, double y) {
   return s;
 }
 
+// Floating and perimeter circle tables, the rows each floating circle
+// evaluates, the Monte Carlo and boundary knots, and the size buckets.
+static void finish_tables(HostCover& C) {
+  const int n = C.nc;
+  const int64_t N = C.N();
+  C.float_pos.assign(n, -1);
+  C.perim_pos.assign(n, -1);
+  // floating-circle tables
+  C.node_off.push_back(0);
+  for (int m = 0; m < n; ++m) {
+    if (C.floating[m]) {
+      C.float_pos[m] = (int32_t)C.float_ids.size();
+      C.float_ids.push_back(m);
+      int64_t nn = (int64_t)C.Nr[m] * C.Nt[m];
+      C.node_off.push_back(C.node_off.back() + nn);
+      C.sum_n += nn;
+      C.sum_n2 += nn * nn;
+      C.max_n = std::max<int32_t>(C.max_n, (int32_t)nn);
+    } else {
+      C.perim_pos[m] = (int32_t)C.perim_ids.size();
+      C.perim_ids.push_back(m);
+      C.max_arc = std::max<int32_t>(C.max_arc, (int32_t)(C.knot_off[m + 1] - C.knot_off[m]));
+    }
+    C.max_M = std::max(C.max_M, C.M[m]);
+  }
+  const size_t nf = C.float_ids.size();
+  std::vector<int64_t> cnt(nf + 1, 0);
+  for (int64_t i = 0; i < N; ++i)
+    if (C.row_class[i] == ROW_SPECTRAL) ++cnt[C.float_pos[C.assigned[i]] + 1];
+  C.fk_off.assign(nf + 1, 0);
+  for (size_t f = 0; f < nf; ++f) C.fk_off[f + 1] = C.fk_off[f] + cnt[f + 1];
+  C.fk_ids.resize(C.fk_off[nf]);
+  std::vector<int64_t> fill(C.fk_off.begin(), C.fk_off.end() - 1);
+  for (int64_t i = 0; i < N; ++i)
+    if (C.row_class[i] == ROW_SPECTRAL) C.fk_ids[fill[C.float_pos[C.assigned[i]]]++] = (int32_t)i;
+  // Monte Carlo knots grouped by circle, boundary knots
+  std::vector<std::vector<int32_t>> per(C.perim_ids.size());
+  for (int64_t i = 0; i < N; ++i) {
+    if (C.row_class[i] == ROW_MC) per[C.perim_pos[C.assigned[i]]].push_back((int32_t)i);
+    if (C.row_class[i] == ROW_BOUNDARY) C.bnd_knots.push_back((int32_t)i);
+  }
+  for (auto& v : per) C.mc_knots.insert(C.mc_knots.end(), v.begin(), v.end());
+  // size buckets of floating circles
+  for (size_t f = 0; f < nf; ++f) {
+    int m = C.float_ids[f];
+    Bucket* b = nullptr;
+    for (auto& bb : C.buckets)
+      if (bb.Nr == C.Nr[m] && bb.Nt == C.Nt[m] && bb.M == C.M[m]) b = &bb;
+    if (!b) {
+      C.buckets.push_back({C.Nr[m], C.Nt[m], C.M[m], {}});
+      b = &C.buckets.back();
+    }
+    b->fl.push_back((int32_t)f);
+  }
+}
+
 std::string build_host_cover(const pdd_domain& dom, int32_t n, const double* centres,
                              const double* radii, const int32_t* Mv, const int32_t* Ntv,
                              const int32_t* Nrv, int32_t rule, double rbf_c2, HostCover& C) {
   C = HostCover();
+  if (rule < PDD_RULE_FLOAT_FIRST_MAX_DEPTH || rule > PDD_RULE_AVERAGED) return "unknown row rule";
   C.dom = dom;
   C.nc = n;
   C.cx.resize(n); C.cy.resize(n); C.r.resize(n);
@@ -203,6 +260,8 @@ std::string build_host_cover(const pdd_domain& dom, int32_t n, const double* cen
 
   C.assigned.assign(N, -1);
   C.row_class.assign(N, ROW_BOUNDARY);
+  const bool averaged = rule == PDD_RULE_AVERAGED;
+  std::vector<std::vector<int32_t>> cont(averaged ? N : 0);
   std::vector<int32_t> cand;
   for (int64_t i = 0; i < N; ++i) {
     if (C.boundary[i]) continue;
@@ -223,6 +282,7 @@ std::string build_host_cover(const pdd_domain& dom, int32_t n, const double* cen
       double dx = x - C.cx[m], dy = y - C.cy[m];
       double depth = C.r[m] - std::sqrt(dx * dx + dy * dy);
       if (depth <= 1e-9 * C.r[m]) continue;
+      if (averaged) cont[i].push_back(m);
       int slot = (rule == PDD_RULE_MAX_DEPTH) ? 0 : (C.floating[m] ? 0 : 1);
       if (best[slot] < 0 || depth > bestd[slot] + 1e-12 * C.r[m]) {
         best[slot] = m;
@@ -235,76 +295,107 @@ std::string build_host_cover(const pdd_domain& dom, int32_t n, const double* cen
     C.row_class[i] = C.floating[m] ? ROW_SPECTRAL : ROW_MC;
   }
 
-  // CSR pattern: diagonal plus the stencil of the chosen circle, columns sorted
-  C.rowptr.assign(N + 1, 0);
-  for (int64_t i = 0; i < N; ++i) {
-    int64_t len = 1;
-    if (C.row_class[i] != ROW_BOUNDARY) {
+  if (averaged) {
+    // CSR pattern: diagonal plus the stencils of all containing circles
+    // (contiguous knot ranges in circle order; x_i is on none of them)
+    C.rowptr.assign(N + 1, 0);
+    for (int64_t i = 0; i < N; ++i) {
+      int64_t len = 1;
+      if (C.row_class[i] != ROW_BOUNDARY)
+        for (int32_t m : cont[i]) len += C.knot_off[m + 1] - C.knot_off[m];
+      C.rowptr[i + 1] = C.rowptr[i] + len;
+    }
+    C.cols.resize(C.rowptr[N]);
+    C.diag_pos.assign(N, 0);
+    for (int64_t i = 0; i < N; ++i) {
+      int64_t p = C.rowptr[i];
+      bool placed = false;
+      if (C.row_class[i] != ROW_BOUNDARY)
+        for (int32_t m : cont[i]) {
+          if (!placed && i < C.knot_off[m]) {
+            C.diag_pos[i] = p;
+            C.cols[p++] = (int32_t)i;
+            placed = true;
+          }
+          for (int64_t j = C.knot_off[m]; j < C.knot_off[m + 1]; ++j) C.cols[p++] = (int32_t)j;
+        }
+      if (!placed) {
+        C.diag_pos[i] = p;
+        C.cols[p++] = (int32_t)i;
+      }
+    }
+  } else {
+    // CSR pattern: diagonal plus the stencil of the chosen circle, columns sorted
+    C.rowptr.assign(N + 1, 0);
+    for (int64_t i = 0; i < N; ++i) {
+      int64_t len = 1;
+      if (C.row_class[i] != ROW_BOUNDARY) {
+        int m = C.assigned[i];
+        len += C.knot_off[m + 1] - C.knot_off[m];
+      }
+      C.rowptr[i + 1] = C.rowptr[i] + len;
+    }
+    C.cols.resize(C.rowptr[N]);
+    for (int64_t i = 0; i < N; ++i) {
+      int64_t p = C.rowptr[i];
+      if (C.row_class[i] == ROW_BOUNDARY) {
+        C.cols[p] = (int32_t)i;
+        continue;
+      }
       int m = C.assigned[i];
-      len += C.knot_off[m + 1] - C.knot_off[m];
+      int64_t lo = C.knot_off[m], hi = C.knot_off[m + 1];
+      if (i < lo) C.cols[p++] = (int32_t)i;
+      for (int64_t j = lo; j < hi; ++j) C.cols[p++] = (int32_t)j;
+      if (i > lo) C.cols[p++] = (int32_t)i;   // i is never inside [lo, hi)
     }
-    C.rowptr[i + 1] = C.rowptr[i] + len;
-  }
-  C.cols.resize(C.rowptr[N]);
-  for (int64_t i = 0; i < N; ++i) {
-    int64_t p = C.rowptr[i];
-    if (C.row_class[i] == ROW_BOUNDARY) {
-      C.cols[p] = (int32_t)i;
-      continue;
-    }
-    int m = C.assigned[i];
-    int64_t lo = C.knot_off[m], hi = C.knot_off[m + 1];
-    if (i < lo) C.cols[p++] = (int32_t)i;
-    for (int64_t j = lo; j < hi; ++j) C.cols[p++] = (int32_t)j;
-    if (i > lo) C.cols[p++] = (int32_t)i;   // i is never inside [lo, hi)
   }
 
-  // floating-circle tables
-  C.node_off.push_back(0);
-  for (int m = 0; m < n; ++m) {
-    if (C.floating[m]) {
-      C.float_pos[m] = (int32_t)C.float_ids.size();
-      C.float_ids.push_back(m);
-      int64_t nn = (int64_t)C.Nr[m] * C.Nt[m];
-      C.node_off.push_back(C.node_off.back() + nn);
-      C.sum_n += nn;
-      C.sum_n2 += nn * nn;
-      C.max_n = std::max<int32_t>(C.max_n, (int32_t)nn);
-    } else {
-      C.perim_pos[m] = (int32_t)C.perim_ids.size();
-      C.perim_ids.push_back(m);
-      C.max_arc = std::max<int32_t>(C.max_arc, (int32_t)(C.knot_off[m + 1] - C.knot_off[m]));
+  finish_tables(C);
+  if (averaged) {
+    // the pairs (knot i, circle m containing x_i), in knot then circle order
+    auto P = std::make_unique<HostCover>();
+    HostCover& Q = *P;
+    Q.dom = C.dom; Q.nc = C.nc;
+    Q.cx = C.cx; Q.cy = C.cy; Q.r = C.r; Q.arc0 = C.arc0; Q.arc1 = C.arc1; Q.rbf_c2 = C.rbf_c2;
+    Q.M = C.M; Q.Nt = C.Nt; Q.Nr = C.Nr; Q.floating = C.floating;
+    Q.knot_off = C.knot_off; Q.ktheta = C.ktheta;
+    C.pair_off.assign(N + 1, 0);
+    for (int64_t i = 0; i < N; ++i) {
+      if (C.row_class[i] != ROW_BOUNDARY)
+        for (int32_t m : cont[i]) {
+          Q.kx.push_back(C.kx[i]);
+          Q.ky.push_back(C.ky[i]);
+          Q.owner.push_back(C.owner[i]);
+          Q.boundary.push_back(0);
+          Q.assigned.push_back(m);
+          Q.row_class.push_back(C.floating[m] ? ROW_SPECTRAL : ROW_MC);
+          Q.pair_knot.push_back((int32_t)i);
+          // circle m's entries in row i: after the columns of row i below knot_off[m]
+          int64_t pos = C.rowptr[i];
+          while (pos < C.rowptr[i + 1] && C.cols[pos] < C.knot_off[m]) ++pos;
+          Q.pair_seg.push_back(pos);
+        }
+      C.pair_off[i + 1] = (int64_t)Q.kx.size();
     }
-    C.max_M = std::max(C.max_M, C.M[m]);
-  }
-  const size_t nf = C.float_ids.size();
-  std::vector<int64_t> cnt(nf + 1, 0);
-  for (int64_t i = 0; i < N; ++i)
-    if (C.row_class[i] == ROW_SPECTRAL) ++cnt[C.float_pos[C.assigned[i]] + 1];
-  C.fk_off.assign(nf + 1, 0);
-  for (size_t f = 0; f < nf; ++f) C.fk_off[f + 1] = C.fk_off[f] + cnt[f + 1];
-  C.fk_ids.resize(C.fk_off[nf]);
-  std::vector<int64_t> fill(C.fk_off.begin(), C.fk_off.end() - 1);
-  for (int64_t i = 0; i < N; ++i)
-    if (C.row_class[i] == ROW_SPECTRAL) C.fk_ids[fill[C.float_pos[C.assigned[i]]]++] = (int32_t)i;
-  // Monte Carlo knots grouped by circle, boundary knots
-  std::vector<std::vector<int32_t>> per(C.perim_ids.size());
-  for (int64_t i = 0; i < N; ++i) {
-    if (C.row_class[i] == ROW_MC) per[C.perim_pos[C.assigned[i]]].push_back((int32_t)i);
-    if (C.row_class[i] == ROW_BOUNDARY) C.bnd_knots.push_back((int32_t)i);
-  }
-  for (auto& v : per) C.mc_knots.insert(C.mc_knots.end(), v.begin(), v.end());
-  // size buckets of floating circles
-  for (size_t f = 0; f < nf; ++f) {
-    int m = C.float_ids[f];
-    Bucket* b = nullptr;
-    for (auto& bb : C.buckets)
-      if (bb.Nr == C.Nr[m] && bb.Nt == C.Nt[m] && bb.M == C.M[m]) b = &bb;
-    if (!b) {
-      C.buckets.push_back({C.Nr[m], C.Nt[m], C.M[m], {}});
-      b = &C.buckets.back();
+    // pair rows as the kernels lay a row out: the diagonal slot, then the
+    // stencil, the diagonal slot first when the row index is below the stencil
+    const int64_t np = Q.N();
+    Q.rowptr.assign(np + 1, 0);
+    for (int64_t q = 0; q < np; ++q) {
+      const int m = Q.assigned[q];
+      Q.rowptr[q + 1] = Q.rowptr[q] + 1 + (C.knot_off[m + 1] - C.knot_off[m]);
     }
-    b->fl.push_back((int32_t)f);
+    Q.cols.resize(Q.rowptr[np]);
+    for (int64_t q = 0; q < np; ++q) {
+      const int m = Q.assigned[q];
+      int64_t p = Q.rowptr[q];
+      const int64_t lo = C.knot_off[m], hi = C.knot_off[m + 1];
+      if (q < lo) Q.cols[p++] = (int32_t)Q.pair_knot[q];
+      for (int64_t j = lo; j < hi; ++j) Q.cols[p++] = (int32_t)j;
+      if (q >= lo) Q.cols[p++] = (int32_t)Q.pair_knot[q];
+    }
+    finish_tables(Q);
+    C.pairs = std::move(P);
   }
   return "";
 }

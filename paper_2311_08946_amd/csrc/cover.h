@@ -3,6 +3,7 @@
 
 #include <cstdint>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "pdd.h"
@@ -45,6 +46,15 @@ struct HostCover {
   int64_t N() const { return (int64_t)kx.size(); }
   int64_t sum_n = 0, sum_n2 = 0;
   int32_t max_n = 0, max_M = 0, max_arc = 0;
+  // rule AVERAGED (eqs. 38-39): the pairs (knot i, circle m containing x_i) as
+  // the rows of a second cover, each the row circle m alone gives at x_i
+  // (diagonal slot included), assembled by the same kernels and then combined
+  // into the rows of this cover
+  std::unique_ptr<HostCover> pairs;
+  std::vector<int32_t> pair_knot;   // (in `pairs`) the knot of each pair
+  std::vector<int64_t> pair_seg;    // (in `pairs`) where circle m's entries start in row i of C
+  std::vector<int64_t> pair_off;    // [N+1] pairs of each knot (contiguous)
+  std::vector<int64_t> diag_pos;    // [N] position of C_ii in the values
 };
 
 // Returns an empty string on success, otherwise the reason the cover is invalid.

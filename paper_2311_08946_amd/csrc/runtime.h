@@ -82,6 +82,7 @@ struct DeviceCover {
   DevBuf cx, cy, rad, arc0, arc1, rbf_c2, kx, ky, ktheta;
   DevBuf knot_off, rowptr, cols, assigned, float_ids, node_off, fk_off, fk_ids;
   DevBuf perim_ids, perim_pos, mc_knots, bnd_knots;
+  DevBuf pair_off, diag_pos, pair_knot, pair_seg;   // rule AVERAGED (see HostCover)
   DevBuf rt_rowptr, rt_cols, rt_perm;   // transpose pattern of C (built on first use)
   bool have_transpose = false;
   bool tuned = false;                   // schedule chosen by the autotuner for this cover
@@ -164,6 +165,7 @@ int factor_chunk(const DeviceCover& D, const BucketData& bk, const NodeSamples& 
 struct pdd_cover_s {
   pdd::HostCover H;
   pdd::DeviceCover D;
+  pdd::DeviceCover DP;   // rule AVERAGED: the pair rows (H.pairs)
 };
 
 struct pdd_system_s {

@@ -95,3 +95,31 @@ def test_invalid_covers_are_rejected():
     with pytest.raises(pdd.PddError) as e:
         pdd.Cover(workloads.box(0.0, 1.0, 0.0, 0.1), cov)
     assert e.value.code == pdd.PDD_ECOVER
+
+
+@pytest.mark.parametrize("name", ["config1", "small_variable", "disk"])
+def test_averaged_cover_matches_oracle(name):
+    # rule AVERAGED (eqs. 38-39): the wider rows of every containing circle
+    _lib_or_skip()
+    if name == "disk":
+        dom = workloads.disk(0.0, 0.0, 1.0, holes=[(0.3, 0.0, 0.2)])
+        cen = workloads.lattice_centres(14, 14, -1.05, 1.05, -1.05, 1.05)
+        keep = (np.hypot(cen[:, 0], cen[:, 1]) - 0.12 < 1.0) & \
+               (np.hypot(cen[:, 0] - 0.3, cen[:, 1]) + 0.12 > 0.2)
+        cov = workloads._cover(cen[keep], np.full(keep.sum(), 0.12), 16, 16, 4)
+    else:
+        cfg = workloads.config1() if name == "config1" else workloads.small_variable()
+        dom, cov = cfg["problem"]["domain"], dict(cfg["cover"])
+    cov["rule"] = geometry.RULE_AVERAGED
+    ref, cv = _compare(cov, dom)
+    assert int(cv.info.nnz) == len(ref.cols)
+
+
+def test_unknown_rule_is_rejected():
+    _lib_or_skip()
+    cfg = workloads.config1()
+    cov = dict(cfg["cover"])
+    cov["rule"] = 3
+    with pytest.raises(pdd.PddError) as e:
+        pdd.Cover(cfg["problem"]["domain"], cov)
+    assert e.value.code == pdd.PDD_EINVAL
