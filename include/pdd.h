@@ -317,6 +317,59 @@ typedef struct pdd_solve_info {
 pdd_status pdd_solve_G(pdd_system sys, const double* rhs, double* u, int32_t transpose,
                        const pdd_solve_opts* opts, void* stream, pdd_solve_info* info);
 
+/* ------------------------------------------------------- RAS + GMRES */
+
+/*
+ * One-level restricted additive Schwarz preconditioner of Section 4
+ * (eqs. 42-44):  M^-1 = sum_p R_p^T D_p C_p^-1 R_p,  C_p = R_p C R_p^T.
+ * Partition: the circles sorted by centre x (stable) are split into parts_x
+ * slabs of near-equal counts (slab s takes sorted positions
+ * [s n / parts_x, (s+1) n / parts_x)), each slab sorted by centre y into
+ * parts_y parts the same way; empty parts are dropped and the rest numbered
+ * in order.  A knot belongs to the part of the circle it lies on; omega_p adds
+ * every knot adjacent to one of its knots in the graph of C taken symmetric
+ * (one layer).  (D_p)_ii = 1 / (number of omega_q holding knot i), eq. 43.
+ * Each C_p (at most 4096 knots) is factorised on the device by LU with partial
+ * pivoting and kept as its explicit inverse; HBM use is about 16 (#omega_p)^2
+ * bytes per part.  The preconditioner refers to `sys`, which must outlive it.
+ * Errors: PDD_EINVAL (bad counts, a part above 4096 knots), PDD_EBREAKDOWN
+ * (a singular C_p), PDD_ENOMEM, PDD_EDEVICE.  Synchronises `stream`.
+ */
+typedef struct pdd_ras_s* pdd_ras;
+typedef struct pdd_ras_opts {
+  int32_t parts_x, parts_y;   /* >= 1 each                                        */
+} pdd_ras_opts;
+
+pdd_status pdd_ras_build(pdd_system sys, const pdd_ras_opts* opts, void* stream, pdd_ras* out);
+
+/* Parts (host outputs, any may be NULL): n_parts; omega_off [n_parts+1];
+ * omega [omega_off[n_parts]] the sorted knots of each omega_p, concatenated. */
+pdd_status pdd_ras_get_parts(pdd_ras ras, int32_t* n_parts, int64_t* omega_off, int32_t* omega);
+
+/* y = M^-1 x (device [N] each, distinct), enqueued on `stream`. */
+pdd_status pdd_ras_apply(pdd_ras ras, const double* x, double* y, void* stream);
+
+void pdd_destroy_ras(pdd_ras ras);
+
+typedef struct pdd_gmres_opts {
+  double rtol;             /* |g_{j+1}| / |r| (the residual of C u = r), default 1e-12 */
+  int32_t max_iter;        /* default 2000                                             */
+  int32_t restart;         /* Krylov dimension m, default 30, at most 200              */
+} pdd_gmres_opts;
+
+/*
+ * pdd_solve_gmres -- restarted GMRES(m) on C u = r with the preconditioner on
+ * the right (eq. 45): C M^-1 t = r, u = M^-1 t; ras NULL solves without one.
+ * Zero initial guess; Arnoldi by classical Gram-Schmidt applied twice; the
+ * Hessenberg column goes to the host each iteration (one synchronisation) for
+ * the Givens rotations and the convergence test.
+ *   rhs  device [N] or NULL for r;  u  device [N] output.
+ * Errors: PDD_EINVAL, PDD_ENOCONV (u holds the last iterate), PDD_ENOMEM,
+ * PDD_EDEVICE.
+ */
+pdd_status pdd_solve_gmres(pdd_system sys, pdd_ras ras, const double* rhs, double* u,
+                           const pdd_gmres_opts* opts, void* stream, pdd_solve_info* info);
+
 /*
  * pdd_assemble_G_backward -- gradients of a loss L(u) with respect to the node
  * samples of pdd_samples, given u (C u = r) and lambda = C^-T dL/du (device

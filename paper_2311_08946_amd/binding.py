@@ -25,7 +25,8 @@ EXPORTED = [
     "pdd_last_error", "pdd_eval_field", "pdd_build_cover", "pdd_cover_get_info", "pdd_cover_knots",
     "pdd_cover_pattern", "pdd_cover_nodes", "pdd_destroy_cover", "pdd_assemble_G",
     "pdd_system_copy", "pdd_system_get_stats", "pdd_solve_G", "pdd_assemble_G_backward",
-    "pdd_destroy_system",
+    "pdd_destroy_system", "pdd_ras_build", "pdd_ras_get_parts", "pdd_ras_apply", "pdd_destroy_ras",
+    "pdd_solve_gmres",
 ]
 
 
@@ -99,6 +100,14 @@ class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("use_guess", C.c_int32)]
 
 
+class RasOpts(C.Structure):
+    _fields_ = [("parts_x", C.c_int32), ("parts_y", C.c_int32)]
+
+
+class GmresOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("restart", C.c_int32)]
+
+
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("rel_residual", C.c_double)]
 
@@ -132,8 +141,14 @@ def lib():
     L.pdd_assemble_G_backward.argtypes = [vp, vp, vp] + [vp] * 7 + [vp]
     L.pdd_destroy_system.argtypes = [vp]
     L.pdd_destroy_system.restype = None
+    L.pdd_ras_build.argtypes = [vp, C.POINTER(RasOpts), vp, C.POINTER(vp)]
+    L.pdd_ras_get_parts.argtypes = [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32)]
+    L.pdd_ras_apply.argtypes = [vp, vp, vp, vp]
+    L.pdd_destroy_ras.argtypes = [vp]
+    L.pdd_destroy_ras.restype = None
+    L.pdd_solve_gmres.argtypes = [vp, vp, vp, vp, C.POINTER(GmresOpts), vp, C.POINTER(SolveInfo)]
     for name in EXPORTED:
-        if name not in ("pdd_last_error", "pdd_destroy_cover", "pdd_destroy_system"):
+        if name not in ("pdd_last_error", "pdd_destroy_cover", "pdd_destroy_system", "pdd_destroy_ras"):
             getattr(L, name).restype = C.c_int32
     _lib = L
     return L
@@ -353,6 +368,17 @@ class System:
                                  _stream_ptr(stream), C.byref(info)), "solve_G: ")
         return u, info
 
+    def solve_gmres(self, ras=None, rhs=None, rtol=1e-12, max_iter=2000, restart=30, stream=None):
+        """Restarted GMRES with the RAS preconditioner ``ras`` on the right (None: none)."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        u = torch.empty(self.cover.N, dtype=torch.float64, device=dev)
+        go = GmresOpts(rtol, max_iter, restart)
+        info = SolveInfo()
+        _check(lib().pdd_solve_gmres(self._h, ras.handle if ras is not None else None, _tptr(rhs), _tptr(u),
+                                     C.byref(go), _stream_ptr(stream), C.byref(info)), "solve_gmres: ")
+        return u, info
+
     def backward(self, u, lam, stream=None, names=("axx", "axy", "ayy", "bx", "by", "c", "f")):
         import torch
         n = int(self.cover.info.sum_n)
@@ -368,4 +394,43 @@ class System:
         h = getattr(self, "_h", None)
         if h is not None and _lib is not None:
             _lib.pdd_destroy_system(h)
+            self._h = None
+
+
+class Ras:
+    """One-level RAS preconditioner of an assembled system (eqs. 42-44)."""
+
+    def __init__(self, system, parts_x, parts_y, stream=None):
+        L = lib()
+        self.system = system          # the preconditioner refers to the system
+        h = C.c_void_p()
+        code = L.pdd_ras_build(system.handle, C.byref(RasOpts(int(parts_x), int(parts_y))),
+                               _stream_ptr(stream), C.byref(h))
+        self._h = h if h.value else None
+        _check(code, "ras_build: ")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def parts(self):
+        L = lib()
+        P = C.c_int32()
+        _check(L.pdd_ras_get_parts(self._h, C.byref(P), None, None))
+        off = np.zeros(P.value + 1, dtype=np.int64)
+        _check(L.pdd_ras_get_parts(self._h, None, off.ctypes.data_as(C.POINTER(C.c_int64)), None))
+        knots = np.zeros(int(off[-1]), dtype=np.int32)
+        _check(L.pdd_ras_get_parts(self._h, None, None, _iptr(knots)))
+        return [knots[off[p]:off[p + 1]].astype(np.int64) for p in range(P.value)]
+
+    def apply(self, x, stream=None):
+        import torch
+        y = torch.empty_like(x)
+        _check(lib().pdd_ras_apply(self._h, _tptr(x), _tptr(y), _stream_ptr(stream)), "ras_apply: ")
+        return y
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.pdd_destroy_ras(h)
             self._h = None

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libpdd.so")
 
-HIP_SOURCES = ["spectral.hip", "lu.hip", "mc.hip", "capi.hip", "assemble.hip", "solve.hip", "adjoint.hip"]
+HIP_SOURCES = ["spectral.hip", "lu.hip", "mc.hip", "capi.hip", "assemble.hip", "solve.hip", "adjoint.hip", "ras.hip"]
 HOST_SOURCES = ["cover.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
