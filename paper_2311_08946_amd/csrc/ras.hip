@@ -34,7 +34,8 @@ struct pdd_ras_s {
   std::vector<int32_t> knots;           // omega_p, sorted, concatenated
   std::vector<int32_t> npad;            // padded order of each C_p
   std::vector<int64_t> aoff;            // offset (doubles) of each [C_p | C_p^-1]
-  pdd::DevBuf d_off, d_knots, d_npad, d_aoff, d_moff, d_mslot, mat, piv, status, work, t;
+  std::vector<int64_t> poff;            // offset of each part's padded vector slots
+  pdd::DevBuf d_off, d_knots, d_npad, d_aoff, d_poff, d_moff, d_mslot, mat, piv, status, work, t, xg;
 };
 
 namespace pdd {
@@ -88,10 +89,26 @@ __global__ void __launch_bounds__(kBlock) gather_blocks_kernel(
   if (lane == 0) A[np + r] = 1.0;
 }
 
-// t_p = C_p^-1 x|omega_p, one wavefront per row of every part.
+// xg_p = x|omega_p, zero-padded to the part's padded order (the rows of the
+// stored inverses are zero beyond #omega_p, so the GEMV runs over npad).
+__global__ void gather_x_kernel(const int64_t* __restrict__ off, const int32_t* __restrict__ knots,
+                                const int32_t* __restrict__ npad, const int64_t* __restrict__ poff,
+                                const double* __restrict__ x, double* __restrict__ xg) {
+  const int p = blockIdx.y;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int np = npad[p];
+  if (c >= np) return;
+  const int64_t o = off[p];
+  const int n = (int)(off[p + 1] - o);
+  xg[poff[p] + c] = c < n ? x[knots[o + c]] : 0.0;
+}
+
+// t_p = C_p^-1 xg_p, one wavefront per row of every part; 16-byte loads of
+// the row (rows start 256-byte aligned: npad is a multiple of 32), two
+// independent accumulators per lane.
 __global__ void __launch_bounds__(kBlock) block_gemv_kernel(
-    const int64_t* __restrict__ off, const int32_t* __restrict__ knots, const int32_t* __restrict__ npad,
-    const int64_t* __restrict__ aoff, const double* __restrict__ mat, const double* __restrict__ x,
+    const int64_t* __restrict__ off, const int32_t* __restrict__ npad, const int64_t* __restrict__ aoff,
+    const int64_t* __restrict__ poff, const double* __restrict__ mat, const double* __restrict__ xg,
     double* __restrict__ t) {
   const int p = blockIdx.y;
   const int r = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
@@ -100,10 +117,22 @@ __global__ void __launch_bounds__(kBlock) block_gemv_kernel(
   const int n = (int)(off[p + 1] - o);
   if (r >= n) return;
   const int np = npad[p];
-  const double* X = mat + aoff[p] + (int64_t)r * 2 * np + np;
-  double acc = 0.0;
-  for (int c = lane; c < n; c += kWave) acc += X[c] * x[knots[o + c]];
-  acc = wave_sum(acc);
+  const double2* X = reinterpret_cast<const double2*>(mat + aoff[p] + (int64_t)r * 2 * np + np);
+  const double2* xv = reinterpret_cast<const double2*>(xg + poff[p]);
+  const int h = np / 2;
+  double a0 = 0.0, a1 = 0.0;
+  int c = lane;
+  for (; c + kWave < h; c += 2 * kWave) {
+    const double2 u0 = X[c], v0 = xv[c];
+    const double2 u1 = X[c + kWave], v1 = xv[c + kWave];
+    a0 += u0.x * v0.x + u0.y * v0.y;
+    a1 += u1.x * v1.x + u1.y * v1.y;
+  }
+  if (c < h) {
+    const double2 u0 = X[c], v0 = xv[c];
+    a0 += u0.x * v0.x + u0.y * v0.y;
+  }
+  const double acc = wave_sum(a0 + a1);
   if (lane == 0) t[o + r] = acc;
 }
 
@@ -236,10 +265,13 @@ struct Ras {
   hipStream_t st;
   // y = M^-1 x
   void apply(const double* x, double* y) const {
+    hipLaunchKernelGGL(gather_x_kernel, dim3((unsigned)((r->max_npad + kBlock - 1) / kBlock), (unsigned)r->P),
+                       dim3(kBlock), 0, st, r->d_off.ptr<int64_t>(), r->d_knots.ptr<int32_t>(),
+                       r->d_npad.ptr<int32_t>(), r->d_poff.ptr<int64_t>(), x, r->xg.ptr<double>());
     const dim3 g((unsigned)((r->max_npad + 3) / 4), (unsigned)r->P);
     hipLaunchKernelGGL(block_gemv_kernel, g, dim3(kBlock), 0, st, r->d_off.ptr<int64_t>(),
-                       r->d_knots.ptr<int32_t>(), r->d_npad.ptr<int32_t>(), r->d_aoff.ptr<int64_t>(),
-                       r->mat.ptr<double>(), x, r->t.ptr<double>());
+                       r->d_npad.ptr<int32_t>(), r->d_aoff.ptr<int64_t>(), r->d_poff.ptr<int64_t>(),
+                       r->mat.ptr<double>(), r->xg.ptr<double>(), r->t.ptr<double>());
     const int64_t N = r->sys->cover->H.N();
     hipLaunchKernelGGL(combine_kernel, grid1(N), dim3(kBlock), 0, st, N, r->d_moff.ptr<int64_t>(),
                        r->d_mslot.ptr<int64_t>(), r->t.ptr<double>(), y);
@@ -314,6 +346,9 @@ pdd_status ras_build_impl(pdd_system sys, const pdd_ras_opts* opts, hipStream_t 
   R->d_knots.upload(R->knots);
   R->d_npad.upload(R->npad);
   R->d_aoff.upload(R->aoff);
+  R->poff = poff;
+  R->d_poff.upload(R->poff);
+  R->xg.alloc(std::max<int64_t>(1, piv_total) * sizeof(double));
   R->d_moff.upload(moff);
   R->d_mslot.upload(mslot);
   R->mat.alloc(mat_doubles * sizeof(double));
