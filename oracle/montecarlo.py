@@ -27,6 +27,15 @@ Readings where the paper defers to its reference on the integrator:
   estimates over sqrt(B).
 * More than step_cap steps on one path is an error (the representation
   needs E[tau] < infinity, Appendix).
+* Scheme 1 (``mc["scheme"] == 1``): the boundary-shifted Euler scheme of
+  Gobet and Menozzi (the paper's ref. [15]; SPA 120 (2010)).  An accepted end
+  point q that lies closer to a piece of the boundary of Omega_m (the circle,
+  a side of the box, the outer circle or a hole of the disk) than
+  c0 sqrt(h) |sigma^T n|, with n the piece's outward normal at q, sigma taken
+  at the step's left point and c0 = -zeta(1/2) / sqrt(2 pi), stops the path
+  there after the full step; the exit point is q projected onto the nearest
+  such piece (ties: the circle first, then the pieces in the order above).
+  End points outside Omega_m exit as in scheme 0.
 """
 from __future__ import annotations
 
@@ -39,6 +48,8 @@ from . import cardinal, fields, philox
 from .geometry import ROW_MC, inside
 
 TWO_PI = 2.0 * math.pi
+# -zeta(1/2) / sqrt(2 pi): the mean overshoot constant of the shifted scheme
+GM_C0 = 0.5825971579390106
 
 
 class PathCapError(RuntimeError):
@@ -91,6 +102,49 @@ def _exit_domain(dom, px, py, qx, qy):
     return t
 
 
+def _shift_stops(dom, qx, qy, cx, cy, r, s11, s21, s22, sqh):
+    """Scheme 1: for end points q inside Omega_m, whether the path stops
+    (q within c0 sqrt(h) |sigma^T n| of a boundary piece), the projection of q
+    onto the nearest such piece, and whether that piece is the circle."""
+    def band(nx, ny):
+        return GM_C0 * sqh * np.sqrt((s11 * nx + s21 * ny) ** 2 + (s22 * ny) ** 2)
+
+    pieces = []      # (distance, normal x, normal y, projection x, projection y, is circle)
+    ex, ey = qx - cx, qy - cy
+    rho = np.sqrt(ex * ex + ey * ey)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        nx, ny = ex / rho, ey / rho
+    pieces.append((r - rho, nx, ny, cx + r * nx, cy + r * ny, True))
+    one, zero = np.ones_like(qx), np.zeros_like(qx)
+    if dom["kind"] == "box":
+        pieces.append((qx - dom["x0"], -one, zero, np.full_like(qx, dom["x0"]), qy, False))
+        pieces.append((dom["x1"] - qx, one, zero, np.full_like(qx, dom["x1"]), qy, False))
+        pieces.append((qy - dom["y0"], zero, -one, qx, np.full_like(qy, dom["y0"]), False))
+        pieces.append((dom["y1"] - qy, zero, one, qx, np.full_like(qy, dom["y1"]), False))
+    else:
+        fx, fy = qx - dom["cx"], qy - dom["cy"]
+        d = np.sqrt(fx * fx + fy * fy)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ux, uy = fx / d, fy / d
+        pieces.append((dom["R"] - d, ux, uy, dom["cx"] + dom["R"] * ux, dom["cy"] + dom["R"] * uy, False))
+        for hx, hy, hr in dom["holes"]:
+            fx, fy = qx - hx, qy - hy
+            d = np.sqrt(fx * fx + fy * fy)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                ux, uy = fx / d, fy / d
+            pieces.append((d - hr, -ux, -uy, hx + hr * ux, hy + hr * uy, False))
+    best = np.full(qx.shape, np.inf)
+    sx, sy = qx.copy(), qy.copy()
+    gam = np.zeros(qx.shape, dtype=bool)
+    for dist, nx_, ny_, px_, py_, circ in pieces:
+        hit = (dist < band(nx_, ny_)) & (dist < best)
+        best = np.where(hit, dist, best)
+        sx = np.where(hit, px_, sx)
+        sy = np.where(hit, py_, sy)
+        gam = np.where(hit, circ, gam)
+    return np.isfinite(best), sx, sy, gam
+
+
 def arc_angles(cover, m):
     """Local angles of the stencil knots of perimeter circle m (eq. 12)."""
     return cover.knot_theta[cover.knot_off[m]:cover.knot_off[m + 1]]
@@ -112,6 +166,7 @@ def run_paths(problem, cover, mc, knots):
     P = int(mc["paths"])
     cap = int(mc["step_cap"])
     seed = int(mc["seed"])
+    scheme = int(mc.get("scheme", 0))
     knots = np.asarray(knots, dtype=np.int64)
     K = len(knots)
     kk = np.repeat(knots, P)
@@ -151,14 +206,26 @@ def run_paths(problem, cover, mc, knots):
         in_d = inside(dom, qx, qy)
         stay = in_c & in_d
         Y0, Z0 = Yw[active], Zw[active]
+        if scheme == 1 and stay.any():
+            stop, sx, sy, sgam = _shift_stops(dom, qx, qy, ccx, ccy, r, s11, s21, s22, sq)
+            stop &= stay
+            if stop.any():
+                ids = active[stop]
+                ex_x[ids] = sx[stop]
+                ex_y[ids] = sy[stop]
+                ex_Y[ids] = Y0[stop] * np.exp(co["c"][stop] * h[stop])
+                ex_Z[ids] = Z0[stop] + co["f"][stop] * Y0[stop] * h[stop]
+                ex_gamma[ids] = sgam[stop]
+                nsteps[ids] = k + 1
+                stay = stay & ~stop
         # accepted steps
         st = active[stay]
         X[st] = qx[stay]
         Yp[st] = qy[stay]
         Yw[st] = Y0[stay] * np.exp(co["c"][stay] * h[stay])
         Zw[st] = Z0[stay] + co["f"][stay] * Y0[stay] * h[stay]
-        # exits
-        e = ~stay
+        # exits through the boundary
+        e = ~(in_c & in_d)
         if e.any():
             px, py, tqx, tqy = x[e], y[e], qx[e], qy[e]
             dxe, dye = tqx - px, tqy - py
