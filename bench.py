@@ -156,6 +156,10 @@ WORKLOADS = {
                     label="Section 4 test problem: Poisson with the exact solution of eq. 46 on [-50,50]^2, "
                           "10x10 circles r in [8.55, 9.43], M=Ntheta=44, Nr=22 (n=968), c^2=1.5, "
                           "5000 paths/perimeter knot, h=0.015 (plain Euler)"),
+    "paper50_gm": dict(adjoint=True, budget=0,
+                       label="Section 4 test problem as run in the paper: eq. 46 on [-50,50]^2, 10x10 circles, "
+                             "M=Ntheta=44, Nr=22, averaged rows (eqs. 38-39), boundary-shifted Euler, "
+                             "5000 paths/perimeter knot, h=0.015"),
 }
 
 

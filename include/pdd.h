@@ -208,7 +208,11 @@ typedef struct pdd_mc_opts {
   int32_t n_batches;       /* batches for standard errors (2..64)                      */
   int32_t step_cap;        /* maximum steps of one path (> 0)                          */
   const double* h_per_circle;  /* host [n_circles] or NULL: per-circle step            */
+  int32_t scheme;          /* PDD_MC_EULER or PDD_MC_SHIFTED (see pdd_assemble_G)      */
+  int32_t reserved;
 } pdd_mc_opts;
+
+enum { PDD_MC_EULER = 0, PDD_MC_SHIFTED = 1 };
 
 enum { PDD_PLAN_BATCHED = 0, PDD_PLAN_PER_CIRCLE = 1, PDD_PLAN_AUTOTUNED = 2 };
 
@@ -255,7 +259,14 @@ typedef struct pdd_assemble_opts {
  * sides [A_IB H | -F] (eqs. 32, 35, 41), and the solutions are interpolated at
  * the knots assigned to the circle.  Perimeter rows: `mc->paths` Euler paths
  * per knot; step k of path p from knot i draws Philox4x32-10 at counter
- * (k, p, i, 0).  Boundary rows: C_ii = 1, r_i = g(x_i).  Rule AVERAGED: each
+ * (k, p, i, 0).  Scheme PDD_MC_SHIFTED is the boundary-shifted Euler scheme of
+ * Gobet and Menozzi (the paper's ref. [15]): an end point inside the
+ * subdomain closer to a boundary piece (the circle, a box side, the disk's
+ * outer circle or a hole) than c0 sqrt(h) |sigma^T n| (n the piece's normal,
+ * sigma the Cholesky factor of a at the step's start, c0 = -zeta(1/2) /
+ * sqrt(2 pi)) stops the path after that step, at its projection onto the
+ * nearest such piece; end points outside exit at the first crossing as in
+ * PDD_MC_EULER.  Boundary rows: C_ii = 1, r_i = g(x_i).  Rule AVERAGED: each
  * pair (knot i, circle m) is assembled as the row circle m gives at x_i (the
  * pair's index takes the place of i in the Philox counter), then row i is
  * C_ii = number of pairs, the pairs' stencil entries, r_i = sum of the

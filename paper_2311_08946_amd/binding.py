@@ -73,7 +73,7 @@ class Samples(C.Structure):
 class McOpts(C.Structure):
     _fields_ = [("paths", C.c_int64), ("h", C.c_double), ("seed", C.c_uint64),
                 ("n_batches", C.c_int32), ("step_cap", C.c_int32),
-                ("h_per_circle", C.POINTER(C.c_double))]
+                ("h_per_circle", C.POINTER(C.c_double)), ("scheme", C.c_int32), ("reserved", C.c_int32)]
 
 
 class AssembleOpts(C.Structure):
@@ -322,6 +322,7 @@ class System:
         mo = McOpts()
         mo.paths, mo.h, mo.seed = int(mc["paths"]), float(mc["h"]), int(mc["seed"])
         mo.n_batches, mo.step_cap = int(mc["n_batches"]), int(mc["step_cap"])
+        mo.scheme = int(mc.get("scheme", 0))
         if mc.get("h_per_circle") is not None:
             hpc = np.ascontiguousarray(mc["h_per_circle"], dtype=np.float64)
             keep.append(hpc)

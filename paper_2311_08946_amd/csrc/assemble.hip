@@ -455,7 +455,8 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
   if (!H.mc_knots.empty()) {
     if (!mc) return fail(PDD_EINVAL, "pdd_assemble_G: Monte Carlo options are required");
     if (mc->paths < 2 || !(mc->h > 0.0) || mc->n_batches < 2 || mc->n_batches > 63 ||
-        mc->step_cap <= 0 || mc->paths < mc->n_batches || mc->paths > ((int64_t)1 << 32))
+        mc->step_cap <= 0 || mc->paths < mc->n_batches || mc->paths > ((int64_t)1 << 32) ||
+        mc->scheme < PDD_MC_EULER || mc->scheme > PDD_MC_SHIFTED)
       return fail(PDD_EINVAL, "pdd_assemble_G: bad Monte Carlo options");
     const int64_t tri = (int64_t)H.max_arc * (H.max_arc + 1) / 2;
     if ((tri + (int64_t)(mc->n_batches + 1) * H.max_arc) * (int64_t)sizeof(double) > 160 * 1024)
@@ -614,6 +615,7 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
     a.paths = mc->paths;
     a.n_batches = mc->n_batches;
     a.step_cap = mc->step_cap;
+    a.scheme = mc->scheme;
     a.n_units = n_mc * mc->n_batches;
     a.out_stride = std::max<int64_t>(1, H.max_arc);
     a.gram_stride = (int64_t)H.max_arc * (H.max_arc + 1) / 2;

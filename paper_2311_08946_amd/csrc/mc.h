@@ -32,6 +32,7 @@ struct McArgs {
   int64_t paths;
   int32_t n_batches;
   int32_t step_cap;
+  int32_t scheme;              // 0 plain Euler, 1 boundary-shifted (Gobet-Menozzi)
   int64_t n_units;             // n_mc * n_batches
   // per-unit results (device)
   double* out_phi;             // [n_units][out_stride]

@@ -98,8 +98,75 @@ __device__ __forceinline__ double domain_exit(const pdd_domain& d, double px, do
   return t;
 }
 
-template <bool CONST_COEF>
-__global__ __launch_bounds__(256) void paths_kernel(const DevProblem* __restrict__ P, McArgs a) {
+// -zeta(1/2) / sqrt(2 pi): the mean overshoot constant of the shifted scheme
+constexpr double kGmC0 = 0.5825971579390106;
+
+// Boundary-shifted Euler (Gobet and Menozzi, SPA 120 (2010)): an end point q
+// inside Omega_m closer to a boundary piece (the circle; box sides, or the
+// outer circle and holes of a disk) than c0 sqrt(h) |sigma^T n| stops the
+// path.  Returns whether it does, the projection of q onto the nearest such
+// piece (ties: the circle first, then the pieces in that order) and whether
+// that piece is the circle.  sigma is the left point's Cholesky factor.
+__device__ __forceinline__ bool shift_stop(const pdd_domain& d, double qx, double qy, double cx, double cy,
+                                           double r, double a11, double a21, double a22, double sqh,
+                                           double& sx, double& sy, bool& gam) {
+  double best = INFINITY;
+  auto consider = [&](double dist, double nx, double ny, double px, double py, bool circ) {
+    const double t1 = a11 * nx + a21 * ny, t2 = a22 * ny;
+    const double band = kGmC0 * sqh * sqrt(t1 * t1 + t2 * t2);
+    if (dist < band && dist < best) {
+      best = dist;
+      sx = px;
+      sy = py;
+      gam = circ;
+    }
+  };
+  {
+    const double ex = qx - cx, ey = qy - cy;
+    const double rho = sqrt(ex * ex + ey * ey);
+    const double nx = ex / rho, ny = ey / rho;
+    consider(r - rho, nx, ny, cx + r * nx, cy + r * ny, true);
+  }
+  if (d.kind == PDD_DOMAIN_BOX) {
+    consider(qx - d.x0, -1.0, 0.0, d.x0, qy, false);
+    consider(d.x1 - qx, 1.0, 0.0, d.x1, qy, false);
+    consider(qy - d.y0, 0.0, -1.0, qx, d.y0, false);
+    consider(d.y1 - qy, 0.0, 1.0, qx, d.y1, false);
+  } else {
+    {
+      const double fx = qx - d.cx, fy = qy - d.cy;
+      const double dd = sqrt(fx * fx + fy * fy);
+      const double ux = fx / dd, uy = fy / dd;
+      consider(d.R - dd, ux, uy, d.cx + d.R * ux, d.cy + d.R * uy, false);
+    }
+    for (int hh = 0; hh < d.n_holes; ++hh) {
+      const double hx = d.holes[hh][0], hy = d.holes[hh][1], hr = d.holes[hh][2];
+      const double fx = qx - hx, fy = qy - hy;
+      const double dd = sqrt(fx * fx + fy * fy);
+      const double ux = fx / dd, uy = fy / dd;
+      consider(dd - hr, -ux, -uy, hx + hr * ux, hy + hr * uy, false);
+    }
+  }
+  return best < INFINITY;
+}
+
+// Whether q (inside Omega_m, at distance dc from the circle) lies within
+// `band` of the circle or of a piece of the domain boundary.
+__device__ __forceinline__ bool near_boundary(const pdd_domain& d, double qx, double qy, double dc, double band) {
+  if (dc < band) return true;
+  if (d.kind == PDD_DOMAIN_BOX)
+    return qx - d.x0 < band || d.x1 - qx < band || qy - d.y0 < band || d.y1 - qy < band;
+  const double fx = qx - d.cx, fy = qy - d.cy;
+  if (d.R - sqrt(fx * fx + fy * fy) < band) return true;
+  for (int hh = 0; hh < d.n_holes; ++hh) {
+    const double gx = qx - d.holes[hh][0], gy = qy - d.holes[hh][1];
+    if (sqrt(gx * gx + gy * gy) - d.holes[hh][2] < band) return true;
+  }
+  return false;
+}
+
+template <bool CONST_COEF, bool SHIFT>
+__device__ __forceinline__ void paths_body(const DevProblem* __restrict__ P, const McArgs& a) {
   const int lane = threadIdx.x & 63;
   const int64_t unit = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (unit >= a.n_units) return;                     // whole wavefront leaves together
@@ -176,7 +243,15 @@ __global__ __launch_bounds__(256) void paths_kernel(const DevProblem* __restrict
       const double ex = qx - cx, ey = qy - cy;
       const bool in_c = ex * ex + ey * ey < r2;
       const bool in_d = in_domain(PP.dom, qx, qy);
-      if (in_c && in_d) {
+      bool stop = false, s_gam = false;
+      double s_x = 0.0, s_y = 0.0;
+      // |sigma^T n| <= |sigma|_F: end points farther than that band from every
+      // piece cannot stop, and most steps are decided without the normals
+      if (SHIFT && in_c && in_d &&
+          near_boundary(PP.dom, qx, qy, r - sqrt(ex * ex + ey * ey),
+                        kGmC0 * sqh * sqrt(a11 * a11 + a21 * a21 + a22 * a22) * (1.0 + 1e-12)))
+        stop = shift_stop(PP.dom, qx, qy, cx, cy, r, a11, a21, a22, sqh, s_x, s_y, s_gam);
+      if (in_c && in_d && !stop) {
         Z = Z + ff * Y * h;
         Y = Y * ec;
         x = qx;
@@ -188,14 +263,24 @@ __global__ __launch_bounds__(256) void paths_kernel(const DevProblem* __restrict
           exited = true;
         }
       } else {
-        const double dx = qx - x, dy = qy - y;
-        const double tc = in_c ? INFINITY : exit_root(x, y, dx, dy, cx, cy, r);
-        const double td = in_d ? INFINITY : domain_exit(PP.dom, x, y, qx, qy);
-        const double ts = fmin(fmax(fmin(tc, td), 0.0), 1.0);
-        const double xe = x + ts * dx, ye = y + ts * dy;
-        const double Ye = Y * exp(cc * ts * h);
-        const double Ze = Z + ff * Y * ts * h;
-        on_gamma = tc <= td;
+        double xe, ye, Ye, Ze;
+        if (stop) {                        // shifted boundary: stopped after the full step
+          xe = s_x;
+          ye = s_y;
+          Ye = Y * ec;
+          Ze = Z + ff * Y * h;
+          on_gamma = s_gam;
+        } else {
+          const double dx = qx - x, dy = qy - y;
+          const double tc = in_c ? INFINITY : exit_root(x, y, dx, dy, cx, cy, r);
+          const double td = in_d ? INFINITY : domain_exit(PP.dom, x, y, qx, qy);
+          const double ts = fmin(fmax(fmin(tc, td), 0.0), 1.0);
+          xe = x + ts * dx;
+          ye = y + ts * dy;
+          Ye = Y * exp(cc * ts * h);
+          Ze = Z + ff * Y * ts * h;
+          on_gamma = tc <= td;
+        }
         acc_g += (on_gamma ? 0.0 : boundary_value(PP, xe, ye) * Ye) + Ze;
         steps += (uint64_t)k + 1;
         exited = true;
@@ -250,6 +335,19 @@ __global__ __launch_bounds__(256) void paths_kernel(const DevProblem* __restrict
     a.out_steps[unit] = steps;
     a.out_capped[unit] = capped;
   }
+}
+
+template <bool CONST_COEF>
+__global__ __launch_bounds__(256) void paths_kernel(const DevProblem* __restrict__ P, McArgs a) {
+  paths_body<CONST_COEF, false>(P, a);
+}
+
+// The shifted scheme's extra live values would otherwise push the kernel
+// to one wavefront per SIMD.
+template <bool CONST_COEF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void paths_shifted_kernel(
+    const DevProblem* __restrict__ P, McArgs a) {
+  paths_body<CONST_COEF, true>(P, a);
 }
 
 // Packed lower-triangle index (j <= i).
@@ -415,8 +513,13 @@ __global__ void boundary_rows_kernel(const DevProblem* __restrict__ P, const int
 void launch_mc_paths(const DevProblem* P, bool const_coef, const McArgs& a, hipStream_t st) {
   if (a.n_units == 0) return;
   const unsigned blocks = (unsigned)((a.n_units + 3) / 4);
-  if (const_coef)
+  const bool shift = a.scheme == 1;
+  if (const_coef && shift)
+    hipLaunchKernelGGL(paths_shifted_kernel<true>, dim3(blocks), dim3(256), 0, st, P, a);
+  else if (const_coef)
     hipLaunchKernelGGL(paths_kernel<true>, dim3(blocks), dim3(256), 0, st, P, a);
+  else if (shift)
+    hipLaunchKernelGGL(paths_shifted_kernel<false>, dim3(blocks), dim3(256), 0, st, P, a);
   else
     hipLaunchKernelGGL(paths_kernel<false>, dim3(blocks), dim3(256), 0, st, P, a);
 }

@@ -293,14 +293,16 @@ def eq46():
     return {"kind": "eq46"}
 
 
-def paper_poisson(half=50.0, paths=5000, h=0.015, seed=46):
+def paper_poisson(half=50.0, paths=5000, h=0.015, seed=46, rule=RULE_FLOAT_FIRST_MAX_DEPTH, scheme=0):
     """Section 4's test problem: Poisson's equation with the exact solution of
     eq. 46 and Dirichlet data equal to it, on the square [-half, half]^2.
     Circles on a square lattice of spacing 10 (100 circles at half = 50, as in
     Table 1; Figure 5's exact layout is not available), radii drawn uniformly
     in [8.55, 9.43], 44 knots and 44 x 22 collocation nodes per circle (n = 968),
-    c^2 = 1.5, paths per perimeter knot and h as in Section 4 (plain Euler
-    here instead of Gobet-Menozzi with variance reduction)."""
+    c^2 = 1.5, paths per perimeter knot and h as in Section 4.  ``rule`` picks
+    the row choice (2: averaged rows) and ``scheme`` the integrator (0 plain
+    Euler, 1 boundary-shifted Gobet-Menozzi; the paper's variance reduction is
+    not included)."""
     rng = np.random.default_rng(seed)
     n_side = int(round(2.0 * half / 10.0))
     centres = lattice_centres(n_side, n_side, -half, half, -half, half)
@@ -312,13 +314,21 @@ def paper_poisson(half=50.0, paths=5000, h=0.015, seed=46):
         "bx": const(0.0), "by": const(0.0), "c": const(0.0),
         "f": derived_f(u), "g": u, "u_exact": u,
     }
-    cover = _cover(centres, radii, 44, 44, 22, rbf_c2=1.5)
-    return {"name": f"paper_poisson_{int(half)}", "problem": prob, "cover": cover,
-            "mc": mc_opts(paths, h, seed=seed)}
+    cover = _cover(centres, radii, 44, 44, 22, rbf_c2=1.5, rule=rule)
+    mc = mc_opts(paths, h, seed=seed)
+    mc["scheme"] = int(scheme)
+    return {"name": f"paper_poisson_{int(half)}", "problem": prob, "cover": cover, "mc": mc}
+
+
+def paper_poisson_as_run(half=50.0):
+    """Section 4's problem with the paper's row choice (averaged rows, which
+    Table 1's density points to) and integrator (boundary-shifted Euler)."""
+    return paper_poisson(half=half, rule=2, scheme=1)
 
 
 CONFIGS = {
     "config1": config1, "config2": config2, "config3": config3,
     "config4": config4, "config5": config5,
     "paper50": paper_poisson,
+    "paper50_gm": paper_poisson_as_run,
 }
