@@ -293,28 +293,38 @@ pdd_status ras_build_impl(pdd_system sys, const pdd_ras_opts* opts, hipStream_t 
   const std::vector<int32_t> cpart = circle_parts(H, px, py, P);
   std::vector<int32_t> kpart(N);
   for (int64_t i = 0; i < N; ++i) kpart[i] = cpart[H.owner[i]];
-  // omega_p: own knots and one layer of the symmetric graph of C
-  std::vector<std::vector<char>> mark(P, std::vector<char>(N, 0));
-  for (int64_t i = 0; i < N; ++i) {
-    mark[kpart[i]][i] = 1;
-    for (int64_t e = H.rowptr[i]; e < H.rowptr[i + 1]; ++e) {
-      const int32_t j = H.cols[e];
-      mark[kpart[i]][j] = 1;
-      mark[kpart[j]][i] = 1;
-    }
+  // omega_p: own knots and one layer of the symmetric graph of C (rows of
+  // C and of C^T), built per part from its own knots
+  std::vector<int64_t> trp(N + 1, 0);
+  for (int64_t e = 0; e < H.rowptr[N]; ++e) ++trp[H.cols[e] + 1];
+  for (int64_t i = 0; i < N; ++i) trp[i + 1] += trp[i];
+  std::vector<int32_t> trc(H.rowptr[N]);
+  {
+    std::vector<int64_t> fill(trp.begin(), trp.end() - 1);
+    for (int64_t i = 0; i < N; ++i)
+      for (int64_t e = H.rowptr[i]; e < H.rowptr[i + 1]; ++e) trc[fill[H.cols[e]]++] = (int32_t)i;
   }
+  std::vector<std::vector<int32_t>> own(P);
+  for (int64_t i = 0; i < N; ++i) own[kpart[i]].push_back((int32_t)i);
   R->P = P;
   R->off.assign(P + 1, 0);
   std::vector<std::vector<int64_t>> slots(N);
+  std::vector<int32_t> w;
   for (int p = 0; p < P; ++p) {
-    for (int64_t i = 0; i < N; ++i)
-      if (mark[p][i]) {
-        slots[i].push_back((int64_t)R->knots.size());
-        R->knots.push_back((int32_t)i);
-      }
+    w.clear();
+    for (int32_t i : own[p]) {
+      w.push_back(i);
+      w.insert(w.end(), H.cols.begin() + H.rowptr[i], H.cols.begin() + H.rowptr[i + 1]);
+      w.insert(w.end(), trc.begin() + trp[i], trc.begin() + trp[i + 1]);
+    }
+    std::sort(w.begin(), w.end());
+    w.erase(std::unique(w.begin(), w.end()), w.end());
+    for (int32_t i : w) {
+      slots[i].push_back((int64_t)R->knots.size());
+      R->knots.push_back(i);
+    }
     R->off[p + 1] = (int64_t)R->knots.size();
   }
-  mark.clear();
   R->total = (int64_t)R->knots.size();
   R->npad.resize(P);
   R->aoff.assign(P, 0);
