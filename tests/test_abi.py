@@ -123,3 +123,17 @@ def test_unknown_rule_is_rejected():
     with pytest.raises(pdd.PddError) as e:
         pdd.Cover(cfg["problem"]["domain"], cov)
     assert e.value.code == pdd.PDD_EINVAL
+
+
+def test_null_handles_are_rejected_without_device_work():
+    # argument checks of the RAS and GMRES entry points happen on the host
+    L = _lib_or_skip()
+    import ctypes as C
+    out = C.c_void_p()
+    assert L.pdd_ras_build(None, None, None, C.byref(out)) == pdd.PDD_EINVAL
+    assert out.value is None
+    assert L.pdd_ras_get_parts(None, None, None, None) == pdd.PDD_EINVAL
+    assert L.pdd_ras_apply(None, None, None, None) == pdd.PDD_EINVAL
+    assert L.pdd_solve_gmres(None, None, None, None, None, None, None) == pdd.PDD_EINVAL
+    assert b"null" in L.pdd_last_error()
+    L.pdd_destroy_ras(None)
