@@ -372,8 +372,8 @@ typedef struct pdd_gmres_opts {
  * pdd_solve_gmres -- restarted GMRES(m) on C u = r with the preconditioner on
  * the right (eq. 45): C M^-1 t = r, u = M^-1 t; ras NULL solves without one.
  * Zero initial guess; Arnoldi by classical Gram-Schmidt applied twice; the
- * Hessenberg column goes to the host each iteration (one synchronisation) for
- * the Givens rotations and the convergence test.
+ * Givens rotations and the convergence test run on the device, and `stream`
+ * is synchronised once per 8 iterations and once per restart.
  *   rhs  device [N] or NULL for r;  u  device [N] output.
  * Errors: PDD_EINVAL, PDD_ENOCONV (u holds the last iterate), PDD_ENOMEM,
  * PDD_EDEVICE.

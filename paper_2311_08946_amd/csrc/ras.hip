@@ -13,8 +13,9 @@
 //
 // GMRES(m): Arnoldi by classical Gram-Schmidt applied twice (two passes of
 // one multi-dot and one update each, instead of j + 1 sequential dot/axpy
-// pairs), the Hessenberg column copied to the host once per iteration for the
-// Givens rotations and the convergence test.
+// pairs); the Givens rotations and the convergence test run on the device in
+// one single-thread kernel per iteration, and the host reads the state once
+// per batch of iterations.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -93,7 +94,9 @@ __global__ void __launch_bounds__(kBlock) gather_blocks_kernel(
 // stored inverses are zero beyond #omega_p, so the GEMV runs over npad).
 __global__ void gather_x_kernel(const int64_t* __restrict__ off, const int32_t* __restrict__ knots,
                                 const int32_t* __restrict__ npad, const int64_t* __restrict__ poff,
-                                const double* __restrict__ x, double* __restrict__ xg) {
+                                const double* __restrict__ x, double* __restrict__ xg,
+                                const int* __restrict__ stop) {
+  if (stop && *stop) return;
   const int p = blockIdx.y;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int np = npad[p];
@@ -109,7 +112,8 @@ __global__ void gather_x_kernel(const int64_t* __restrict__ off, const int32_t* 
 __global__ void __launch_bounds__(kBlock) block_gemv_kernel(
     const int64_t* __restrict__ off, const int32_t* __restrict__ npad, const int64_t* __restrict__ aoff,
     const int64_t* __restrict__ poff, const double* __restrict__ mat, const double* __restrict__ xg,
-    double* __restrict__ t) {
+    double* __restrict__ t, const int* __restrict__ stop) {
+  if (stop && *stop) return;
   const int p = blockIdx.y;
   const int r = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
@@ -138,7 +142,9 @@ __global__ void __launch_bounds__(kBlock) block_gemv_kernel(
 
 // y_i = sum over the parts holding knot i (in part order) of D_ii t_p(i).
 __global__ void combine_kernel(int64_t N, const int64_t* __restrict__ moff, const int64_t* __restrict__ mslot,
-                               const double* __restrict__ t, double* __restrict__ y) {
+                               const double* __restrict__ t, double* __restrict__ y,
+                               const int* __restrict__ stop) {
+  if (stop && *stop) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   const int64_t a = moff[i], b = moff[i + 1];
@@ -152,7 +158,9 @@ __global__ void __launch_bounds__(kBlock) spmv_kernel(int64_t N, const int64_t* 
                                                       const int32_t* __restrict__ cols,
                                                       const double* __restrict__ val,
                                                       const double* __restrict__ x, double* __restrict__ y,
-                                                      const double* __restrict__ sub) {
+                                                      const double* __restrict__ sub,
+                                                      const int* __restrict__ stop) {
+  if (stop && *stop) return;
   const int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
   if (i >= N) return;
@@ -165,7 +173,9 @@ __global__ void __launch_bounds__(kBlock) spmv_kernel(int64_t N, const int64_t* 
 // part[k * kDotBlocks + blk] = partial <w, V_k> over this block's rows, k < nv.
 __global__ void __launch_bounds__(kBlock) multidot_kernel(int64_t N, int nv, const double* __restrict__ V,
                                                           const double* __restrict__ w,
-                                                          double* __restrict__ part) {
+                                                          double* __restrict__ part,
+                                                          const int* __restrict__ stop) {
+  if (stop && *stop) return;
   __shared__ double red[kBlock / kWave];
   const int64_t chunk = (N + kDotBlocks - 1) / kDotBlocks;
   const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(N, i0 + chunk);
@@ -186,7 +196,9 @@ __global__ void __launch_bounds__(kBlock) multidot_kernel(int64_t N, int nv, con
 }
 
 // h[k] (+)= sum of the partials of dot k, in block order; one wavefront per dot.
-__global__ void reduce_dots_kernel(int nv, const double* __restrict__ part, double* __restrict__ h, int accumulate) {
+__global__ void reduce_dots_kernel(int nv, const double* __restrict__ part, double* __restrict__ h, int accumulate,
+                                   const int* __restrict__ stop) {
+  if (stop && *stop) return;
   const int k = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   if (k >= nv) return;
@@ -198,7 +210,8 @@ __global__ void reduce_dots_kernel(int nv, const double* __restrict__ part, doub
 
 // w -= sum_k c[k] V_k  (c read from device memory)
 __global__ void update_kernel(int64_t N, int nv, const double* __restrict__ V, const double* __restrict__ c,
-                              double* __restrict__ w) {
+                              double* __restrict__ w, const int* __restrict__ stop) {
+  if (stop && *stop) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   double s = w[i];
@@ -208,7 +221,8 @@ __global__ void update_kernel(int64_t N, int nv, const double* __restrict__ V, c
 
 // v = w / sqrt(nrm2) (v = 0 when the norm vanishes); nrm[1] receives the norm.
 __global__ void normalise_kernel(int64_t N, const double* __restrict__ w, double* __restrict__ nrm,
-                                 double* __restrict__ v) {
+                                 double* __restrict__ v, const int* __restrict__ stop) {
+  if (stop && *stop) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const double s = sqrt(nrm[0]);
   if (i == 0) nrm[1] = s;
@@ -230,9 +244,50 @@ __global__ void axpy_kernel(int64_t N, const double* __restrict__ x, double* __r
   if (i < N) y[i] += x[i];
 }
 
-__global__ void copy_kernel(int64_t N, const double* __restrict__ x, double* __restrict__ y) {
+__global__ void copy_kernel(int64_t N, const double* __restrict__ x, double* __restrict__ y,
+                            const int* __restrict__ stop) {
+  if (stop && *stop) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < N) y[i] = x[i];
+}
+
+// GMRES state kept on the device between host checks.
+struct GmState {
+  int stop;     // the cycle has ended: converged or out of iterations
+  int k;        // Arnoldi columns of this cycle
+  int iters;    // iterations over all cycles
+  int pad;
+  double rel;   // |g_{k}| / |r|
+};
+
+// Column j of the Hessenberg matrix (row-major, (m+1) x m) from the Gram-
+// Schmidt coefficients h[0..j] and the new vector's norm nrm[1]; the earlier
+// Givens rotations on it, a new rotation, the residual estimate and the stop
+// test.  One thread.
+__global__ void givens_kernel(int j, int m, const double* __restrict__ h, const double* __restrict__ nrm,
+                              double* __restrict__ Hm, double* __restrict__ cs, double* __restrict__ sn,
+                              double* __restrict__ g, GmState* __restrict__ gs, double bnorm, double rtol,
+                              int max_iter) {
+  if (threadIdx.x != 0 || gs->stop) return;
+  for (int i = 0; i <= j; ++i) Hm[(int64_t)i * m + j] = h[i];
+  Hm[(int64_t)(j + 1) * m + j] = nrm[1];
+  for (int i = 0; i < j; ++i) {
+    const double a = Hm[(int64_t)i * m + j], c = Hm[(int64_t)(i + 1) * m + j];
+    Hm[(int64_t)i * m + j] = cs[i] * a + sn[i] * c;
+    Hm[(int64_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+  }
+  const double a = Hm[(int64_t)j * m + j], c = Hm[(int64_t)(j + 1) * m + j];
+  const double den = hypot(a, c);
+  cs[j] = a / den;
+  sn[j] = c / den;
+  Hm[(int64_t)j * m + j] = den;
+  Hm[(int64_t)(j + 1) * m + j] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  gs->iters += 1;
+  gs->k = j + 1;
+  gs->rel = fabs(g[j + 1]) / bnorm;
+  if (gs->rel <= rtol || gs->iters >= max_iter) gs->stop = 1;
 }
 
 inline dim3 grid1(int64_t N) { return dim3((unsigned)std::max<int64_t>(1, (N + kBlock - 1) / kBlock)); }
@@ -263,18 +318,18 @@ std::vector<int32_t> circle_parts(const HostCover& H, int px, int py, int32_t& P
 struct Ras {
   pdd_ras r;
   hipStream_t st;
-  // y = M^-1 x
-  void apply(const double* x, double* y) const {
+  // y = M^-1 x (nothing when *stop is set)
+  void apply(const double* x, double* y, const int* stop = nullptr) const {
     hipLaunchKernelGGL(gather_x_kernel, dim3((unsigned)((r->max_npad + kBlock - 1) / kBlock), (unsigned)r->P),
                        dim3(kBlock), 0, st, r->d_off.ptr<int64_t>(), r->d_knots.ptr<int32_t>(),
-                       r->d_npad.ptr<int32_t>(), r->d_poff.ptr<int64_t>(), x, r->xg.ptr<double>());
+                       r->d_npad.ptr<int32_t>(), r->d_poff.ptr<int64_t>(), x, r->xg.ptr<double>(), stop);
     const dim3 g((unsigned)((r->max_npad + 3) / 4), (unsigned)r->P);
     hipLaunchKernelGGL(block_gemv_kernel, g, dim3(kBlock), 0, st, r->d_off.ptr<int64_t>(),
                        r->d_npad.ptr<int32_t>(), r->d_aoff.ptr<int64_t>(), r->d_poff.ptr<int64_t>(),
-                       r->mat.ptr<double>(), r->xg.ptr<double>(), r->t.ptr<double>());
+                       r->mat.ptr<double>(), r->xg.ptr<double>(), r->t.ptr<double>(), stop);
     const int64_t N = r->sys->cover->H.N();
     hipLaunchKernelGGL(combine_kernel, grid1(N), dim3(kBlock), 0, st, N, r->d_moff.ptr<int64_t>(),
-                       r->d_mslot.ptr<int64_t>(), r->t.ptr<double>(), y);
+                       r->d_mslot.ptr<int64_t>(), r->t.ptr<double>(), y, stop);
   }
 };
 
@@ -309,16 +364,21 @@ pdd_status ras_build_impl(pdd_system sys, const pdd_ras_opts* opts, hipStream_t 
   R->P = P;
   R->off.assign(P + 1, 0);
   std::vector<std::vector<int64_t>> slots(N);
-  std::vector<int32_t> w;
+  std::vector<int32_t> w, seen(N, -1);   // seen[j] == p: j already in omega_p
   for (int p = 0; p < P; ++p) {
     w.clear();
+    auto add = [&](int32_t j) {
+      if (seen[j] != p) {
+        seen[j] = p;
+        w.push_back(j);
+      }
+    };
     for (int32_t i : own[p]) {
-      w.push_back(i);
-      w.insert(w.end(), H.cols.begin() + H.rowptr[i], H.cols.begin() + H.rowptr[i + 1]);
-      w.insert(w.end(), trc.begin() + trp[i], trc.begin() + trp[i + 1]);
+      add(i);
+      for (int64_t e = H.rowptr[i]; e < H.rowptr[i + 1]; ++e) add(H.cols[e]);
+      for (int64_t e = trp[i]; e < trp[i + 1]; ++e) add(trc[e]);
     }
     std::sort(w.begin(), w.end());
-    w.erase(std::unique(w.begin(), w.end()), w.end());
     for (int32_t i : w) {
       slots[i].push_back((int64_t)R->knots.size());
       R->knots.push_back(i);
@@ -412,10 +472,13 @@ pdd_status gmres_impl(pdd_system sys, pdd_ras ras, const double* rhs, double* u,
   const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 2000;
   const int m = (opts && opts->restart > 0) ? std::min(opts->restart, 200) : 30;
   const double* b = rhs ? rhs : sys->b.ptr<double>();
-  DevBuf work;
-  // V [m+1][N], w, z, s, partial sums, h and norm scratch
+  // V [m+1][N], w, z, s, partial sums, h, y, norm scratch, Hessenberg
+  // [(m+1) m], rotations, g, state
   const int64_t nv = (int64_t)(m + 1) * N;
-  work.alloc(sizeof(double) * (nv + 3 * N + (int64_t)(m + 2) * kDotBlocks + 2 * (m + 2) + 4));
+  const int64_t nd = nv + 3 * N + (int64_t)(m + 2) * kDotBlocks + 2 * (m + 2) + 4 + (int64_t)(m + 1) * m +
+                     2 * m + (m + 1);
+  DevBuf work;
+  work.alloc(sizeof(double) * nd + sizeof(GmState));
   double* V = work.ptr<double>();
   double* w = V + nv;
   double* z = w + N;
@@ -424,30 +487,37 @@ pdd_status gmres_impl(pdd_system sys, pdd_ras ras, const double* rhs, double* u,
   double* h = part + (int64_t)(m + 2) * kDotBlocks;
   double* yv = h + (m + 2);
   double* nrm = yv + (m + 2);
+  double* Hm = nrm + 4;
+  double* cs = Hm + (int64_t)(m + 1) * m;
+  double* sn = cs + m;
+  double* g = sn + m;
+  GmState* gs = reinterpret_cast<GmState*>(g + (m + 1));
+  const int* stop = &gs->stop;
   const Ras prec{ras, st};
-  auto precond = [&](const double* x, double* y) {
-    if (ras) prec.apply(x, y);
-    else hipLaunchKernelGGL(copy_kernel, grid1(N), dim3(kBlock), 0, st, N, x, y);
+  auto precond = [&](const double* x, double* y, const int* flag) {
+    if (ras) prec.apply(x, y, flag);
+    else hipLaunchKernelGGL(copy_kernel, grid1(N), dim3(kBlock), 0, st, N, x, y, flag);
   };
-  auto spmv = [&](const double* x, double* y, const double* sub) {
+  auto spmv = [&](const double* x, double* y, const double* sub, const int* flag) {
     hipLaunchKernelGGL(spmv_kernel, dim3((unsigned)std::max<int64_t>(1, (N + 3) / 4)), dim3(kBlock), 0, st, N,
-                       D.rowptr.ptr<int64_t>(), D.cols.ptr<int32_t>(), sys->val.ptr<double>(), x, y, sub);
+                       D.rowptr.ptr<int64_t>(), D.cols.ptr<int32_t>(), sys->val.ptr<double>(), x, y, sub, flag);
   };
-  auto dots = [&](int k, const double* Vb, const double* x, double* out, int acc) {
-    hipLaunchKernelGGL(multidot_kernel, dim3(kDotBlocks), dim3(kBlock), 0, st, N, k, Vb, x, part);
-    hipLaunchKernelGGL(reduce_dots_kernel, dim3((unsigned)((k + 3) / 4)), dim3(kBlock), 0, st, k, part, out, acc);
+  auto dots = [&](int k, const double* Vb, const double* x, double* out, int acc, const int* flag) {
+    hipLaunchKernelGGL(multidot_kernel, dim3(kDotBlocks), dim3(kBlock), 0, st, N, k, Vb, x, part, flag);
+    hipLaunchKernelGGL(reduce_dots_kernel, dim3((unsigned)((k + 3) / 4)), dim3(kBlock), 0, st, k, part, out, acc,
+                       flag);
   };
-  auto norm_into = [&](const double* x, double* v) {   // v = x / |x|, nrm[1] = |x|
-    dots(1, x, x, nrm, 0);
-    hipLaunchKernelGGL(normalise_kernel, grid1(N), dim3(kBlock), 0, st, N, x, nrm, v);
+  auto norm_into = [&](const double* x, double* v, const int* flag) {   // v = x / |x|, nrm[1] = |x|
+    dots(1, x, x, nrm, 0, flag);
+    hipLaunchKernelGGL(normalise_kernel, grid1(N), dim3(kBlock), 0, st, N, x, nrm, v, flag);
   };
-  auto read = [&](const double* d, double* hst, int k) {
-    PDD_HIP(hipMemcpyAsync(hst, d, k * sizeof(double), hipMemcpyDeviceToHost, st));
+  auto read = [&](const void* d, void* hst, size_t bytes) {
+    PDD_HIP(hipMemcpyAsync(hst, d, bytes, hipMemcpyDeviceToHost, st));
     PDD_HIP(hipStreamSynchronize(st));
   };
   double bn2 = 0.0;
-  dots(1, b, b, nrm, 0);
-  read(nrm, &bn2, 1);
+  dots(1, b, b, nrm, 0, nullptr);
+  read(nrm, &bn2, sizeof(double));
   const double bnorm = std::sqrt(bn2);
   PDD_HIP(hipMemsetAsync(u, 0, N * sizeof(double), st));
   pdd_solve_info res{0, 0, 0.0};
@@ -457,68 +527,67 @@ pdd_status gmres_impl(pdd_system sys, pdd_ras ras, const double* rhs, double* u,
     if (info) *info = res;
     return PDD_OK;
   }
-  std::vector<double> Hh((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), col(m + 2);
+  // Iterations are enqueued in batches; the host reads the device state once
+  // per batch (kernels of iterations past the stop return at once).
+  constexpr int kBatch = 8;
+  std::vector<double> Hh((size_t)(m + 1) * m), gh(m + 1);
   int it = 0;
   double rel = 1.0;
+  GmState hs{};
   while (it < max_iter) {
-    spmv(u, w, b);                       // w = b - C u
+    spmv(u, w, b, nullptr);              // w = b - C u
     double nb[2];
-    norm_into(w, V);
-    read(nrm, nb, 2);
+    norm_into(w, V, nullptr);
+    read(nrm, nb, 2 * sizeof(double));
     rel = nb[1] / bnorm;
     if (rel <= rtol) break;
-    std::fill(Hh.begin(), Hh.end(), 0.0);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = nb[1];
-    int k = 0;
-    for (int j = 0; j < m; ++j) {
-      precond(V + (int64_t)j * N, z);
-      spmv(z, w, nullptr);
-      // classical Gram-Schmidt, twice: h = V^T w, w -= V h; c = V^T w,
-      // w -= V c, h += c (the second reduction re-sums the same partials)
-      dots(j + 1, V, w, h, 0);
-      hipLaunchKernelGGL(update_kernel, grid1(N), dim3(kBlock), 0, st, N, j + 1, V, h, w);
-      dots(j + 1, V, w, yv, 0);
-      hipLaunchKernelGGL(update_kernel, grid1(N), dim3(kBlock), 0, st, N, j + 1, V, yv, w);
-      hipLaunchKernelGGL(reduce_dots_kernel, dim3((unsigned)((j + 1 + 3) / 4)), dim3(kBlock), 0, st, j + 1,
-                         part, h, 1);
-      norm_into(w, V + (int64_t)(j + 1) * N);
-      read(h, col.data(), j + 1);
-      read(nrm, nb, 2);
-      for (int i = 0; i <= j; ++i) Hh[(size_t)i * m + j] = col[i];
-      Hh[(size_t)(j + 1) * m + j] = nb[1];
-      for (int i = 0; i < j; ++i) {
-        const double a = Hh[(size_t)i * m + j], c = Hh[(size_t)(i + 1) * m + j];
-        Hh[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
-        Hh[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+    std::vector<double> g0(m + 1, 0.0);
+    g0[0] = nb[1];
+    GmState init{0, 0, it, 0, rel};
+    PDD_HIP(hipMemcpyAsync(g, g0.data(), (m + 1) * sizeof(double), hipMemcpyHostToDevice, st));
+    PDD_HIP(hipMemcpyAsync(gs, &init, sizeof(GmState), hipMemcpyHostToDevice, st));
+    for (int j0 = 0; j0 < m; j0 += kBatch) {
+      const int j1 = std::min(m, j0 + kBatch);
+      for (int j = j0; j < j1; ++j) {
+        precond(V + (int64_t)j * N, z, stop);
+        spmv(z, w, nullptr, stop);
+        // classical Gram-Schmidt, twice: h = V^T w, w -= V h; c = V^T w,
+        // w -= V c, h += c (the second reduction re-sums the same partials)
+        dots(j + 1, V, w, h, 0, stop);
+        hipLaunchKernelGGL(update_kernel, grid1(N), dim3(kBlock), 0, st, N, j + 1, V, h, w, stop);
+        dots(j + 1, V, w, yv, 0, stop);
+        hipLaunchKernelGGL(update_kernel, grid1(N), dim3(kBlock), 0, st, N, j + 1, V, yv, w, stop);
+        hipLaunchKernelGGL(reduce_dots_kernel, dim3((unsigned)((j + 1 + 3) / 4)), dim3(kBlock), 0, st, j + 1,
+                           part, h, 1, stop);
+        norm_into(w, V + (int64_t)(j + 1) * N, stop);
+        hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(64), 0, st, j, m, h, nrm, Hm, cs, sn, g, gs, bnorm,
+                           rtol, max_iter);
       }
-      const double a = Hh[(size_t)j * m + j], c = Hh[(size_t)(j + 1) * m + j];
-      const double den = std::hypot(a, c);
-      cs[j] = a / den;
-      sn[j] = c / den;
-      Hh[(size_t)j * m + j] = den;
-      Hh[(size_t)(j + 1) * m + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      ++it;
-      k = j + 1;
-      rel = std::fabs(g[j + 1]) / bnorm;
-      if (rel <= rtol || it >= max_iter) break;
+      PDD_HIP(hipGetLastError());
+      read(gs, &hs, sizeof(GmState));
+      if (hs.stop) break;
     }
-    // y = H_k^-1 g_k, u += M^-1 (V_k y)
-    std::vector<double> y(k);
+    const int k = hs.k;
+    it = hs.iters;
+    rel = hs.rel;
+    // y = H_k^-1 g_k (upper triangular after the rotations), u += M^-1 (V_k y)
+    read(Hm, Hh.data(), (size_t)(m + 1) * m * sizeof(double));
+    read(g, gh.data(), (m + 1) * sizeof(double));
+    std::vector<double> y(std::max(k, 1));
     for (int i = k - 1; i >= 0; --i) {
-      double t = g[i];
+      double t = gh[i];
       for (int q = i + 1; q < k; ++q) t -= Hh[(size_t)i * m + q] * y[q];
       y[i] = t / Hh[(size_t)i * m + i];
     }
-    PDD_HIP(hipMemcpyAsync(yv, y.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(combine_basis_kernel, grid1(N), dim3(kBlock), 0, st, N, k, V, yv, s);
-    precond(s, z);
-    hipLaunchKernelGGL(axpy_kernel, grid1(N), dim3(kBlock), 0, st, N, z, u);
-    PDD_HIP(hipGetLastError());
+    if (k > 0) {
+      PDD_HIP(hipMemcpyAsync(yv, y.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(combine_basis_kernel, grid1(N), dim3(kBlock), 0, st, N, k, V, yv, s);
+      precond(s, z, nullptr);
+      hipLaunchKernelGGL(axpy_kernel, grid1(N), dim3(kBlock), 0, st, N, z, u);
+      PDD_HIP(hipGetLastError());
+    }
     PDD_HIP(hipStreamSynchronize(st));   // y lives on the host stack
-    if (rel <= rtol) break;
+    if (rel <= rtol || k == 0) break;
   }
   PDD_HIP(hipStreamSynchronize(st));
   res.iterations = it;
@@ -559,7 +628,7 @@ pdd_status pdd_ras_apply(pdd_ras ras, const double* x, double* y, void* stream) 
   if (!ras || !x || !y) return fail(PDD_EINVAL, "pdd_ras_apply: null argument");
   try {
     const Ras prec{ras, (hipStream_t)stream};
-    prec.apply(x, y);
+    prec.apply(x, y, nullptr);
     PDD_HIP(hipGetLastError());
     return PDD_OK;
   } catch (const HipError& e) {

@@ -41,6 +41,15 @@ def _case(name):
         return workloads.config1(paths=128)
     if name == "small_variable":
         return workloads.small_variable(paths=128)
+    if name == "disk_hole":                     # unit disk minus a hole, 14 x 14 lattice
+        dom = workloads.disk(0.0, 0.0, 1.0, holes=[(0.3, 0.0, 0.2)])
+        cen = workloads.lattice_centres(14, 14, -1.05, 1.05, -1.05, 1.05)
+        keep = (np.hypot(cen[:, 0], cen[:, 1]) - 0.12 < 1.0) & \
+               (np.hypot(cen[:, 0] - 0.3, cen[:, 1]) + 0.12 > 0.2)
+        g = workloads.degenerate("no_floating")["problem"]["g"]
+        return {"problem": workloads.laplace_problem(dom, g),
+                "cover": workloads._cover(cen[keep], np.full(keep.sum(), 0.12), 16, 16, 4),
+                "mc": workloads.mc_opts(64, 1e-3, seed=5)}
     cfg = workloads.config1(paths=128)
     cfg["cover"] = dict(cfg["cover"])
     cfg["cover"]["rule"] = RULE_AVERAGED
@@ -59,7 +68,8 @@ def _system(pdd, cfg):
 
 
 @pytest.mark.parametrize("name,parts", [("config1", (2, 2)), ("small_variable", (2, 2)),
-                                        ("config1_averaged", (2, 2)), ("config1", (4, 1))])
+                                        ("config1_averaged", (2, 2)), ("config1", (4, 1)),
+                                        ("disk_hole", (3, 2))])
 def test_ras_matches_oracle(name, parts):
     pdd, torch = _gpu()
     cfg = _case(name)
