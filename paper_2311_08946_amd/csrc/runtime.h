@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -162,10 +163,24 @@ int factor_chunk(const DeviceCover& D, const BucketData& bk, const NodeSamples& 
 
 }  // namespace pdd
 
+namespace pdd {
+// BiCGStab scratch (device vectors and partial sums, two pinned convergence
+// records), kept by the cover between solves so that a solve on a new system
+// allocates nothing; concurrent solves each take their own.
+struct SolveScratch {
+  int device = -1;
+  DevBuf work;
+  double* pinned = nullptr;
+  ~SolveScratch() { if (pinned) (void)hipHostFree(pinned); }
+};
+}  // namespace pdd
+
 struct pdd_cover_s {
   pdd::HostCover H;
   pdd::DeviceCover D;
   pdd::DeviceCover DP;   // rule AVERAGED: the pair rows (H.pairs)
+  std::mutex solve_mu;
+  std::vector<std::unique_ptr<pdd::SolveScratch>> solve_free;
 };
 
 struct pdd_system_s {
@@ -179,9 +194,5 @@ struct pdd_system_s {
   int32_t plan = 0;
   pdd_system_stats stats{};
   std::vector<double> host_problem_bytes;
-  // solver scratch kept between pdd_solve_G calls on this system (calls on
-  // one system are serialised by the caller's stream order)
-  pdd::DevBuf solve_work, val_t;       // vectors and partial sums; C^T values
-  double* solve_pinned = nullptr;      // 2 convergence records (pinned host memory)
-  ~pdd_system_s() { if (solve_pinned) (void)hipHostFree(solve_pinned); }
+  pdd::DevBuf val_t;                   // C^T values (formed on the first transposed solve)
 };

@@ -351,8 +351,36 @@ pdd_status solve_impl(pdd_system sys, const double* rhs, double* u, int32_t tran
   c.nblocks = (int)((N + kRowsPerBlock - 1) / kRowsPerBlock);
   c.vblocks = (int)((N + kThreads - 1) / kThreads);
   const size_t wbytes = sizeof(double) * (5 * N + 5 * (int64_t)c.nblocks + 2 * (int64_t)c.vblocks + 2 * S_COUNT);
-  if (sys->solve_work.bytes() < wbytes) sys->solve_work.alloc(wbytes);
-  c.r = sys->solve_work.ptr<double>();
+  // scratch from the cover's pool, returned when this call ends
+  int dev = 0;
+  PDD_HIP(hipGetDevice(&dev));
+  std::unique_ptr<SolveScratch> scr;
+  {
+    std::lock_guard<std::mutex> lk(sys->cover->solve_mu);
+    auto& pool = sys->cover->solve_free;
+    for (size_t k = 0; k < pool.size(); ++k)
+      if (pool[k]->device == dev) {
+        scr = std::move(pool[k]);
+        pool.erase(pool.begin() + k);
+        break;
+      }
+  }
+  if (!scr) {
+    scr = std::make_unique<SolveScratch>();
+    scr->device = dev;
+  }
+  struct Return {
+    pdd_cover cv;
+    hipStream_t q;
+    std::unique_ptr<SolveScratch>& s;
+    ~Return() {
+      (void)hipStreamSynchronize(q);     // nothing in flight uses it (also on an error path)
+      std::lock_guard<std::mutex> lk(cv->solve_mu);
+      cv->solve_free.push_back(std::move(s));
+    }
+  } give_back{sys->cover, st, scr};
+  if (scr->work.bytes() < wbytes) scr->work.alloc(wbytes);
+  c.r = scr->work.ptr<double>();
   c.r0 = c.r + N;
   c.p = c.r0 + N;
   c.v = c.p + N;
@@ -377,9 +405,8 @@ pdd_status solve_impl(pdd_system sys, const double* rhs, double* u, int32_t tran
         if (e) (void)hipEventDestroy(e);
     }
   } pin;
-  if (!sys->solve_pinned)
-    PDD_HIP(hipHostMalloc(&sys->solve_pinned, 2 * S_COUNT * sizeof(double), hipHostMallocDefault));
-  pin.p = sys->solve_pinned;
+  if (!scr->pinned) PDD_HIP(hipHostMalloc(&scr->pinned, 2 * S_COUNT * sizeof(double), hipHostMallocDefault));
+  pin.p = scr->pinned;
   for (int k = 0; k < 2 * S_COUNT; ++k) pin.p[k] = 0.0;
   for (auto& e : pin.ev) PDD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   int enq = 0, slot = 0;
