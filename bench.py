@@ -242,6 +242,28 @@ def ras_measurement(cfg, parts, reps):
     out["apply_roofline"] = {"bound": "hbm", "kernel": "gather_x_kernel + block_gemv_kernel + combine_kernel",
                              "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                              "frac": achieved / PEAK_HBM_GBS, "bytes_per_apply": nbytes}
+    # the same with the inverses kept in FP32
+    del R
+    R32, ms_b32 = timed(lambda: pdd.Ras(sysm, *parts, fp32_inverses=True))
+    sysm.solve_gmres(R32, rtol=1e-12)
+    (u, info), ms = timed(lambda: sysm.solve_gmres(R32, rtol=1e-12))
+    out["fp32_inverses"] = {"setup_ms": ms_b32, "gmres_ras": {"ms": ms, "iterations": int(info.iterations),
+                                                               "converged": bool(info.converged)}}
+    for _ in range(3):
+        R32.apply(x)
+    e0.record()
+    for _ in range(reps):
+        R32.apply(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms32 = e0.elapsed_time(e1) / reps
+    nbytes32 = float(np.sum(4.0 * sizes * sizes + 16.0 * sizes))
+    a32 = nbytes32 / (ms32 * 1e-3) / 1e9
+    out["fp32_inverses"]["apply_ms"] = ms32
+    out["fp32_inverses"]["apply_roofline"] = {
+        "bound": "hbm", "kernel": "gather_x_kernel + block_gemv_f32_kernel + combine_kernel",
+        "achieved": a32, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": a32 / PEAK_HBM_GBS,
+        "bytes_per_apply": nbytes32}
     return out
 
 

@@ -341,14 +341,17 @@ pdd_status pdd_solve_G(pdd_system sys, const double* rhs, double* u, int32_t tra
  * every knot adjacent to one of its knots in the graph of C taken symmetric
  * (one layer).  (D_p)_ii = 1 / (number of omega_q holding knot i), eq. 43.
  * Each C_p (at most 4096 knots) is factorised on the device by LU with partial
- * pivoting and kept as its explicit inverse; HBM use is about 16 (#omega_p)^2
- * bytes per part.  The preconditioner refers to `sys`, which must outlive it.
+ * pivoting and kept as its explicit inverse; HBM use is about 8 (#omega_p)^2
+ * bytes per part (4 with fp32_inverses), 16 during the set-up.  The preconditioner refers to `sys`, which must outlive it.
  * Errors: PDD_EINVAL (bad counts, a part above 4096 knots), PDD_EBREAKDOWN
  * (a singular C_p), PDD_ENOMEM, PDD_EDEVICE.  Synchronises `stream`.
  */
 typedef struct pdd_ras_s* pdd_ras;
 typedef struct pdd_ras_opts {
   int32_t parts_x, parts_y;   /* >= 1 each                                        */
+  int32_t fp32_inverses;      /* 1: keep C_p^-1 rounded to FP32 (half the bytes per
+                                 apply; products still accumulate in FP64)        */
+  int32_t reserved;
 } pdd_ras_opts;
 
 pdd_status pdd_ras_build(pdd_system sys, const pdd_ras_opts* opts, void* stream, pdd_ras* out);

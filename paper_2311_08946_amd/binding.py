@@ -101,7 +101,8 @@ class SolveOpts(C.Structure):
 
 
 class RasOpts(C.Structure):
-    _fields_ = [("parts_x", C.c_int32), ("parts_y", C.c_int32)]
+    _fields_ = [("parts_x", C.c_int32), ("parts_y", C.c_int32), ("fp32_inverses", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class GmresOpts(C.Structure):
@@ -401,11 +402,12 @@ class System:
 class Ras:
     """One-level RAS preconditioner of an assembled system (eqs. 42-44)."""
 
-    def __init__(self, system, parts_x, parts_y, stream=None):
+    def __init__(self, system, parts_x, parts_y, fp32_inverses=False, stream=None):
         L = lib()
         self.system = system          # the preconditioner refers to the system
         h = C.c_void_p()
-        code = L.pdd_ras_build(system.handle, C.byref(RasOpts(int(parts_x), int(parts_y))),
+        opts = RasOpts(int(parts_x), int(parts_y), int(bool(fp32_inverses)), 0)
+        code = L.pdd_ras_build(system.handle, C.byref(opts),
                                _stream_ptr(stream), C.byref(h))
         self._h = h if h.value else None
         _check(code, "ras_build: ")

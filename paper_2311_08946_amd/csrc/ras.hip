@@ -30,13 +30,16 @@
 struct pdd_ras_s {
   pdd_system sys = nullptr;
   int32_t P = 0, max_npad = 0;
+  bool f32 = false;                     // inverses kept in FP32 (inv32), else in mat
   int64_t total = 0;                    // sum of #omega_p
   std::vector<int64_t> off;             // [P+1] offsets into knots
   std::vector<int32_t> knots;           // omega_p, sorted, concatenated
   std::vector<int32_t> npad;            // padded order of each C_p
   std::vector<int64_t> aoff;            // offset (doubles) of each [C_p | C_p^-1]
   std::vector<int64_t> poff;            // offset of each part's padded vector slots
+  std::vector<int64_t> ioff;            // offset (floats) of each part's FP32 inverse
   pdd::DevBuf d_off, d_knots, d_npad, d_aoff, d_poff, d_moff, d_mslot, mat, piv, status, work, t, xg;
+  pdd::DevBuf d_ioff, inv32;
 };
 
 namespace pdd {
@@ -135,6 +138,46 @@ __global__ void __launch_bounds__(kBlock) block_gemv_kernel(
   if (c < h) {
     const double2 u0 = X[c], v0 = xv[c];
     a0 += u0.x * v0.x + u0.y * v0.y;
+  }
+  const double acc = wave_sum(a0 + a1);
+  if (lane == 0) t[o + r] = acc;
+}
+
+// FP32 copy of every C_p^-1 (rows and columns padded to npad, zeros beyond #omega_p).
+__global__ void to_f32_kernel(const int32_t* __restrict__ npad, const int64_t* __restrict__ aoff,
+                              const int64_t* __restrict__ ioff, const double* __restrict__ mat,
+                              float* __restrict__ inv32) {
+  const int p = blockIdx.y;
+  const int np = npad[p];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)np * np) return;
+  const int r = (int)(e / np), c = (int)(e - (int64_t)r * np);
+  inv32[ioff[p] + e] = (float)mat[aoff[p] + (int64_t)r * 2 * np + np + c];
+}
+
+// t_p = C_p^-1 xg_p from the FP32 inverses: 16-byte loads of four entries,
+// products and sums in FP64.
+__global__ void __launch_bounds__(kBlock) block_gemv_f32_kernel(
+    const int64_t* __restrict__ off, const int32_t* __restrict__ npad, const int64_t* __restrict__ ioff,
+    const int64_t* __restrict__ poff, const float* __restrict__ inv32, const double* __restrict__ xg,
+    double* __restrict__ t, const int* __restrict__ stop) {
+  if (stop && *stop) return;
+  const int p = blockIdx.y;
+  const int r = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
+  const int lane = threadIdx.x % kWave;
+  const int64_t o = off[p];
+  const int n = (int)(off[p + 1] - o);
+  if (r >= n) return;
+  const int np = npad[p];
+  const float4* X = reinterpret_cast<const float4*>(inv32 + ioff[p] + (int64_t)r * np);
+  const double2* xv = reinterpret_cast<const double2*>(xg + poff[p]);
+  const int q = np / 4;
+  double a0 = 0.0, a1 = 0.0;
+  for (int c = lane; c < q; c += kWave) {
+    const float4 u = X[c];
+    const double2 v0 = xv[2 * c], v1 = xv[2 * c + 1];
+    a0 += (double)u.x * v0.x + (double)u.y * v0.y;
+    a1 += (double)u.z * v1.x + (double)u.w * v1.y;
   }
   const double acc = wave_sum(a0 + a1);
   if (lane == 0) t[o + r] = acc;
@@ -324,9 +367,14 @@ struct Ras {
                        dim3(kBlock), 0, st, r->d_off.ptr<int64_t>(), r->d_knots.ptr<int32_t>(),
                        r->d_npad.ptr<int32_t>(), r->d_poff.ptr<int64_t>(), x, r->xg.ptr<double>(), stop);
     const dim3 g((unsigned)((r->max_npad + 3) / 4), (unsigned)r->P);
-    hipLaunchKernelGGL(block_gemv_kernel, g, dim3(kBlock), 0, st, r->d_off.ptr<int64_t>(),
-                       r->d_npad.ptr<int32_t>(), r->d_aoff.ptr<int64_t>(), r->d_poff.ptr<int64_t>(),
-                       r->mat.ptr<double>(), r->xg.ptr<double>(), r->t.ptr<double>(), stop);
+    if (r->f32)
+      hipLaunchKernelGGL(block_gemv_f32_kernel, g, dim3(kBlock), 0, st, r->d_off.ptr<int64_t>(),
+                         r->d_npad.ptr<int32_t>(), r->d_ioff.ptr<int64_t>(), r->d_poff.ptr<int64_t>(),
+                         r->inv32.ptr<float>(), r->xg.ptr<double>(), r->t.ptr<double>(), stop);
+    else
+      hipLaunchKernelGGL(block_gemv_kernel, g, dim3(kBlock), 0, st, r->d_off.ptr<int64_t>(),
+                         r->d_npad.ptr<int32_t>(), r->d_aoff.ptr<int64_t>(), r->d_poff.ptr<int64_t>(),
+                         r->mat.ptr<double>(), r->xg.ptr<double>(), r->t.ptr<double>(), stop);
     const int64_t N = r->sys->cover->H.N();
     hipLaunchKernelGGL(combine_kernel, grid1(N), dim3(kBlock), 0, st, N, r->d_moff.ptr<int64_t>(),
                        r->d_mslot.ptr<int64_t>(), r->t.ptr<double>(), y, stop);
@@ -459,6 +507,24 @@ pdd_status ras_build_impl(pdd_system sys, const pdd_ras_opts* opts, hipStream_t 
   PDD_HIP(hipMemcpy(stat.data(), R->status.ptr<void>(), P * sizeof(int32_t), hipMemcpyDeviceToHost));
   for (int p = 0; p < P; ++p)
     if (stat[p]) return fail(PDD_EBREAKDOWN, "pdd_ras_build: zero pivot in block " + std::to_string(p));
+  if (opts && opts->fp32_inverses) {
+    R->f32 = true;
+    R->ioff.assign(P, 0);
+    int64_t nf = 0;
+    for (int p = 0; p < P; ++p) {
+      R->ioff[p] = nf;
+      nf += (int64_t)R->npad[p] * R->npad[p];
+    }
+    R->d_ioff.upload(R->ioff);
+    R->inv32.alloc(nf * sizeof(float));
+    const int64_t most = (int64_t)R->max_npad * R->max_npad;
+    hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)((most + kBlock - 1) / kBlock), (unsigned)P), dim3(kBlock),
+                       0, st, R->d_npad.ptr<int32_t>(), R->d_aoff.ptr<int64_t>(), R->d_ioff.ptr<int64_t>(),
+                       R->mat.ptr<double>(), R->inv32.ptr<float>());
+    PDD_HIP(hipGetLastError());
+    PDD_HIP(hipStreamSynchronize(st));
+    R->mat.release();                    // the FP64 factors are no longer needed
+  }
   *out = R.release();
   return PDD_OK;
 }

@@ -120,3 +120,30 @@ def test_ras_on_the_benchmark_lattice():
     assert info_r.iterations < info_n.iterations
     _say(f"[gpu] 32x32: GMRES+RAS {info_r.iterations}, GMRES {info_n.iterations}, "
          f"BiCGStab {info_b.iterations} iterations")
+
+
+@pytest.mark.parametrize("name", ["config1", "small_variable"])
+def test_fp32_inverses(name):
+    # Inverses rounded to FP32: each entry moves by at most 2^-24 of itself, so
+    # |dy_i| <= 2^-24 sum_p D_ii sum_c |(C_p^-1)_rc| |x_c| (bound doubled below);
+    # GMRES with the preconditioner on the right still meets the FP64 tolerance.
+    pdd, torch = _gpu()
+    cfg = _case(name)
+    _say(f"[gpu] ras fp32 inverses {name}")
+    cv, sysm, C, b, ref_cover = _system(pdd, cfg)
+    R32 = pdd.Ras(sysm, 2, 2, fp32_inverses=True)
+    omegas, D = ras.subdomains(ref_cover, 2, 2)
+    x = np.random.default_rng(4).standard_normal(cv.N)
+    y = R32.apply(torch.tensor(x, device="cuda")).cpu().numpy()
+    y_ref = ras.RAS(C, ref_cover, 2, 2).apply(x)
+    bound = np.zeros(cv.N)
+    for w, d in zip(omegas, D):
+        Xp = np.linalg.inv(C[w][:, w].toarray())
+        bound[w] += d * (np.abs(Xp) @ np.abs(x[w]))
+    bound = 2.0 ** -23 * bound + 1e-12 * np.max(np.abs(y_ref))
+    assert np.all(np.abs(y - y_ref) <= bound), float(np.max(np.abs(y - y_ref) / bound))
+    u, info = sysm.solve_gmres(R32, rtol=1e-11)
+    assert info.converged
+    u_ref = spla.spsolve(sp.csc_matrix(C), b)
+    assert np.max(np.abs(u.cpu().numpy() - u_ref)) <= 1e-9 * np.max(np.abs(u_ref))
+    _say(f"[gpu] {name} fp32 RAS: {info.iterations} GMRES iterations")
