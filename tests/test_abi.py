@@ -137,3 +137,16 @@ def test_null_handles_are_rejected_without_device_work():
     assert L.pdd_solve_gmres(None, None, None, None, None, None, None) == pdd.PDD_EINVAL
     assert b"null" in L.pdd_last_error()
     L.pdd_destroy_ras(None)
+
+
+def test_header_is_plain_c():
+    # the boundary is a C ABI: the public header compiles as C99 on its own
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    hdr = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "pdd.h")
+    r = subprocess.run([gcc, "-fsyntax-only", "-std=c99", "-Wall", "-Wextra", "-Werror", "-x", "c", hdr],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
