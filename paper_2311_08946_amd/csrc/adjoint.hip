@@ -417,5 +417,9 @@ extern "C" pdd_status pdd_assemble_G_backward(pdd_system sys, const double* u, c
     return backward_impl(sys, u, lambda, g, (hipStream_t)stream);
   } catch (const HipError& e) {
     return fail(PDD_EDEVICE, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(PDD_ENOMEM, "pdd_assemble_G_backward: out of host memory");
+  } catch (const std::exception& e) {
+    return fail(PDD_EDEVICE, std::string("pdd_assemble_G_backward: ") + e.what());
   }
 }

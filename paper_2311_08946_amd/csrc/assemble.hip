@@ -769,6 +769,10 @@ pdd_status pdd_eval_field(const pdd_problem* problem, int32_t which, const doubl
     return PDD_OK;
   } catch (const HipError& e) {
     return fail(PDD_EDEVICE, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(PDD_ENOMEM, "pdd_eval_field: out of host memory");
+  } catch (const std::exception& e) {
+    return fail(PDD_EDEVICE, std::string("pdd_eval_field: ") + e.what());
   }
 }
 
@@ -787,6 +791,10 @@ pdd_status pdd_system_copy(pdd_system sys, double* val, double* b, double* se, d
     return PDD_OK;
   } catch (const HipError& e) {
     return fail(PDD_EDEVICE, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(PDD_ENOMEM, "pdd_system_copy: out of host memory");
+  } catch (const std::exception& e) {
+    return fail(PDD_EDEVICE, std::string("pdd_system_copy: ") + e.what());
   }
 }
 

@@ -679,6 +679,8 @@ pdd_status pdd_ras_build(pdd_system sys, const pdd_ras_opts* opts, void* stream,
     return fail(e.code == hipErrorOutOfMemory ? PDD_ENOMEM : PDD_EDEVICE, e.what());
   } catch (const std::bad_alloc&) {
     return fail(PDD_ENOMEM, "pdd_ras_build: out of host memory");
+  } catch (const std::exception& e) {
+    return fail(PDD_EDEVICE, std::string("pdd_ras_build: ") + e.what());
   }
 }
 
@@ -710,6 +712,10 @@ pdd_status pdd_solve_gmres(pdd_system sys, pdd_ras ras, const double* rhs, doubl
     return gmres_impl(sys, ras, rhs, u, opts, (hipStream_t)stream, info);
   } catch (const HipError& e) {
     return fail(e.code == hipErrorOutOfMemory ? PDD_ENOMEM : PDD_EDEVICE, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(PDD_ENOMEM, "pdd_solve_gmres: out of host memory");
+  } catch (const std::exception& e) {
+    return fail(PDD_EDEVICE, std::string("pdd_solve_gmres: ") + e.what());
   }
 }
 

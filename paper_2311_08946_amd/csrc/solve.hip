@@ -472,5 +472,7 @@ extern "C" pdd_status pdd_solve_G(pdd_system sys, const double* rhs, double* u, 
     return fail(e.code == hipErrorOutOfMemory ? PDD_ENOMEM : PDD_EDEVICE, e.what());
   } catch (const std::bad_alloc&) {
     return fail(PDD_ENOMEM, "pdd_solve_G: out of host memory");
+  } catch (const std::exception& e) {
+    return fail(PDD_EDEVICE, std::string("pdd_solve_G: ") + e.what());
   }
 }
