@@ -343,6 +343,8 @@ pdd_status pdd_solve_G(pdd_system sys, const double* rhs, double* u, int32_t tra
  * Each C_p (at most 4096 knots) is factorised on the device by LU with partial
  * pivoting and kept as its explicit inverse; HBM use is about 8 (#omega_p)^2
  * bytes per part (4 with fp32_inverses), 16 during the set-up.  The preconditioner refers to `sys`, which must outlive it.
+ * With parts_x = parts_y = 1 (N <= 4096) the preconditioner is C^-1 itself and
+ * pdd_solve_gmres becomes a direct solve (one iteration).
  * Errors: PDD_EINVAL (bad counts, a part above 4096 knots), PDD_EBREAKDOWN
  * (a singular C_p), PDD_ENOMEM, PDD_EDEVICE.  Synchronises `stream`.
  */

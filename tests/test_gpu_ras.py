@@ -147,3 +147,22 @@ def test_fp32_inverses(name):
     u_ref = spla.spsolve(sp.csc_matrix(C), b)
     assert np.max(np.abs(u.cpu().numpy() - u_ref)) <= 1e-9 * np.max(np.abs(u_ref))
     _say(f"[gpu] {name} fp32 RAS: {info.iterations} GMRES iterations")
+
+
+def test_one_part_is_a_direct_solve():
+    # one part: omega = every knot, M^-1 = C^-1 (eq. 44 with R = I); GMRES stops
+    # after one iteration at the direct solution
+    pdd, torch = _gpu()
+    cfg = _case("config1")
+    _say("[gpu] ras one part")
+    cv, sysm, C, b, ref_cover = _system(pdd, cfg)
+    R = pdd.Ras(sysm, 1, 1)
+    assert len(R.parts()) == 1 and np.array_equal(R.parts()[0], np.arange(cv.N))
+    x = np.random.default_rng(6).standard_normal(cv.N)
+    y = R.apply(torch.tensor(x, device="cuda")).cpu().numpy()
+    ref = spla.spsolve(sp.csc_matrix(C), x)
+    assert np.max(np.abs(y - ref)) <= 1e-11 * np.max(np.abs(ref))
+    u, info = sysm.solve_gmres(R, rtol=1e-12)
+    assert info.converged and info.iterations == 1
+    u_ref = spla.spsolve(sp.csc_matrix(C), b)
+    assert np.max(np.abs(u.cpu().numpy() - u_ref)) <= 1e-11 * np.max(np.abs(u_ref))
