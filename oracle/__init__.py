@@ -22,9 +22,12 @@ follows:
 * ``philox``      the Philox4x32-10 counter-based generator (Salmon et al.,
                   SC'11), uniform and Box-Muller maps
 * ``montecarlo``  Euler-Maruyama Feynman-Kac estimates for perimeter rows
-                  (Section 2.3 eqs. 25-30, Appendix eq. 53)
-* ``assemble``    the sparse system C u = r (eqs. 28-30), its direct solve and
-                  diagnostics
+                  (Section 2.3 eqs. 25-30, Appendix eq. 53), plain or with the
+                  boundary-shifted scheme of the paper's ref. [15]
+* ``assemble``    the sparse system C u = r (eqs. 28-30; averaged rows,
+                  eqs. 38-39), its direct solve and diagnostics
+* ``ras``         the one-level restricted additive Schwarz preconditioner and
+                  right-preconditioned restarted GMRES (Section 4, eqs. 42-45)
 * ``adjoint``     exact derivative of the discrete map with respect to the
                   node samples of the coefficients (not in the paper)
 
