@@ -14,8 +14,9 @@
 // reduction launch; workgroup 0 records them.  Every kernel returns at once
 // after the stopping test has fired, which lets the host enqueue several
 // iterations per status read; a one-workgroup status kernel per batch adds
-// the last partials for the host.  Sparse rows are handled by 16-lane groups
-// (64 rows per 1024-thread workgroup, so that few partial sums are re-added).
+// the last partials for the host.  Sparse rows are handled by 8-lane groups
+// (128 rows per 1024-thread workgroup: the grid fits the GPU in one round, and
+// few partial sums are re-added).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,8 +30,9 @@ namespace pdd {
 namespace {
 
 constexpr int kThreads = 256;        // vector kernels: one entry per thread
-constexpr int kSpThreads = 1024;     // sparse kernels: 16 lanes per row
-constexpr int kRowsPerBlock = kSpThreads / 16;
+constexpr int kSpThreads = 1024;     // sparse kernels: kLanesPerRow lanes per row
+constexpr int kLanesPerRow = 8;
+constexpr int kRowsPerBlock = kSpThreads / kLanesPerRow;
 constexpr int kItersPerSync = 8;
 
 enum {
@@ -86,28 +88,28 @@ __device__ __forceinline__ double sum_parts(const double* __restrict__ part, int
   return block_sum<NW>(a, s);
 }
 
-// Row of a 16-lane group: sum_k val[k] (y - beta z)[cols[k]], reduced inside the group.
-__device__ __forceinline__ double row16(const SolveCtx& c, int64_t row, const double* y,
+// Row of a kLanesPerRow-lane group: sum_k val[k] (y - beta z)[cols[k]], reduced inside the group.
+__device__ __forceinline__ double row_sum(const SolveCtx& c, int64_t row, const double* y,
                                         const double* z, double beta, int sub) {
   double acc = 0.0;
   if (row < c.N) {
     const int64_t lo = c.rowptr[row], hi = c.rowptr[row + 1];
-    for (int64_t k = lo + sub; k < hi; k += 16) {
+    for (int64_t k = lo + sub; k < hi; k += kLanesPerRow) {
       const int32_t j = c.cols[k];
       acc += c.val[k] * (z ? y[j] - beta * z[j] : y[j]);
     }
   }
-  for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+  for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
   return acc;
 }
 
 __global__ __launch_bounds__(kSpThreads) void init_kernel(SolveCtx c, const double* __restrict__ b,
                                                           int use_guess) {
   __shared__ double s16[16];
-  const int sub = threadIdx.x & 15;
-  const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 4);
+  const int sub = threadIdx.x & (kLanesPerRow - 1);
+  const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x / kLanesPerRow);
   // r = b - C x (x = 0 unless a guess is given)
-  const double ax = use_guess ? row16(c, row, c.x, nullptr, 0.0, sub) : 0.0;
+  const double ax = use_guess ? row_sum(c, row, c.x, nullptr, 0.0, sub) : 0.0;
   double pbb = 0.0, prr = 0.0;
   if (sub == 0 && row < c.N) {
     const double ri = b[row] - ax;
@@ -202,9 +204,9 @@ __global__ __launch_bounds__(kThreads) void update_p_kernel(SolveCtx c, int firs
 __global__ __launch_bounds__(kSpThreads) void spmv_v_kernel(SolveCtx c) {
   __shared__ double s16[16];
   if (c.sc[S_DONE] != 0.0) return;
-  const int sub = threadIdx.x & 15;
-  const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 4);
-  const double vi = row16(c, row, c.p, nullptr, 0.0, sub);
+  const int sub = threadIdx.x & (kLanesPerRow - 1);
+  const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x / kLanesPerRow);
+  const double vi = row_sum(c, row, c.p, nullptr, 0.0, sub);
   double prv = 0.0;
   if (sub == 0 && row < c.N) {
     c.v[row] = vi;
@@ -224,9 +226,9 @@ __global__ __launch_bounds__(kSpThreads) void spmv_t_kernel(SolveCtx c) {
     c.sc[S_RV] = rv;
     c.sc[S_ALPHA] = alpha;
   }
-  const int sub = threadIdx.x & 15;
-  const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 4);
-  const double ti = row16(c, row, c.r, c.v, alpha, sub);
+  const int sub = threadIdx.x & (kLanesPerRow - 1);
+  const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x / kLanesPerRow);
+  const double ti = row_sum(c, row, c.r, c.v, alpha, sub);
   double pts = 0.0, ptt = 0.0;
   if (sub == 0 && row < c.N) {
     c.t[row] = ti;
