@@ -105,3 +105,29 @@ def test_adjoint_dot_product_identity(small_var):
     lhs = float(Jv @ lam[knots])
     rhs = -sum(float(grads[m][k] @ v[k]) for k in v)
     assert abs(lhs - rhs) < 1e-6 * (abs(lhs) + abs(rhs))
+
+
+def test_config2_floating_rows_annihilate_the_manufactured_solution():
+    # Variable a, b, clipped c and the derived source (eqs. 1-3) on the 32x32
+    # benchmark cover, n = 1024: collocation is spectrally accurate for the
+    # smooth manufactured u, so the floating rows (eqs. 31-35) applied to u at
+    # the knots leave rounding-level residuals.  This ties derived_source (the
+    # operator of eq. 1 applied analytically) to the collocation operator of
+    # eq. 40 built from node samples; a dropped term, a wrong factor or sign
+    # leaves residuals of order r^2 |f error| >> 1e-10.  First, last and a
+    # seeded sample of the 900 floating circles.
+    cfg = workloads.config2()
+    prob = cfg["problem"]
+    cv = geometry.build_cover(prob["domain"], cfg["cover"])
+    fl = np.nonzero(cv.floating)[0]
+    rng = np.random.default_rng(22)
+    sel = np.concatenate([fl[:2], fl[-2:], rng.choice(fl[2:-2], 8, replace=False)])
+    u = prob["u_exact"]
+    worst = 0.0
+    for m in sel:
+        knots, Crows, rv = spectral.floating_rows(prob, cv, m)
+        st = cv.stencil(m)
+        u_st = fields.value(u, cv.knot_xy[st, 0], cv.knot_xy[st, 1])
+        for t, i in enumerate(knots):
+            worst = max(worst, abs(fields.value(u, *cv.knot_xy[i]) + Crows[t] @ u_st - rv[t]))
+    assert worst <= 1e-10, worst
