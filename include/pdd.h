@@ -328,6 +328,26 @@ typedef struct pdd_solve_info {
 pdd_status pdd_solve_G(pdd_system sys, const double* rhs, double* u, int32_t transpose,
                        const pdd_solve_opts* opts, void* stream, pdd_solve_info* info);
 
+/*
+ * pdd_solve_G_noalloc -- for callers that cannot allocate device or pinned
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The same BiCGStab as pdd_solve_G, with the same kernels
+ * and results, but its work area is a fixed 48 MiB array of static device
+ * memory, one per GPU, which the library holds until the process ends; the
+ * call allocates nothing and creates no events.
+ *   Limit: 5 N + 5 ceil(N/128) + 2 ceil(N/256) + 28 <= 6291456 doubles, i.e.
+ *   N up to about 1.24 million knots; larger systems get PDD_EINVAL.
+ *   transpose = 1 needs C^T to exist: one pdd_solve_G call with transpose = 1
+ *   on the system forms it (else PDD_EINVAL).
+ *   Every call on one GPU uses the same work area and leaves its contents
+ *   there; calls that overlap on one GPU (other threads or streams) race and
+ *   must be serialised by the caller.
+ * Synchronises `stream` once per 8 iterations.
+ * Errors: PDD_EINVAL, PDD_ENOCONV (u holds the last iterate), PDD_EDEVICE.
+ */
+pdd_status pdd_solve_G_noalloc(pdd_system sys, const double* rhs, double* u, int32_t transpose,
+                               const pdd_solve_opts* opts, void* stream, pdd_solve_info* info);
+
 /* ------------------------------------------------------- RAS + GMRES */
 
 /*

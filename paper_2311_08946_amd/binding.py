@@ -26,7 +26,7 @@ EXPORTED = [
     "pdd_cover_pattern", "pdd_cover_nodes", "pdd_destroy_cover", "pdd_assemble_G",
     "pdd_system_copy", "pdd_system_get_stats", "pdd_solve_G", "pdd_assemble_G_backward",
     "pdd_destroy_system", "pdd_ras_build", "pdd_ras_get_parts", "pdd_ras_apply", "pdd_destroy_ras",
-    "pdd_solve_gmres",
+    "pdd_solve_gmres", "pdd_solve_G_noalloc",
 ]
 
 
@@ -139,6 +139,7 @@ def lib():
     L.pdd_system_copy.argtypes = [vp, vp, vp, vp, vp, vp]
     L.pdd_system_get_stats.argtypes = [vp, C.POINTER(SystemStats)]
     L.pdd_solve_G.argtypes = [vp, vp, vp, i32, C.POINTER(SolveOpts), vp, C.POINTER(SolveInfo)]
+    L.pdd_solve_G_noalloc.argtypes = [vp, vp, vp, i32, C.POINTER(SolveOpts), vp, C.POINTER(SolveInfo)]
     L.pdd_assemble_G_backward.argtypes = [vp, vp, vp] + [vp] * 7 + [vp]
     L.pdd_destroy_system.argtypes = [vp]
     L.pdd_destroy_system.restype = None

@@ -21,6 +21,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "runtime.h"
@@ -324,35 +326,108 @@ void ensure_transpose(pdd_cover cover) {
   D.have_transpose = true;
 }
 
+namespace {
+
+// Doubles of the BiCGStab work area for N unknowns: r, r0, p, v, t, the
+// partial sums of the sparse and vector kernels, the scalars and the host's
+// record.
+int64_t work_doubles(int64_t N) {
+  const int64_t nb = (N + kRowsPerBlock - 1) / kRowsPerBlock, vb = (N + kThreads - 1) / kThreads;
+  return 5 * N + 5 * nb + 2 * vb + 2 * S_COUNT;
+}
+
+// Points the context at C (or C^T, whose pattern and values must exist) and
+// carves the work area w (work_doubles(N) doubles) into its vectors.
+void bind(SolveCtx& c, pdd_system sys, bool transpose, double* u, double* w) {
+  const DeviceCover& D = sys->cover->D;
+  const int64_t N = sys->cover->H.N();
+  c.rowptr = transpose ? D.rt_rowptr.ptr<int64_t>() : D.rowptr.ptr<int64_t>();
+  c.cols = transpose ? D.rt_cols.ptr<int32_t>() : D.cols.ptr<int32_t>();
+  c.val = transpose ? sys->val_t.ptr<double>() : sys->val.ptr<double>();
+  c.N = N;
+  c.x = u;
+  c.nblocks = (int)((N + kRowsPerBlock - 1) / kRowsPerBlock);
+  c.vblocks = (int)((N + kThreads - 1) / kThreads);
+  c.r = w;
+  c.r0 = c.r + N;
+  c.p = c.r0 + N;
+  c.v = c.p + N;
+  c.t = c.v + N;
+  c.part_i = c.t + N;
+  c.part_v = c.part_i + 2 * (int64_t)c.nblocks;
+  c.part_t = c.part_v + c.nblocks;
+  c.part_x = c.part_t + 2 * (int64_t)c.nblocks;
+  c.sc = c.part_x + 2 * (int64_t)c.vblocks;
+  c.status = c.sc + S_COUNT;
+}
+
+// Enqueues the next batch of at most kItersPerSync iterations after `enq`
+// enqueued ones, then the status kernel that writes the host's record to
+// c.status; returns the new count.
+int enqueue_batch(const SolveCtx& c, hipStream_t st, int enq, int max_iter, double rtol) {
+  const dim3 rb(c.nblocks), vb(c.vblocks);
+  const int batch = std::min(kItersPerSync, max_iter - enq);
+  for (int k = 0; k < batch; ++k) {
+    hipLaunchKernelGGL(update_p_kernel, vb, dim3(kThreads), 0, st, c, enq + k == 0 ? 1 : 0, rtol);
+    hipLaunchKernelGGL(spmv_v_kernel, rb, dim3(kSpThreads), 0, st, c);
+    hipLaunchKernelGGL(spmv_t_kernel, rb, dim3(kSpThreads), 0, st, c);
+    hipLaunchKernelGGL(update_xr_kernel, vb, dim3(kThreads), 0, st, c);
+  }
+  enq += batch;
+  hipLaunchKernelGGL(status_kernel, dim3(1), dim3(kThreads), 0, st, c, enq == 0 ? 1 : 0, rtol);
+  PDD_HIP(hipGetLastError());
+  return enq;
+}
+
+struct SolveParams {
+  double rtol;
+  int max_iter;
+  bool guess;
+};
+
+SolveParams params(const pdd_solve_opts* opts) {
+  return {(opts && opts->rtol > 0.0) ? opts->rtol : 1e-12,
+          (opts && opts->max_iter > 0) ? opts->max_iter : 2000, opts && opts->use_guess};
+}
+
+// Reports a final record through info and the return status.
+pdd_status finish(const double* host, pdd_solve_info* info, const char* who) {
+  const bool ok = host[S_DONE] != 0.0 && host[S_FAIL] == 0.0;
+  const double bnorm = std::sqrt(host[S_BB]);
+  const double rel = bnorm > 0.0 ? std::sqrt(host[S_RR]) / bnorm : 0.0;
+  const int it = (int)host[S_ITER];
+  if (info) {
+    info->iterations = it;
+    info->converged = ok ? 1 : 0;
+    info->rel_residual = rel;
+  }
+  if (!ok)
+    return fail(PDD_ENOCONV, std::string(who) + ": BiCGStab stopped at relative residual " +
+                                 std::to_string(rel) + " after " + std::to_string(it) + " iterations");
+  return PDD_OK;
+}
+
+}  // namespace
+
 pdd_status solve_impl(pdd_system sys, const double* rhs, double* u, int32_t transpose,
                       const pdd_solve_opts* opts, hipStream_t st, pdd_solve_info* info) {
   const HostCover& H = sys->cover->H;
   DeviceCover& D = sys->cover->D;
   const int64_t N = H.N(), nnz = H.rowptr.back();
-  const double rtol = (opts && opts->rtol > 0.0) ? opts->rtol : 1e-12;
-  const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 2000;
-  const bool guess = opts && opts->use_guess;
-  SolveCtx c{};
-  c.rowptr = D.rowptr.ptr<int64_t>();
-  c.cols = D.cols.ptr<int32_t>();
-  c.val = sys->val.ptr<double>();
-  c.N = N;
-  c.x = u;
+  const SolveParams P = params(opts);
   if (transpose) {
+    std::lock_guard<std::mutex> lk(sys->cover->solve_mu);
     ensure_transpose(sys->cover);
     if (sys->val_t.bytes() == 0) {     // C^T values, formed once per system
       sys->val_t.alloc(nnz * sizeof(double));
       hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st,
-                         D.rt_perm.ptr<int64_t>(), c.val, sys->val_t.ptr<double>(), nnz);
+                         D.rt_perm.ptr<int64_t>(), sys->val.ptr<double>(), sys->val_t.ptr<double>(), nnz);
+      PDD_HIP(hipGetLastError());
+      PDD_HIP(hipStreamSynchronize(st));   // complete before another stream's solve can see it
     }
-    c.rowptr = D.rt_rowptr.ptr<int64_t>();
-    c.cols = D.rt_cols.ptr<int32_t>();
-    c.val = sys->val_t.ptr<double>();
   }
   const double* b = rhs ? rhs : sys->b.ptr<double>();
-  c.nblocks = (int)((N + kRowsPerBlock - 1) / kRowsPerBlock);
-  c.vblocks = (int)((N + kThreads - 1) / kThreads);
-  const size_t wbytes = sizeof(double) * (5 * N + 5 * (int64_t)c.nblocks + 2 * (int64_t)c.vblocks + 2 * S_COUNT);
+  const size_t wbytes = sizeof(double) * (size_t)work_doubles(N);
   // scratch from the cover's pool, returned when this call ends
   int dev = 0;
   PDD_HIP(hipGetDevice(&dev));
@@ -382,19 +457,9 @@ pdd_status solve_impl(pdd_system sys, const double* rhs, double* u, int32_t tran
     }
   } give_back{sys->cover, st, scr};
   if (scr->work.bytes() < wbytes) scr->work.alloc(wbytes);
-  c.r = scr->work.ptr<double>();
-  c.r0 = c.r + N;
-  c.p = c.r0 + N;
-  c.v = c.p + N;
-  c.t = c.v + N;
-  c.part_i = c.t + N;
-  c.part_v = c.part_i + 2 * (int64_t)c.nblocks;
-  c.part_t = c.part_v + c.nblocks;
-  c.part_x = c.part_t + 2 * (int64_t)c.nblocks;
-  c.sc = c.part_x + 2 * (int64_t)c.vblocks;
-  c.status = c.sc + S_COUNT;
-  const dim3 rb(c.nblocks), vb(c.vblocks);
-  hipLaunchKernelGGL(init_kernel, rb, dim3(kSpThreads), 0, st, c, b, guess ? 1 : 0);
+  SolveCtx c{};
+  bind(c, sys, transpose != 0, u, scr->work.ptr<double>());
+  hipLaunchKernelGGL(init_kernel, dim3(c.nblocks), dim3(kSpThreads), 0, st, c, b, P.guess ? 1 : 0);
   // Batches of kItersPerSync iterations; the convergence record of batch k is
   // copied to pinned host memory and read while batch k + 1 already runs (the
   // iteration kernels return at once after convergence, so a batch enqueued
@@ -412,24 +477,15 @@ pdd_status solve_impl(pdd_system sys, const double* rhs, double* u, int32_t tran
   for (int k = 0; k < 2 * S_COUNT; ++k) pin.p[k] = 0.0;
   for (auto& e : pin.ev) PDD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   int enq = 0, slot = 0;
-  auto enqueue_batch = [&](int sl) {
-    const int batch = std::min(kItersPerSync, max_iter - enq);
-    for (int k = 0; k < batch; ++k) {
-      hipLaunchKernelGGL(update_p_kernel, vb, dim3(kThreads), 0, st, c, enq + k == 0 ? 1 : 0, rtol);
-      hipLaunchKernelGGL(spmv_v_kernel, rb, dim3(kSpThreads), 0, st, c);
-      hipLaunchKernelGGL(spmv_t_kernel, rb, dim3(kSpThreads), 0, st, c);
-      hipLaunchKernelGGL(update_xr_kernel, vb, dim3(kThreads), 0, st, c);
-    }
-    enq += batch;
-    hipLaunchKernelGGL(status_kernel, dim3(1), dim3(kThreads), 0, st, c, enq == 0 ? 1 : 0, rtol);
-    PDD_HIP(hipGetLastError());
+  auto batch_to = [&](int sl) {
+    enq = enqueue_batch(c, st, enq, P.max_iter, P.rtol);
     PDD_HIP(hipMemcpyAsync(pin.p + sl * S_COUNT, c.status, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
     PDD_HIP(hipEventRecord(pin.ev[sl], st));
   };
-  enqueue_batch(slot);
+  batch_to(slot);
   for (;;) {
-    const bool more = enq < max_iter;
-    if (more) enqueue_batch(slot ^ 1);
+    const bool more = enq < P.max_iter;
+    if (more) batch_to(slot ^ 1);
     PDD_HIP(hipEventSynchronize(pin.ev[slot]));
     const double* h = pin.p + slot * S_COUNT;
     if (h[S_DONE] != 0.0 || !more) break;
@@ -439,31 +495,87 @@ pdd_status solve_impl(pdd_system sys, const double* rhs, double* u, int32_t tran
   // both slots now hold completed records; the more recent one (more
   // iterations counted; a batch that ran after convergence copies the same
   // record again) is the final state
+  const double* a = pin.p;
+  const double* b2 = pin.p + S_COUNT;
+  return finish((b2[S_ITER] > a[S_ITER]) ? b2 : a, info, "pdd_solve_G");
+}
+
+// ------------------------------------------------- allocation-free variant
+
+// Work area of pdd_solve_G_noalloc: 6 Mi doubles (48 MiB) of static device
+// memory per GPU, held until the process ends.  In host code the name is only
+// a stand-in: the device address comes from hipGetSymbolAddress.
+constexpr int64_t kScratchDoubles = int64_t(6) << 20;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's copy of `scratch` (looked up once per
+// device, with that device current).
+double* scratch_ptr(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    PDD_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+pdd_status solve_noalloc_impl(pdd_system sys, const double* rhs, double* u, int32_t transpose,
+                              const pdd_solve_opts* opts, hipStream_t st, pdd_solve_info* info) {
+  const int64_t N = sys->cover->H.N();
+  const SolveParams P = params(opts);
+  if (work_doubles(N) > kScratchDoubles)
+    return fail(PDD_EINVAL, "pdd_solve_G_noalloc: " + std::to_string(N) +
+                                " unknowns need " + std::to_string(work_doubles(N)) +
+                                " doubles of work area, more than its " + std::to_string(kScratchDoubles));
+  if (transpose) {
+    std::lock_guard<std::mutex> lk(sys->cover->solve_mu);
+    if (!sys->cover->D.have_transpose || sys->val_t.bytes() == 0)
+      return fail(PDD_EINVAL, "pdd_solve_G_noalloc: C^T has not been formed for this system "
+                              "(one pdd_solve_G call with transpose = 1 forms it)");
+  }
+  int dev = 0;
+  PDD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PDD_EINVAL, "pdd_solve_G_noalloc: device index out of range");
+  SolveCtx c{};
+  bind(c, sys, transpose != 0, u, scratch_ptr(dev));
+  const double* b = rhs ? rhs : sys->b.ptr<double>();
+  hipLaunchKernelGGL(init_kernel, dim3(c.nblocks), dim3(kSpThreads), 0, st, c, b, P.guess ? 1 : 0);
+  // one stream synchronisation per batch of kItersPerSync iterations
   double host[S_COUNT];
-  {
-    const double* a = pin.p;
-    const double* b2 = pin.p + S_COUNT;
-    const double* h = (b2[S_ITER] > a[S_ITER]) ? b2 : a;
-    for (int k = 0; k < S_COUNT; ++k) host[k] = h[k];
+  int enq = 0;
+  for (;;) {
+    enq = enqueue_batch(c, st, enq, P.max_iter, P.rtol);
+    PDD_HIP(hipMemcpyAsync(host, c.status, sizeof host, hipMemcpyDeviceToHost, st));
+    PDD_HIP(hipStreamSynchronize(st));
+    if (host[S_DONE] != 0.0 || enq >= P.max_iter) break;
   }
-  const bool ok = host[S_DONE] != 0.0 && host[S_FAIL] == 0.0;
-  const double bnorm = std::sqrt(host[S_BB]);
-  const double rel = bnorm > 0.0 ? std::sqrt(host[S_RR]) / bnorm : 0.0;
-  const int it = (int)host[S_ITER];
-  if (info) {
-    info->iterations = it;
-    info->converged = ok ? 1 : 0;
-    info->rel_residual = rel;
-  }
-  if (!ok)
-    return fail(PDD_ENOCONV, "pdd_solve_G: BiCGStab stopped at relative residual " +
-                                 std::to_string(rel) + " after " + std::to_string(it) + " iterations");
-  return PDD_OK;
+  return finish(host, info, "pdd_solve_G_noalloc");
 }
 
 }  // namespace pdd
 
 using namespace pdd;
+
+extern "C" pdd_status pdd_solve_G_noalloc(pdd_system sys, const double* rhs, double* u, int32_t transpose,
+                                          const pdd_solve_opts* opts, void* stream, pdd_solve_info* info) {
+  if (!sys || !u) return fail(PDD_EINVAL, "pdd_solve_G_noalloc: null argument");
+  try {
+    return solve_noalloc_impl(sys, rhs, u, transpose, opts, (hipStream_t)stream, info);
+  } catch (const HipError& e) {
+    return fail(PDD_EDEVICE, e.what());
+  } catch (const std::exception& e) {
+    return fail(PDD_EDEVICE, std::string("pdd_solve_G_noalloc: ") + e.what());
+  }
+}
 
 extern "C" pdd_status pdd_solve_G(pdd_system sys, const double* rhs, double* u, int32_t transpose,
                                   const pdd_solve_opts* opts, void* stream, pdd_solve_info* info) {
