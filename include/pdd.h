@@ -31,6 +31,10 @@
  *     breakdown, path-step cap, solver convergence) synchronise that stream
  *     before returning.
  *   - All floating point is IEEE binary64.
+ *   - Calls that take the same cover or system handle must not overlap, with
+ *     two exceptions: pdd_solve_G calls on one system may run concurrently
+ *     (each takes its own work area; forming C^T is locked), and read-only
+ *     queries (info, knots, pattern, nodes, stats) may run at any time.
  */
 #ifndef PDD_H
 #define PDD_H
@@ -172,20 +176,23 @@ typedef struct pdd_cover_info {
   int32_t max_n, max_M, max_arc, n_buckets;
 } pdd_cover_info;
 
+/* Sizes of the cover (Section 2.1, eqs. 9-12: knots, stencils, rows by kind;
+ * Section 3.3: collocation sizes).  Host only. */
 pdd_status pdd_cover_get_info(pdd_cover cover, pdd_cover_info* out);
 
-/* Knot table (host outputs, any may be NULL): xy [2N]; row_class [N]
+/* Knot table of eqs. 9-12 and the row choice of Section 3.2 (host outputs,
+ * any may be NULL): xy [2N]; row_class [N]
  * (0 spectral, 1 Monte Carlo, 2 boundary); assigned [N] (circle of the row,
  * -1 for boundary rows); owner [N] (circle the knot lies on). */
 pdd_status pdd_cover_knots(pdd_cover cover, double* xy, int32_t* row_class,
                            int32_t* assigned, int32_t* owner);
 
-/* CSR pattern of C (host outputs): rowptr [N+1], cols [nnz]; columns of each
+/* CSR pattern of C (eqs. 28-30; host outputs): rowptr [N+1], cols [nnz]; columns of each
  * row increase; row i holds i and, unless boundary, the stencil of its circle
  * (of every containing circle under rule AVERAGED). */
 pdd_status pdd_cover_pattern(pdd_cover cover, int64_t* rowptr, int32_t* cols);
 
-/* Collocation nodes of the floating circles (host outputs): xy [2*sum_n],
+/* Collocation nodes of the floating circles (Section 3.3, eq. 40; host outputs): xy [2*sum_n],
  * circle-major, node q = (j-1) Ntheta + l at radius r cos(j pi/(2 Nr + 1)) and
  * angle 2 pi l / Ntheta; node_off [n_float+1]; float_ids [n_float]. */
 pdd_status pdd_cover_nodes(pdd_cover cover, double* xy, int64_t* node_off, int32_t* float_ids);
@@ -205,7 +212,7 @@ typedef struct pdd_mc_opts {
   int64_t paths;           /* Ntilde paths per perimeter knot                         */
   double h;                /* Euler step                                              */
   uint64_t seed;           /* Philox key = (seed mod 2^32, seed div 2^32)              */
-  int32_t n_batches;       /* batches for standard errors (2..64)                      */
+  int32_t n_batches;       /* batches for standard errors (2..63)                      */
   int32_t step_cap;        /* maximum steps of one path (> 0)                          */
   const double* h_per_circle;  /* host [n_circles] or NULL: per-circle step            */
   int32_t scheme;          /* PDD_MC_EULER or PDD_MC_SHIFTED (see pdd_assemble_G)      */
@@ -280,11 +287,18 @@ pdd_status pdd_assemble_G(pdd_cover cover, const pdd_problem* problem,
                           const pdd_samples* samples, const pdd_mc_opts* mc,
                           const pdd_assemble_opts* opts, void* stream, pdd_system* out);
 
-/* Copies the system to caller buffers (device or host, any may be NULL):
- * val [nnz], b [N], se [nnz] (standard error of each entry, 0 if exact),
- * se_b [N].  Stream-ordered on `stream`. */
+/* Copies the assembled C and r of eqs. 28-30 to caller buffers (device or
+ * host, any may be NULL): val [nnz] on the pdd_cover_pattern layout, b [N]
+ * (= r), se [nnz] (Monte Carlo standard error of each entry, 0 if exact),
+ * se_b [N].  Enqueued on `stream`, which is synchronised before returning. */
 pdd_status pdd_system_copy(pdd_system sys, double* val, double* b, double* se, double* se_b,
                            void* stream);
+
+/* C in CSR form with r (eqs. 28-30), all outputs device or host, any may be
+ * NULL: rowptr [N+1], cols [nnz] (increasing per row), val [nnz], b [N],
+ * se [nnz].  Enqueued on `stream`, which is synchronised before returning. */
+pdd_status pdd_system_csr(pdd_system sys, int64_t* rowptr, int32_t* cols, double* val, double* b, double* se,
+                          void* stream);
 
 typedef struct pdd_system_stats {
   int64_t path_steps;      /* Euler steps over all paths                              */
@@ -307,10 +321,14 @@ pdd_status pdd_system_get_stats(pdd_system sys, pdd_system_stats* out);
 
 /* ------------------------------------------------------------------ solve */
 
+enum { PDD_SOLVE_BICGSTAB = 0, PDD_SOLVE_DIRECT_SMALL = 1 };
+
 typedef struct pdd_solve_opts {
   double rtol;             /* relative residual |r - C u| / |r|, default 1e-12         */
   int32_t max_iter;        /* default 2000                                             */
-  int32_t use_guess;       /* start from the contents of u                             */
+  int32_t use_guess;       /* start from the contents of u (BiCGStab)                  */
+  int32_t method;          /* PDD_SOLVE_BICGSTAB (default) or PDD_SOLVE_DIRECT_SMALL    */
+  int32_t reserved;
 } pdd_solve_opts;
 
 typedef struct pdd_solve_info {
@@ -320,10 +338,25 @@ typedef struct pdd_solve_info {
 } pdd_solve_info;
 
 /*
- * pdd_solve_G -- BiCGStab on C (transpose = 0) or C^T (transpose = 1).
+ * pdd_solve_G -- solves the assembled system C u = r (eqs. 28-30; Section 4
+ * and Remark 2 on solving it) or the transposed system C^T lambda = g of the
+ * adjoint (transpose = 1).
  *   rhs  device [N] or NULL for r;  u  device [N] output (and guess).
- * Synchronises `stream` once per iteration to test convergence.
- * Errors: PDD_EINVAL, PDD_ENOCONV (u holds the last iterate), PDD_EDEVICE.
+ *   PDD_SOLVE_BICGSTAB: BiCGStab from u = 0 (or the guess) until
+ *     |rhs - C u| <= rtol |rhs|, at most max_iter iterations.  The stream is
+ *     synchronised once per 8 iterations (the convergence record of batch k
+ *     is read while batch k + 1 runs).
+ *   PDD_SOLVE_DIRECT_SMALL: for N <= 4096, [C | rhs] is formed densely on the
+ *     device and solved by LU with partial pivoting (the batched LU of the
+ *     collocation matrices, one matrix); info->iterations = 1 and
+ *     rel_residual = |rhs - C u| / |rhs|.  Allocates about 8 N^2 bytes for
+ *     the call; synchronises the stream once.
+ * The first transposed solve on a system forms C^T (its pattern per cover,
+ * its values per system) and synchronises the stream.  Solves on one system
+ * may run concurrently on different streams.
+ * Errors: PDD_EINVAL (unknown method, N > 4096 for the direct method),
+ * PDD_ENOCONV (BiCGStab; u holds the last iterate), PDD_EBREAKDOWN (zero
+ * pivot in the direct method), PDD_ENOMEM, PDD_EDEVICE.
  */
 pdd_status pdd_solve_G(pdd_system sys, const double* rhs, double* u, int32_t transpose,
                        const pdd_solve_opts* opts, void* stream, pdd_solve_info* info);
@@ -407,21 +440,29 @@ pdd_status pdd_solve_gmres(pdd_system sys, pdd_ras ras, const double* rhs, doubl
                            const pdd_gmres_opts* opts, void* stream, pdd_solve_info* info);
 
 /*
- * pdd_assemble_G_backward -- gradients of a loss L(u) with respect to the node
- * samples of pdd_samples, given u (C u = r) and lambda = C^-T dL/du (device
- * [N] each).  For floating circle m with mu = A_II^-T E_m^T lambda_Km:
+ * pdd_assemble_G_backward -- gradients of a loss L(u) with respect to the
+ * node samples of pdd_samples and to r, given u (C u = r) and
+ * lambda = C^-T dL/du (device [N] each).  It differentiates the floating
+ * rows: the local problems of eqs. 32 and 35 discretised by eq. 40 and
+ * solved as in eq. 41, evaluated at the knots (eq. 33).  For floating circle
+ * m with mu = A_II^-T E_m^T lambda_Km (E_m the evaluation at its knots):
  *   dL/d coef_q = -mu_q (row q of the operator multiplying coef) . [w_I; w_B]
  *   dL/d f_q    = -mu_q
  * with w_B = H u_Xi and w_I the local interior solution.  Outputs are device
- * arrays [sum_n] in the node layout; NULL skips one.  Monte Carlo and boundary
- * rows do not depend on node samples (dL/dr = lambda).  Needs the system to
- * have been assembled with keep_factors (stored factors, or a chunked
- * recomputation when they exceeded hbm_budget_bytes).
+ * arrays [sum_n] in the node layout; NULL skips one.  g_r (device [N], NULL
+ * skips it) receives dL/dr = lambda: the Monte Carlo and boundary rows
+ * (eqs. 29-30) do not depend on node samples, and their expectations enter
+ * only through r.  Needs the system to have been assembled with
+ * keep_factors (stored factors, or a chunked recomputation when they
+ * exceeded hbm_budget_bytes).  Stream-ordered; synchronises the stream only
+ * to release chunk buffers (recomputation, rule AVERAGED).
+ * Errors: PDD_EINVAL (no factors kept, a bucket whose adjoint layout exceeds
+ * the 160 KiB of LDS), PDD_ENOMEM, PDD_EDEVICE.
  */
 pdd_status pdd_assemble_G_backward(pdd_system sys, const double* u, const double* lambda,
                                    double* g_axx, double* g_axy, double* g_ayy,
                                    double* g_bx, double* g_by, double* g_c, double* g_f,
-                                   void* stream);
+                                   double* g_r, void* stream);
 
 void pdd_destroy_system(pdd_system sys);
 

@@ -26,7 +26,7 @@ EXPORTED = [
     "pdd_cover_pattern", "pdd_cover_nodes", "pdd_destroy_cover", "pdd_assemble_G",
     "pdd_system_copy", "pdd_system_get_stats", "pdd_solve_G", "pdd_assemble_G_backward",
     "pdd_destroy_system", "pdd_ras_build", "pdd_ras_get_parts", "pdd_ras_apply", "pdd_destroy_ras",
-    "pdd_solve_gmres", "pdd_solve_G_noalloc",
+    "pdd_solve_gmres", "pdd_solve_G_noalloc", "pdd_system_csr",
 ]
 
 
@@ -97,7 +97,11 @@ class SystemStats(C.Structure):
 
 
 class SolveOpts(C.Structure):
-    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("use_guess", C.c_int32)]
+    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("use_guess", C.c_int32),
+                ("method", C.c_int32), ("reserved", C.c_int32)]
+
+
+SOLVE_METHODS = {"bicgstab": 0, "direct": 1}
 
 
 class RasOpts(C.Structure):
@@ -137,10 +141,11 @@ def lib():
     L.pdd_assemble_G.argtypes = [vp, C.POINTER(Problem), C.POINTER(Samples), C.POINTER(McOpts),
                                  C.POINTER(AssembleOpts), vp, C.POINTER(vp)]
     L.pdd_system_copy.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.pdd_system_csr.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.pdd_system_get_stats.argtypes = [vp, C.POINTER(SystemStats)]
     L.pdd_solve_G.argtypes = [vp, vp, vp, i32, C.POINTER(SolveOpts), vp, C.POINTER(SolveInfo)]
     L.pdd_solve_G_noalloc.argtypes = [vp, vp, vp, i32, C.POINTER(SolveOpts), vp, C.POINTER(SolveInfo)]
-    L.pdd_assemble_G_backward.argtypes = [vp, vp, vp] + [vp] * 7 + [vp]
+    L.pdd_assemble_G_backward.argtypes = [vp, vp, vp] + [vp] * 8 + [vp]
     L.pdd_destroy_system.argtypes = [vp]
     L.pdd_destroy_system.restype = None
     L.pdd_ras_build.argtypes = [vp, C.POINTER(RasOpts), vp, C.POINTER(vp)]
@@ -361,11 +366,25 @@ class System:
                                      _stream_ptr(stream)))
         return val, b, se, se_b
 
-    def solve(self, rhs=None, transpose=False, rtol=1e-12, max_iter=2000, guess=None, stream=None):
+    def csr(self, stream=None):
+        """(rowptr, cols, val, b, se) of C and r on the device (pdd_system_csr)."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        rowptr = torch.empty(self.cover.N + 1, dtype=torch.int64, device=dev)
+        cols = torch.empty(self.cover.nnz, dtype=torch.int32, device=dev)
+        val = torch.empty(self.cover.nnz, dtype=torch.float64, device=dev)
+        se = torch.empty_like(val)
+        b = torch.empty(self.cover.N, dtype=torch.float64, device=dev)
+        _check(lib().pdd_system_csr(self._h, _tptr(rowptr), _tptr(cols), _tptr(val), _tptr(b), _tptr(se),
+                                    _stream_ptr(stream)))
+        return rowptr, cols, val, b, se
+
+    def solve(self, rhs=None, transpose=False, rtol=1e-12, max_iter=2000, guess=None, stream=None,
+              method="bicgstab"):
         import torch
         dev = torch.device("cuda", torch.cuda.current_device())
         u = guess.clone() if guess is not None else torch.zeros(self.cover.N, dtype=torch.float64, device=dev)
-        so = SolveOpts(rtol, max_iter, 1 if guess is not None else 0)
+        so = SolveOpts(rtol, max_iter, 1 if guess is not None else 0, SOLVE_METHODS[method], 0)
         info = SolveInfo()
         _check(lib().pdd_solve_G(self._h, _tptr(rhs), _tptr(u), int(bool(transpose)), C.byref(so),
                                  _stream_ptr(stream), C.byref(info)), "solve_G: ")
@@ -383,13 +402,17 @@ class System:
         return u, info
 
     def backward(self, u, lam, stream=None, names=("axx", "axy", "ayy", "bx", "by", "c", "f")):
+        """Gradients w.r.t. the node samples named in ``names``; "r" in names also
+        returns dL/dr (= lam)."""
         import torch
         n = int(self.cover.info.sum_n)
         dev = u.device
         out = {k: torch.empty(n, dtype=torch.float64, device=dev) if k in names else None
                for k in ("axx", "axy", "ayy", "bx", "by", "c", "f")}
+        out["r"] = torch.empty(self.cover.N, dtype=torch.float64, device=dev) if "r" in names else None
         _check(lib().pdd_assemble_G_backward(self._h, _tptr(u), _tptr(lam),
-                                             *[_tptr(out[k]) for k in ("axx", "axy", "ayy", "bx", "by", "c", "f")],
+                                             *[_tptr(out[k]) for k in ("axx", "axy", "ayy", "bx", "by", "c", "f",
+                                                                       "r")],
                                              _stream_ptr(stream)), "assemble_G_backward: ")
         return {k: v for k, v in out.items() if v is not None}
 

@@ -328,8 +328,11 @@ __global__ void gather_pairs_kernel(int64_t np, const int32_t* __restrict__ pair
 }
 
 pdd_status backward_impl(pdd_system sys, const double* u, const double* lambda, double* const g[7],
-                         hipStream_t st) {
+                         double* g_r, hipStream_t st) {
   const bool avg = sys->cover->H.pairs != nullptr;
+  // r enters C u = r linearly: dL/dr = lambda for every row
+  if (g_r && sys->cover->H.N() > 0)
+    PDD_HIP(hipMemcpyAsync(g_r, lambda, sizeof(double) * (size_t)sys->cover->H.N(), hipMemcpyDefault, st));
   const DeviceCover& D = avg ? sys->cover->DP : sys->cover->D;
   if (sys->factors.empty() && !sys->recompute && !sys->cover->H.float_ids.empty())
     return fail(PDD_EINVAL, "pdd_assemble_G_backward: assemble with keep_factors to differentiate");
@@ -410,11 +413,11 @@ using namespace pdd;
 extern "C" pdd_status pdd_assemble_G_backward(pdd_system sys, const double* u, const double* lambda,
                                               double* g_axx, double* g_axy, double* g_ayy,
                                               double* g_bx, double* g_by, double* g_c, double* g_f,
-                                              void* stream) {
+                                              double* g_r, void* stream) {
   if (!sys || !u || !lambda) return fail(PDD_EINVAL, "pdd_assemble_G_backward: null argument");
   try {
     double* const g[7] = {g_axx, g_axy, g_ayy, g_bx, g_by, g_c, g_f};
-    return backward_impl(sys, u, lambda, g, (hipStream_t)stream);
+    return backward_impl(sys, u, lambda, g, g_r, (hipStream_t)stream);
   } catch (const HipError& e) {
     return fail(PDD_EDEVICE, e.what());
   } catch (const std::bad_alloc&) {

@@ -798,6 +798,27 @@ pdd_status pdd_system_copy(pdd_system sys, double* val, double* b, double* se, d
   }
 }
 
+pdd_status pdd_system_csr(pdd_system sys, int64_t* rowptr, int32_t* cols, double* val, double* b, double* se,
+                          void* stream) {
+  if (!sys) return fail(PDD_EINVAL, "pdd_system_csr: null system");
+  try {
+    hipStream_t st = (hipStream_t)stream;
+    const DeviceCover& D = sys->cover->D;
+    const int64_t N = sys->cover->H.N(), nnz = sys->cover->H.rowptr.back();
+    if (rowptr) PDD_HIP(hipMemcpyAsync(rowptr, D.rowptr.ptr<void>(), (N + 1) * 8, hipMemcpyDefault, st));
+    if (cols && nnz) PDD_HIP(hipMemcpyAsync(cols, D.cols.ptr<void>(), nnz * 4, hipMemcpyDefault, st));
+    if (val && nnz) PDD_HIP(hipMemcpyAsync(val, sys->val.ptr<void>(), nnz * 8, hipMemcpyDefault, st));
+    if (se && nnz) PDD_HIP(hipMemcpyAsync(se, sys->se.ptr<void>(), nnz * 8, hipMemcpyDefault, st));
+    if (b && N) PDD_HIP(hipMemcpyAsync(b, sys->b.ptr<void>(), N * 8, hipMemcpyDefault, st));
+    PDD_HIP(hipStreamSynchronize(st));
+    return PDD_OK;
+  } catch (const HipError& e) {
+    return fail(PDD_EDEVICE, e.what());
+  } catch (const std::exception& e) {
+    return fail(PDD_EDEVICE, std::string("pdd_system_csr: ") + e.what());
+  }
+}
+
 pdd_status pdd_system_get_stats(pdd_system sys, pdd_system_stats* out) {
   if (!sys || !out) return fail(PDD_EINVAL, "pdd_system_get_stats: null argument");
   *out = sys->stats;

@@ -300,6 +300,47 @@ __global__ void gather_kernel(const int64_t* __restrict__ perm, const double* __
   if (i < n) dst[i] = src[perm[i]];
 }
 
+// Dense [A | b] of order np >= N for the operator A (C or C^T) in CSR,
+// row-major with leading dimension ld, zeroed beforehand: a workgroup per
+// row of A scatters its entries; padding rows get a unit diagonal; column np
+// holds the right-hand side (zero on padding rows).
+__global__ void dense_scatter_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ cols,
+                                     const double* __restrict__ val, const double* __restrict__ b, int64_t N,
+                                     int np, double* __restrict__ A, int ld) {
+  const int64_t i = blockIdx.x;
+  double* row = A + i * ld;
+  if (i < N) {
+    for (int64_t k = rowptr[i] + threadIdx.x; k < rowptr[i + 1]; k += blockDim.x) row[cols[k]] = val[k];
+    if (threadIdx.x == 0) row[np] = b[i];
+  } else if (threadIdx.x == 0) {
+    row[i] = 1.0;
+  }
+}
+
+// u = the solution column; |b - A u|^2 and |b|^2 into out[0], out[1], summed
+// by one workgroup in a fixed order.
+__global__ __launch_bounds__(kThreads) void dense_finish_kernel(
+    const int64_t* __restrict__ rowptr, const int32_t* __restrict__ cols, const double* __restrict__ val,
+    const double* __restrict__ b, int64_t N, int np, const double* __restrict__ A, int ld,
+    double* __restrict__ u, double* __restrict__ out) {
+  __shared__ double s4[4];
+  double rr = 0.0, bb = 0.0;
+  for (int64_t i = threadIdx.x; i < N; i += kThreads) {
+    u[i] = A[i * ld + np];
+    double ax = 0.0;
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) ax += val[k] * A[(int64_t)cols[k] * ld + np];
+    const double ri = b[i] - ax;
+    rr += ri * ri;
+    bb += b[i] * b[i];
+  }
+  rr = block_sum<4>(rr, s4);
+  bb = block_sum<4>(bb, s4);
+  if (threadIdx.x == 0) {
+    out[0] = rr;
+    out[1] = bb;
+  }
+}
+
 }  // namespace
 
 // Transpose pattern of C: rows of C^T with, for each entry, its position in C.
@@ -383,11 +424,75 @@ struct SolveParams {
   double rtol;
   int max_iter;
   bool guess;
+  int method;
 };
 
 SolveParams params(const pdd_solve_opts* opts) {
   return {(opts && opts->rtol > 0.0) ? opts->rtol : 1e-12,
-          (opts && opts->max_iter > 0) ? opts->max_iter : 2000, opts && opts->use_guess};
+          (opts && opts->max_iter > 0) ? opts->max_iter : 2000, opts && opts->use_guess,
+          opts ? opts->method : PDD_SOLVE_BICGSTAB};
+}
+
+constexpr int64_t kDirectMax = 4096;   // largest order of the batched LU's panel classes
+
+// PDD_SOLVE_DIRECT_SMALL: [A | b] (A = C or C^T) formed densely and solved by
+// the batched LU with partial pivoting (one matrix, one right-hand side,
+// eliminated and back-substituted inside the factorisation); reports the
+// relative residual |b - A u| / |b|.
+pdd_status direct_impl(pdd_system sys, const double* b, double* u, bool transpose, hipStream_t st,
+                       pdd_solve_info* info) {
+  const DeviceCover& D = sys->cover->D;
+  const int64_t N = sys->cover->H.N();
+  if (N > kDirectMax)
+    return fail(PDD_EINVAL, "pdd_solve_G: the direct method takes at most " + std::to_string(kDirectMax) +
+                                " knots, the system has " + std::to_string(N));
+  if (N == 0) {
+    if (info) *info = pdd_solve_info{0, 1, 0.0};
+    return PDD_OK;
+  }
+  const int64_t* rowptr = transpose ? D.rt_rowptr.ptr<int64_t>() : D.rowptr.ptr<int64_t>();
+  const int32_t* cols = transpose ? D.rt_cols.ptr<int32_t>() : D.cols.ptr<int32_t>();
+  const double* val = transpose ? sys->val_t.ptr<double>() : sys->val.ptr<double>();
+  const int np = (int)((N + 31) / 32 * 32);
+  const int ld = np + 16;
+  DevBuf mat, piv, status, work, out;
+  mat.alloc((size_t)np * ld * sizeof(double));
+  piv.alloc((size_t)np * sizeof(int32_t));
+  status.alloc(sizeof(int32_t));
+  work.alloc(lu_work_bytes_per_matrix(np));
+  out.alloc(2 * sizeof(double));
+  PDD_HIP(hipMemsetAsync(mat.ptr<void>(), 0, mat.bytes(), st));
+  PDD_HIP(hipMemsetAsync(status.ptr<void>(), 0, sizeof(int32_t), st));
+  hipLaunchKernelGGL(dense_scatter_kernel, dim3((unsigned)np), dim3(64), 0, st, rowptr, cols, val, b, N, np,
+                     mat.ptr<double>(), ld);
+  PDD_HIP(hipGetLastError());
+  LuItem it{};
+  it.A = mat.ptr<double>();
+  it.piv = piv.ptr<int32_t>();
+  it.status = status.ptr<int32_t>();
+  it.work = work.ptr<LuWork>();
+  it.uinv = reinterpret_cast<double*>(work.ptr<char>() + lu_work_header_bytes());
+  it.n = np;
+  it.ld = ld;
+  it.nrhs = 1;
+  it.cls = lu_panel_class(np);
+  int32_t stat = 0;
+  double host[2] = {0.0, 0.0};
+  {
+    LuPlan plan;
+    plan.build(std::vector<LuItem>{it});
+    plan.launch(st, 1 << 30);
+    hipLaunchKernelGGL(dense_finish_kernel, dim3(1), dim3(kThreads), 0, st, rowptr, cols, val, b, N, np,
+                       mat.ptr<double>(), ld, u, out.ptr<double>());
+    PDD_HIP(hipGetLastError());
+    PDD_HIP(hipMemcpyAsync(host, out.ptr<void>(), sizeof host, hipMemcpyDeviceToHost, st));
+    PDD_HIP(hipMemcpyAsync(&stat, status.ptr<void>(), sizeof stat, hipMemcpyDeviceToHost, st));
+    PDD_HIP(hipStreamSynchronize(st));   // the plan and the buffers are released on return
+  }
+  const double rel = host[1] > 0.0 ? std::sqrt(host[0] / host[1]) : 0.0;
+  if (info) *info = pdd_solve_info{1, stat ? 0 : 1, rel};
+  if (stat) return fail(PDD_EBREAKDOWN, "pdd_solve_G: zero pivot in the dense LU of the system");
+  return PDD_OK;
 }
 
 // Reports a final record through info and the return status.
@@ -427,6 +532,8 @@ pdd_status solve_impl(pdd_system sys, const double* rhs, double* u, int32_t tran
     }
   }
   const double* b = rhs ? rhs : sys->b.ptr<double>();
+  if (P.method == PDD_SOLVE_DIRECT_SMALL) return direct_impl(sys, b, u, transpose != 0, st, info);
+  if (P.method != PDD_SOLVE_BICGSTAB) return fail(PDD_EINVAL, "pdd_solve_G: unknown method");
   const size_t wbytes = sizeof(double) * (size_t)work_doubles(N);
   // scratch from the cover's pool, returned when this call ends
   int dev = 0;
@@ -532,6 +639,8 @@ pdd_status solve_noalloc_impl(pdd_system sys, const double* rhs, double* u, int3
                               const pdd_solve_opts* opts, hipStream_t st, pdd_solve_info* info) {
   const int64_t N = sys->cover->H.N();
   const SolveParams P = params(opts);
+  if (P.method != PDD_SOLVE_BICGSTAB)
+    return fail(PDD_EINVAL, "pdd_solve_G_noalloc: only PDD_SOLVE_BICGSTAB runs without allocating");
   if (work_doubles(N) > kScratchDoubles)
     return fail(PDD_EINVAL, "pdd_solve_G_noalloc: " + std::to_string(N) +
                                 " unknowns need " + std::to_string(work_doubles(N)) +

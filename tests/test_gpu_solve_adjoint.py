@@ -54,6 +54,30 @@ def test_solve_matches_direct_solve(name):
     _say(f"[gpu] {name}: {info.iterations} / {info_t.iterations} BiCGStab iterations")
 
 
+@pytest.mark.parametrize("name", ["config1", "small_variable", "no_floating"])
+def test_direct_small_matches_direct_solve(name):
+    # PDD_SOLVE_DIRECT_SMALL: dense LU of [C | r] on the device (one matrix of
+    # the batched LU) against scipy's sparse LU, on C and on C^T
+    pdd, torch = _gpu()
+    cfg = {"config1": workloads.config1, "no_floating": lambda: workloads.degenerate("no_floating"),
+           "small_variable": lambda: workloads.small_variable(paths=128)}[name]()
+    prob = cfg["problem"]
+    _say(f"[gpu] direct solve {name}")
+    cv = pdd.Cover(prob["domain"], cfg["cover"])
+    sysm = pdd.System(cv, prob, cfg["mc"])
+    val, b, _, _ = (t.cpu().numpy() for t in sysm.copy())
+    A = sp.csc_matrix(_host_matrix(cv, val))
+    u_ref = spla.splu(A).solve(b)
+    u, info = sysm.solve(method="direct")
+    assert info.converged and info.iterations == 1 and info.rel_residual < 1e-13
+    assert np.max(np.abs(u.cpu().numpy() - u_ref)) <= 1e-12 * np.max(np.abs(u_ref))
+    g = np.random.default_rng(2).standard_normal(cv.N)
+    lam, info_t = sysm.solve(rhs=torch.tensor(g, device="cuda"), transpose=True, method="direct")
+    lam_ref = spla.splu(sp.csc_matrix(A.T)).solve(g)
+    assert info_t.converged and info_t.rel_residual < 1e-13
+    assert np.max(np.abs(lam.cpu().numpy() - lam_ref)) <= 1e-12 * np.max(np.abs(lam_ref))
+
+
 def _setup_variable():
     cfg = workloads.small_variable(paths=64)
     prob = cfg["problem"]
@@ -70,10 +94,12 @@ def test_adjoint_matches_oracle_adjoint():
     rng = np.random.default_rng(5)
     target = torch.tensor(u.cpu().numpy() + rng.normal(0, 1e-2, cv.N), device="cuda")
     lam, _ = sysm.solve(rhs=2.0 * (u - target), transpose=True, rtol=1e-13)
-    g = {k: v.cpu().numpy() for k, v in sysm.backward(u, lam).items()}
+    g = {k: v.cpu().numpy() for k, v in sysm.backward(u, lam, names=("axx", "axy", "ayy", "bx", "by", "c",
+                                                                       "f", "r")).items()}
     ref_cover = geometry.build_cover(prob["domain"], cfg["cover"])
     xy, off, ids = cv.nodes()
     u_h, lam_h = u.cpu().numpy(), lam.cpu().numpy()
+    assert np.array_equal(g["r"], lam_h)          # dL/dr = lambda (r enters C u = r linearly)
     for f, m in enumerate(ids):
         grid = spectral.local_grid(ref_cover.Nr[m], ref_cover.Ntheta[m])
         samples = spectral.node_samples(prob, grid, *ref_cover.centres[m], ref_cover.radii[m])
@@ -145,3 +171,21 @@ def test_chunked_factor_recompute_matches_stored_factors():
     g2 = s2.backward(u, lam)
     for k in g1:
         assert torch.equal(g1[k], g2[k]), k
+
+
+@pytest.mark.parametrize("rule", [0, 2])
+def test_system_csr_matches_pattern_and_values(rule):
+    # pdd_system_csr: the CSR of C and r in one call, equal to the host
+    # pattern and to pdd_system_copy (rule 2: the averaged rows of eqs. 38-39)
+    pdd, torch = _gpu()
+    cfg = workloads.config1(paths=64)
+    prob = cfg["problem"]
+    cov = dict(cfg["cover"], rule=rule)
+    _say(f"[gpu] system_csr rule {rule}")
+    cv = pdd.Cover(prob["domain"], cov)
+    sysm = pdd.System(cv, prob, cfg["mc"])
+    rowptr, cols, val, b, se = (t.cpu().numpy() for t in sysm.csr())
+    rp_h, cols_h = cv.pattern()
+    assert np.array_equal(rowptr, rp_h) and np.array_equal(cols, cols_h)
+    val2, b2, se2, _ = (t.cpu().numpy() for t in sysm.copy())
+    assert np.array_equal(val, val2) and np.array_equal(b, b2) and np.array_equal(se, se2)
