@@ -254,7 +254,9 @@ typedef struct pdd_assemble_opts {
                               compute units (each strides over its work list);
                               0 = one workgroup per tile                              */
   int32_t use_graph;       /* 1: capture the LU launch sequence of a group in a HIP
-                              graph and replay it for groups of the same shape        */
+                              graph and replay it for groups of the same shape; only
+                              when such groups follow (transient factor buffers and
+                              more than one group), otherwise launched directly      */
   int32_t reserved;
 } pdd_assemble_opts;
 
@@ -315,6 +317,7 @@ typedef struct pdd_system_stats {
   int32_t grid_cap;        /*   PDD_PLAN_AUTOTUNED)                                    */
   int32_t graph_replays;   /* LU launch sequences replayed from a captured graph     */
   float ms_autotune;       /* time spent tuning in this call (0 when cached)         */
+  int64_t gamma_exits;     /* Monte Carlo paths that exited on the interface Gamma_m  */
 } pdd_system_stats;
 
 pdd_status pdd_system_get_stats(pdd_system sys, pdd_system_stats* out);
@@ -351,9 +354,13 @@ typedef struct pdd_solve_info {
  *     collocation matrices, one matrix); info->iterations = 1 and
  *     rel_residual = |rhs - C u| / |rhs|.  Allocates about 8 N^2 bytes for
  *     the call; synchronises the stream once.
- * The first transposed solve on a system forms C^T (its pattern per cover,
- * its values per system) and synchronises the stream.  Solves on one system
- * may run concurrently on different streams.
+ * The first BiCGStab solve on a system lays its values out per row (the
+ * stencil entries of each row in knot order, the diagonal apart: about
+ * 8 nnz bytes, kept with the system) and synchronises the stream; that form
+ * serves C and C^T.  Under rule AVERAGED (several stencils per row) C keeps
+ * its CSR form and the first transposed solve forms C^T in CSR (pattern per
+ * cover, values per system).  Solves on one system may run concurrently on
+ * different streams.
  * Errors: PDD_EINVAL (unknown method, N > 4096 for the direct method),
  * PDD_ENOCONV (BiCGStab; u holds the last iterate), PDD_EBREAKDOWN (zero
  * pivot in the direct method), PDD_ENOMEM, PDD_EDEVICE.
@@ -368,10 +375,10 @@ pdd_status pdd_solve_G(pdd_system sys, const double* rhs, double* u, int32_t tra
  * and results, but its work area is a fixed 48 MiB array of static device
  * memory, one per GPU, which the library holds until the process ends; the
  * call allocates nothing and creates no events.
- *   Limit: 5 N + 5 ceil(N/128) + 2 ceil(N/256) + 28 <= 6291456 doubles, i.e.
- *   N up to about 1.24 million knots; larger systems get PDD_EINVAL.
- *   transpose = 1 needs C^T to exist: one pdd_solve_G call with transpose = 1
- *   on the system forms it (else PDD_EINVAL).
+ *   Limit: 5 N + 14364 <= 6291456 doubles, i.e. N up to 1255418 knots;
+ *   larger systems get PDD_EINVAL.
+ *   The operator must already be in its solve form: one pdd_solve_G call on
+ *   the system in the same direction builds it (else PDD_EINVAL).
  *   Every call on one GPU uses the same work area and leaves its contents
  *   there; calls that overlap on one GPU (other threads or streams) race and
  *   must be serialised by the caller.

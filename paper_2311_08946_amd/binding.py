@@ -93,7 +93,7 @@ class SystemStats(C.Structure):
                                          "ms_mc", "ms_total")] + \
                [("factor_bytes", C.c_int64), ("recompute", C.c_int32), ("n_groups", C.c_int32),
                 ("mixed_buckets", C.c_int32), ("grid_cap", C.c_int32), ("graph_replays", C.c_int32),
-                ("ms_autotune", C.c_float)]
+                ("ms_autotune", C.c_float), ("gamma_exits", C.c_int64)]
 
 
 class SolveOpts(C.Structure):

@@ -256,7 +256,13 @@ struct GroupRun {
   int cus = 256;
   LuScratch work;
   std::vector<std::unique_ptr<BucketFactors>> reuse;   // per bucket, transient groups
-  std::vector<std::unique_ptr<LuPlan>> plans;          // alive until finish()
+  std::vector<std::unique_ptr<LuPlan>> plans;          // alive as long as the run
+  struct Planned {
+    std::vector<int32_t> counts;
+    std::vector<BucketFactors*> fs;
+    LuPlan* plan;
+  };
+  std::vector<Planned> planned;
   LuPlan* last_plan = nullptr;
   std::vector<int32_t> last_counts;
   std::vector<BucketFactors*> last_fs;
@@ -306,6 +312,7 @@ struct GroupRun {
       PDD_HIP(hipStreamSynchronize(st));
       drop_graph();
       last_plan = nullptr;
+      planned.clear();                     // their items point into the old work buffer
       work.buf.alloc(wbytes);
       work.bytes = wbytes;
     }
@@ -321,8 +328,15 @@ struct GroupRun {
     std::vector<int32_t> counts;
     for (const auto& sl : grp) counts.push_back(sl.bucket), counts.push_back(sl.cnt);
     const bool same = last_plan && counts == last_counts && fs == last_fs;
+    // a group this run has planned before (the autotuner repeats its groups)
+    LuPlan* seen = nullptr;
+    if (!same)
+      for (const auto& pk : planned)
+        if (pk.counts == counts && pk.fs == fs) seen = pk.plan;
     e = hooks ? hooks->begin(PH_LU) : -1;
-    if (!same) {
+    if (seen) {
+      launches += seen->launch(st, grid_cap());
+    } else if (!same) {
       std::vector<LuItem> its;
       char* w = static_cast<char*>(work.buf.ptr<void>());
       for (size_t k = 0; k < grp.size(); ++k) {
@@ -346,6 +360,7 @@ struct GroupRun {
       auto plan = std::make_unique<LuPlan>();
       plan->build(its);
       last_plan = plan.get();
+      planned.push_back(Planned{counts, fs, plan.get()});
       plans.push_back(std::move(plan));
       last_counts = counts;
       last_fs = fs;
@@ -390,13 +405,21 @@ struct GroupRun {
 };
 
 // Times the candidate schedules (mixed or per-bucket groups, grid caps) on a
-// sample of up to 64 circles per bucket (build and LU only) and returns the
-// fastest.
+// sample of each bucket (build and LU) and returns the fastest.  The sample
+// is large enough to fill the GPU several times over (up to 2048 circles per
+// bucket, at most 8 GiB of factors in all), every candidate's plan is built
+// and run once untimed, then its launches are timed three times and the
+// median kept.  With one bucket the mixed and per-bucket groupings are the
+// same schedule and only the grid caps are compared.
 void autotune(const DeviceCover& D, const NodeSamples& S, int64_t budget, hipStream_t st, bool& mixed,
               int& cap) {
+  constexpr int kSampleMax = 2048;
+  constexpr int64_t kSampleBytes = (int64_t)8 << 30;
   std::vector<std::vector<Slice>> sample_mixed(1), sample_sep;
+  int64_t per_bucket_bytes = kSampleBytes / std::max<int64_t>(1, (int64_t)D.buckets.size());
   for (int b = 0; b < (int)D.buckets.size(); ++b) {
-    const int32_t c = std::min<int32_t>(64, D.buckets[b]->count);
+    const int64_t fit = std::max<int64_t>(1, per_bucket_bytes / factor_bytes_per_circle(*D.buckets[b]));
+    const int32_t c = (int32_t)std::min<int64_t>({(int64_t)kSampleMax, fit, (int64_t)D.buckets[b]->count});
     if (c == 0) continue;
     sample_mixed[0].push_back(Slice{b, 0, c});
     sample_sep.push_back({Slice{b, 0, c}});
@@ -412,37 +435,45 @@ void autotune(const DeviceCover& D, const NodeSamples& S, int64_t budget, hipStr
   hipEvent_t e0, e1;
   PDD_HIP(hipEventCreate(&e0));
   PDD_HIP(hipEventCreate(&e1));
+  struct Guard {
+    hipEvent_t a, b;
+    ~Guard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  } guard{e0, e1};
   float best = 1e30f;
   const int caps[3] = {0, 1, 2};
-  bool first = true;
-  for (int mx = 1; mx >= 0; --mx)
+  const bool one_bucket = sample_sep.size() <= 1;
+  for (int mx = 1; mx >= (one_bucket ? 1 : 0); --mx)
     for (int ci = 0; ci < 3; ++ci) {
       Schedule sc;
       sc.mixed = mx != 0;
       sc.grid_cap = caps[ci];
       const auto& groups = sc.mixed ? sample_mixed : sample_sep;
-      for (int rep = 0; rep < (first ? 2 : 1); ++rep) {
-        GroupRun run(D, st, sc);
-        PDD_HIP(hipEventRecord(e0, st));
+      GroupRun run(D, st, sc);
+      auto once = [&]() {
         for (const auto& grp : groups) {
           std::vector<BucketFactors*> fs;
           for (const auto& sl : grp) fs.push_back(fac[sl.bucket].get());
           run.group(grp, fs, S, nullptr, nullptr, nullptr, fails.ptr<uint64_t>());
         }
+      };
+      once();                                   // builds the plans, first-touch costs
+      once();                                   // (groups planned before a work-buffer growth)
+      run.finish();
+      float ms[3];
+      for (int rep = 0; rep < 3; ++rep) {
+        PDD_HIP(hipEventRecord(e0, st));
+        once();
         PDD_HIP(hipEventRecord(e1, st));
         run.finish();
+        PDD_HIP(hipEventElapsedTime(&ms[rep], e0, e1));
       }
-      first = false;
-      float ms = 0.0f;
-      PDD_HIP(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best) {
-        best = ms;
+      std::sort(ms, ms + 3);
+      if (ms[1] < best) {
+        best = ms[1];
         mixed = sc.mixed;
         cap = sc.grid_cap;
       }
     }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   (void)budget;
 }
 
@@ -574,8 +605,8 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
   // The Monte Carlo and boundary rows run on a second stream, concurrently
   // with the floating rows; both write disjoint rows of the CSR arrays.
   DevBuf lu_fail;
-  lu_fail.alloc(sizeof(uint64_t) * 4);
-  PDD_HIP(hipMemsetAsync(lu_fail.ptr<void>(), 0, sizeof(uint64_t) * 4, st));
+  lu_fail.alloc(sizeof(uint64_t) * 5);
+  PDD_HIP(hipMemsetAsync(lu_fail.ptr<void>(), 0, sizeof(uint64_t) * 5, st));
   if (!D.side) PDD_HIP(hipStreamCreateWithFlags(&D.side, hipStreamNonBlocking));
   hipStream_t side = D.side;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -591,7 +622,7 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
   // ---- perimeter rows by Monte Carlo (side stream)
   const int64_t n_mc = (int64_t)H.mc_knots.size();
   const int64_t n_perim = (int64_t)H.perim_ids.size();
-  DevBuf out_phi, out_g, out_steps, out_capped, gram, gram_status, hcirc;
+  DevBuf out_phi, out_g, out_steps, out_capped, out_gamma, gram, gram_status, hcirc;
   int32_t n_launch_mc = 0;
   if (n_mc > 0) {
     const int e = timer.begin(PH_MC, side);
@@ -623,12 +654,14 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
     out_g.alloc(std::max<int64_t>(1, a.n_units) * sizeof(double));
     out_steps.alloc(std::max<int64_t>(1, a.n_units) * sizeof(uint64_t));
     out_capped.alloc(std::max<int64_t>(1, a.n_units) * sizeof(uint64_t));
+    out_gamma.alloc(std::max<int64_t>(1, a.n_units) * sizeof(uint64_t));
     gram.alloc(std::max<int64_t>(1, n_perim * a.gram_stride) * sizeof(double));
     gram_status.alloc(std::max<int64_t>(1, n_perim) * sizeof(int32_t));
     a.out_phi = out_phi.ptr<double>();
     a.out_g = out_g.ptr<double>();
     a.out_steps = out_steps.ptr<uint64_t>();
     a.out_capped = out_capped.ptr<uint64_t>();
+    a.out_gamma = out_gamma.ptr<uint64_t>();
     launch_mc_paths(P, dp.const_coef != 0, a, side);
     launch_gram_cholesky(a, (int32_t)n_perim, gram.ptr<double>(), gram_status.ptr<int32_t>(), side);
     launch_mc_finalize(a, (int32_t)n_mc, H.max_arc, gram.ptr<double>(), val, se, bv, se_b, side);
@@ -640,6 +673,8 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
     if (n_perim > 0)
       hipLaunchKernelGGL(reduce_i32_kernel, dim3(1), dim3(256), 0, side, gram_status.ptr<int32_t>(),
                          n_perim, lu_fail.ptr<uint64_t>() + 3);
+    hipLaunchKernelGGL(reduce_u64_kernel, dim3(1), dim3(256), 0, side, out_gamma.ptr<uint64_t>(),
+                       a.n_units, lu_fail.ptr<uint64_t>() + 4);
     n_launch_mc = 3;
     timer.end(e);
   }
@@ -651,6 +686,9 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
 
   // ---- floating rows in groups (see the schedule in pdd.h)
   const auto groups = make_groups(D, plan, keep_all, budget, sched.mixed);
+  // a captured graph pays only when later groups replay it: groups of the same
+  // shape on the same transient buffers (stored factors give every group its own)
+  if (keep_all || groups.size() < 2) sched.graph = false;
   GroupRun run(D, st, sched);
   int32_t n_launch_spectral = 0;
   int64_t kept = 0;
@@ -688,12 +726,13 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
   }
   timer.end(t_all);
 
-  uint64_t flags[4] = {0, 0, 0, 0};
+  uint64_t flags[5] = {0, 0, 0, 0, 0};
   PDD_HIP(hipMemcpyAsync(flags, lu_fail.ptr<void>(), sizeof(flags), hipMemcpyDeviceToHost, st));
   PDD_HIP(hipStreamSynchronize(st));
   pdd_system_stats& s = sys->stats;
   s.path_steps = (int64_t)flags[1];
   s.capped_paths = (int64_t)flags[2];
+  s.gamma_exits = (int64_t)flags[4];
   s.paths = mc ? n_mc * mc->paths : 0;
   s.breakdowns = (int32_t)(flags[0] + flags[3]);
   s.n_launch_spectral = n_launch_spectral;

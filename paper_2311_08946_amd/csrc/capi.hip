@@ -131,6 +131,7 @@ void DeviceCover::upload(const HostCover& Hc) {
   pair_off.upload(Hc.pair_off); diag_pos.upload(Hc.diag_pos);
   pair_knot.upload(Hc.pair_knot); pair_seg.upload(Hc.pair_seg);
   have_transpose = false;
+  have_blocked = false;
   buckets.clear();
   for (const Bucket& b : Hc.buckets) {
     auto bd = std::make_unique<BucketData>();

@@ -387,9 +387,12 @@ namespace {
 
 // Composes the interchanges (base + t) <-> piv[t], t = 0..cnt-1 in order
 // (cnt <= 128), into one permutation of at most 2 cnt rows: rows[e] receives
-// the old contents of rows[src[e]].  Run by one thread.
+// the old contents of rows[src[e]].  slot[r] locates row r among the rows
+// added below the block (-1: not yet added); it must be -1 for every row on
+// entry and is restored on return, so each interchange costs O(1).  Run by
+// one thread on LDS arrays.
 __device__ void compose_perm(const int* __restrict__ piv, int base, int cnt, int* __restrict__ rows,
-                             int* __restrict__ src, int* __restrict__ count) {
+                             int* __restrict__ src, int* __restrict__ count, short* __restrict__ slot) {
   int nt = cnt;
   for (int t = 0; t < cnt; ++t) {
     rows[t] = base + t;
@@ -402,19 +405,19 @@ __device__ void compose_perm(const int* __restrict__ piv, int base, int cnt, int
     if (b < base + cnt) {
       sb = b - base;
     } else {
-      sb = -1;
-      for (int e = cnt; e < nt; ++e)
-        if (rows[e] == b) { sb = e; break; }
+      sb = slot[b];
       if (sb < 0) {
         sb = nt++;
         rows[sb] = b;
         src[sb] = sb;
+        slot[b] = (short)sb;
       }
     }
     const int tmp = src[t];
     src[t] = src[sb];
     src[sb] = tmp;
   }
+  for (int e = cnt; e < nt; ++e) slot[rows[e]] = -1;
   *count = nt;
 }
 
@@ -612,12 +615,15 @@ union PanelScratch {
   TriLds t;
 };
 
+constexpr int kMaxOrder = 4096;   // largest matrix order of the panel classes
+
 template <int NB>
 struct PanelShared {
   PanelScratch u;
   PanelLds<NB> pl;
   int piv[kOuter];
   PermLds perm;
+  short slot[kMaxOrder];        // compose_perm's row -> slot map
 };
 
 template <int ROWS, int NB>
@@ -629,6 +635,7 @@ __device__ __attribute__((always_inline)) void panel_body(const LuItem& it, int 
   const int tid = threadIdx.x;
   const int kb = min(kOuter, n - K0);
   int singular = 0;
+  for (int r = tid; r < n; r += kThreads) sh.slot[r] = -1;
   // groups of kTB columns, each factorised by sub-panels of NB columns; the
   // group's update of the rest of the panel uses K = kTB
   for (int b = 0, g0 = K0; g0 < K0 + kb; ++b, g0 += kTB) {
@@ -636,7 +643,8 @@ __device__ __attribute__((always_inline)) void panel_body(const LuItem& it, int 
     for (int k0 = g0; k0 < g0 + gw; k0 += NB) {
       const int pw = min(NB, g0 + gw - k0);
       factor_subpanel<ROWS, NB>(A, ld, n, k0, pw, K0, sh.piv, it.piv, sh.pl, singular);
-      if (tid == 0) compose_perm(sh.piv + (k0 - K0), k0, pw, sh.perm.rows, sh.perm.src, &sh.perm.count);
+      if (tid == 0)
+        compose_perm(sh.piv + (k0 - K0), k0, pw, sh.perm.rows, sh.perm.src, &sh.perm.count, sh.slot);
       __syncthreads();
       // the sub-panel's interchanges on the rest of the panel
       apply_perm(A, ld, sh.perm, K0, K0 + kb, k0, k0 + pw, &sh.u.sU[0][0]);
@@ -661,7 +669,15 @@ __device__ __attribute__((always_inline)) void panel_body(const LuItem& it, int 
     __syncthreads();
   }
   const int par = (K0 / kOuter) & 1;
-  if (tid == 0) compose_perm(sh.piv, K0, kb, W->rows[par], W->src[par], &W->count[par]);
+  // the step's composed permutation, formed in LDS and copied out
+  if (tid == 0) compose_perm(sh.piv, K0, kb, sh.perm.rows, sh.perm.src, &sh.perm.count, sh.slot);
+  __syncthreads();
+  const int nt = sh.perm.count;
+  for (int e = tid; e < nt; e += kThreads) {
+    W->rows[par][e] = sh.perm.rows[e];
+    W->src[par][e] = sh.perm.src[e];
+  }
+  if (tid == 0) W->count[par] = nt;
   if (tid == 0 && (K0 == 0 || singular)) *it.status = singular;
 }
 

@@ -40,6 +40,7 @@ struct McArgs {
   double* out_g;               // [n_units]
   uint64_t* out_steps;
   uint64_t* out_capped;
+  uint64_t* out_gamma;         // [n_units] paths that exited on Gamma_m
   int64_t gram_stride;         // max_arc^2
 };
 

@@ -24,6 +24,13 @@ namespace {
 
 constexpr int kW = 64;
 
+// Lane l's double, read by every lane (l wavefront-uniform).
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 struct Philox4 { uint32_t v[4]; };
 
 __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
@@ -189,6 +196,8 @@ __device__ __forceinline__ void paths_body(const DevProblem* __restrict__ P, con
   const int cap = a.step_cap;
   const DevProblem& PP = *P;
 
+  // arc knots in chunks of 64 (lane l holds knot l + 64 s); chunks is uniform
+  const int chunks = (n_arc + kW - 1) / kW;
   double th_arc[3];
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
@@ -197,7 +206,7 @@ __device__ __forceinline__ void paths_body(const DevProblem* __restrict__ P, con
   }
   double acc_phi[3] = {0.0, 0.0, 0.0};
   double acc_g = 0.0;
-  uint64_t steps = 0, capped = 0;
+  uint64_t steps = 0, capped = 0, gamma_exits = 0;
 
   // constant coefficients (Laplace-type problems)
   double s11 = 0, s21 = 0, s22 = 0, kbx = 0, kby = 0, kc = 0, kf = 0;
@@ -285,6 +294,7 @@ __device__ __forceinline__ void paths_body(const DevProblem* __restrict__ P, con
         steps += (uint64_t)k + 1;
         exited = true;
         if (on_gamma) {
+          ++gamma_exits;
           double th = atan2(ye - cy, xe - cx) - t0;
           th = t0 + (th - kTwoPiD * floor(th / kTwoPiD));
           if (th > t1) th = (th - t1 <= t0 + kTwoPiD - th) ? t1 : t0;
@@ -298,12 +308,15 @@ __device__ __forceinline__ void paths_body(const DevProblem* __restrict__ P, con
     while (gmask) {
       const int e = __ffsll((unsigned long long)gmask) - 1;
       gmask &= gmask - 1;
-      const double th = __shfl(th_e, e, kW);
-      const double wt = __shfl(w_e, e, kW);
+      // e is wavefront-uniform: the exit's angle and weight as scalars
+      const double th = readlane_f64(th_e, e);
+      const double wt = readlane_f64(w_e, e);
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
-        const double d = th - th_arc[s];
-        acc_phi[s] += wt * rsqrt(d * d + c2);
+        if (s < chunks) {
+          const double d = th - th_arc[s];
+          acc_phi[s] += wt * rsqrt(d * d + c2);
+        }
       }
     }
     // refill exited lanes with the next paths of the batch
@@ -323,6 +336,7 @@ __device__ __forceinline__ void paths_body(const DevProblem* __restrict__ P, con
     acc_g += __shfl_xor(acc_g, off, kW);
     steps += __shfl_xor(steps, off, kW);
     capped += __shfl_xor(capped, off, kW);
+    gamma_exits += __shfl_xor(gamma_exits, off, kW);
   }
   double* out = a.out_phi + unit * a.out_stride;
 #pragma unroll
@@ -334,6 +348,7 @@ __device__ __forceinline__ void paths_body(const DevProblem* __restrict__ P, con
     a.out_g[unit] = acc_g;
     a.out_steps[unit] = steps;
     a.out_capped[unit] = capped;
+    a.out_gamma[unit] = gamma_exits;
   }
 }
 

@@ -86,6 +86,14 @@ struct DeviceCover {
   DevBuf pair_off, diag_pos, pair_knot, pair_seg;   // rule AVERAGED (see HostCover)
   DevBuf rt_rowptr, rt_cols, rt_perm;   // transpose pattern of C (built on first use)
   bool have_transpose = false;
+  // Circle-blocked structure of C (built on the first solve; rules with one
+  // subdomain per row): row i holds C_ii and the stencil of its circle, a
+  // contiguous knot range starting at blk_so[i]; blk_circ_rows lists the rows
+  // of each circle (offsets blk_circ_off), which are the only rows whose
+  // stencils hold that circle's knots.
+  DevBuf blk_so, blk_circ_off, blk_circ_rows;
+  bool have_blocked = false;
+  bool blocked_ok = false;
   bool tuned = false;                   // schedule chosen by the autotuner for this cover
   bool tuned_mixed = true;
   int tuned_cap = 0;
@@ -195,4 +203,7 @@ struct pdd_system_s {
   pdd_system_stats stats{};
   std::vector<double> host_problem_bytes;
   pdd::DevBuf val_t;                   // C^T values (formed on the first transposed solve)
+  pdd::DevBuf vblk, dg;                // circle-blocked values: per row its stencil entries
+                                       // (at rowptr[i] - i) and the diagonal (formed on the first solve)
+  bool have_vblk = false;
 };

@@ -1,22 +1,36 @@
 // Solve of the interfacial system C u = r (and C^T lambda = g for the
 // adjoint) by BiCGStab on the device.  The paper solves C u = r with GMRES and
 // a one-level restricted additive Schwarz preconditioner (Section 4, eqs.
-// 42-45); C has a unit diagonal, and plain BiCGStab converges in tens of
+// 42-45); C has a unit diagonal, and plain BiCGStab converges in hundreds of
 // iterations on the covers here.
 //
-// One iteration is four launches: p = r + beta (p - omega v); v = C p with
-// per-workgroup partial sums of (r0, v); t = C s with s = r - alpha v formed on
+// Operator layout.  With one subdomain per row (eqs. 28-30, Section 3.2), row
+// i of C holds C_ii and the entries of one circle's stencil, a contiguous
+// range of knots (eq. 9); and the knots of circle m appear only in the rows
+// assigned to m.  On the first solve of a system the values are re-laid out
+// per row -- the stencil entries in knot order at rowptr[i] - i, the diagonal
+// apart -- so that a product reads 8 bytes per entry and no column indices:
+//   C x   : a 16-lane group per row, y_i = C_ii x_i + sum_j V_ij x[so_i + j],
+//           the gathers from x contiguous;
+//   C^T x : a wavefront per circle m, its lanes over the knots j of m,
+//           y_j = C_jj x_j + sum_{rows i of m} V_ij x_i, each row's entries
+//           one coalesced load and x_i one scalar load -- no atomics and no
+//           transposed copy.
+// Rows of the averaged rule (eqs. 38-39) hold several stencils; those systems
+// keep the CSR form (and a transposed CSR copy for C^T).
+//
+// One iteration is four launches: p = r + beta (p - omega v); v = A p with
+// per-workgroup partial sums of (r0, v); t = A s with s = r - alpha v formed on
 // the fly and partial sums of (t, s), (t, t); the x and r updates with partial
-// sums of (r, r) and (r0, r).  Each kernel's workgroups first add the partial
-// sums of the kernel before it -- every workgroup the same partials in the
-// same fixed order, so all derive the same scalars (alpha, omega, beta, the
-// stopping test) and results are bitwise reproducible without a separate
-// reduction launch; workgroup 0 records them.  Every kernel returns at once
-// after the stopping test has fired, which lets the host enqueue several
-// iterations per status read; a one-workgroup status kernel per batch adds
-// the last partials for the host.  Sparse rows are handled by 8-lane groups
-// (128 rows per 1024-thread workgroup: the grid fits the GPU in one round, and
-// few partial sums are re-added).
+// sums of (r, r) and (r0, r).  Every kernel runs on a fixed grid of kGrid
+// workgroups striding over its rows or circles, and each workgroup first adds
+// the kGrid partial sums of the kernel before it -- every workgroup the same
+// partials in the same fixed order, so all derive the same scalars (alpha,
+// omega, beta, the stopping test) and results are bitwise reproducible
+// without a separate reduction launch; workgroup 0 records them.  Every kernel
+// returns at once after the stopping test has fired, which lets the host
+// enqueue several iterations per status read; a one-workgroup status kernel
+// per batch adds the last partials for the host.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,11 +45,13 @@ namespace pdd {
 
 namespace {
 
-constexpr int kThreads = 256;        // vector kernels: one entry per thread
-constexpr int kSpThreads = 1024;     // sparse kernels: kLanesPerRow lanes per row
-constexpr int kLanesPerRow = 8;
-constexpr int kRowsPerBlock = kSpThreads / kLanesPerRow;
+constexpr int kThreads = 256;        // every kernel: four wavefronts
+constexpr int kGrid = 2048;          // workgroups of every iteration kernel (strided)
+constexpr int kLanes = 16;           // lanes per row in the row products
+constexpr int kRowsPerPass = kThreads / kLanes;
 constexpr int kItersPerSync = 8;
+
+enum { OP_CSR = 0, OP_ROWS = 1, OP_CIRCLES = 2 };
 
 enum {
   S_RHO = 0, S_ALPHA, S_OMEGA, S_BETA, S_RV, S_TS, S_TT, S_RR, S_BB, S_TOL2, S_DONE, S_FAIL,
@@ -43,9 +59,18 @@ enum {
 };
 
 struct SolveCtx {
-  const int64_t* rowptr;
-  const int32_t* cols;
-  const double* val;
+  // the operator A (C or C^T)
+  int kind;
+  const int64_t* rowptr;   // CSR row pointers of A (OP_CSR) or of C (blocked kinds)
+  const int32_t* cols;     // OP_CSR
+  const double* val;       // OP_CSR
+  const double* vblk;      // blocked: stencil entries of row i at rowptr[i] - i
+  const double* dg;        // blocked: diagonal
+  const int32_t* so;       // OP_ROWS: first knot of row i's stencil
+  const int64_t* knot_off; // OP_CIRCLES: knots of circle m are [knot_off[m], knot_off[m + 1])
+  const int64_t* circ_off; // OP_CIRCLES: rows of circle m are circ_rows[circ_off[m] ..)
+  const int32_t* circ_rows;
+  int32_t nc;
   int64_t N;
   double* x;
   double* r;
@@ -53,12 +78,10 @@ struct SolveCtx {
   double* p;
   double* v;
   double* t;
-  double* part_i;      // [2][nblocks] init: (b, b), (r, r)
-  double* part_v;      // [nblocks]    spmv_v: (r0, v)
-  double* part_t;      // [2][nblocks] spmv_t: (t, s), (t, t)
-  double* part_x;      // [2][vblocks] update_xr: (r, r), (r0, r)
-  int nblocks;         // grid of the sparse kernels (one workgroup per 64 rows)
-  int vblocks;         // grid of the vector kernels (one workgroup per 256 entries)
+  double* part_i;      // [2][kGrid] init: (b, b), (r, r)
+  double* part_v;      // [kGrid]    spmv_v: (r0, v)
+  double* part_t;      // [2][kGrid] spmv_t: (t, s), (t, t)
+  double* part_x;      // [2][kGrid] update_xr: (r, r), (r0, r)
   double* sc;          // scalars, written by workgroup 0 of the kernel that derives them
   double* status;      // the host's record: the state after the last finished iteration
 };
@@ -69,66 +92,161 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Workgroup sum in a fixed order (wave sums, then the wave totals in order).
-template <int NW>
 __device__ __forceinline__ double block_sum(double v, double* s) {
   v = wave_sum(v);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __syncthreads();
   if (lane == 0) s[w] = v;
   __syncthreads();
-  double t = 0.0;
-#pragma unroll
-  for (int k = 0; k < NW; ++k) t += s[k];
-  return t;
+  return s[0] + s[1] + s[2] + s[3];
 }
 
-// Sum of part[0:n) in a fixed order (the same in every workgroup of a grid).
-template <int NW>
-__device__ __forceinline__ double sum_parts(const double* __restrict__ part, int n, double* s) {
+// Sum of part[0:kGrid) in a fixed order (the same in every workgroup).
+__device__ __forceinline__ double sum_parts(const double* __restrict__ part, double* s) {
   double a = 0.0;
-  for (int i = threadIdx.x; i < n; i += 64 * NW) a += part[i];
-  return block_sum<NW>(a, s);
+#pragma unroll
+  for (int i = 0; i < kGrid / kThreads; ++i) a += part[threadIdx.x + kThreads * i];
+  return block_sum(a, s);
 }
 
-// Row of a kLanesPerRow-lane group: sum_k val[k] (y - beta z)[cols[k]], reduced inside the group.
-__device__ __forceinline__ double row_sum(const SolveCtx& c, int64_t row, const double* y,
-                                        const double* z, double beta, int sub) {
-  double acc = 0.0;
-  if (row < c.N) {
-    const int64_t lo = c.rowptr[row], hi = c.rowptr[row + 1];
-    for (int64_t k = lo + sub; k < hi; k += kLanesPerRow) {
-      const int32_t j = c.cols[k];
-      acc += c.val[k] * (z ? y[j] - beta * z[j] : y[j]);
+// The input vector of a product: y (ALPHA = false) or y - alpha z.
+template <bool ALPHA>
+struct In {
+  const double* y;
+  const double* z;
+  double alpha;
+  __device__ __forceinline__ double operator()(int64_t j) const { return ALPHA ? y[j] - alpha * z[j] : y[j]; }
+};
+
+// Lane l's value, read by every lane (l wavefront-uniform).
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ int64_t readlane_i64(int64_t v, int l) {
+  const int lo = __builtin_amdgcn_readlane((int)v, l), hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+  return ((int64_t)hi << 32) | (unsigned)lo;
+}
+
+// Visits every output (A x)_i once, in a partition fixed by the grid, calling
+// sink(i, value) from one lane per output.
+template <int OPK, class X, class Sink>
+__device__ __forceinline__ void apply_op(const SolveCtx& c, const X& in, Sink& sink) {
+  const int tid = threadIdx.x;
+  if (OPK == OP_CIRCLES) {
+    // circle m: lanes over its knots j; its rows' offsets and inputs are
+    // staged one per lane (64 rows at a time) and broadcast by readlane, so
+    // the loop issues only the coalesced loads of the rows' entries
+    const int lane = tid & 63;
+    for (int m = blockIdx.x * (kThreads / 64) + (tid >> 6); m < c.nc; m += gridDim.x * (kThreads / 64)) {
+      const int64_t s0 = c.knot_off[m], s1 = c.knot_off[m + 1];
+      const int64_t q0 = c.circ_off[m], q1 = c.circ_off[m + 1];
+      for (int64_t jb = s0; jb < s1; jb += 64) {
+        const int64_t j = jb + lane;
+        const bool ok = j < s1;
+        const int64_t jl = j - s0;
+        double a0 = 0.0, a1 = 0.0;
+        for (int64_t qb = q0; qb < q1; qb += 64) {
+          const int cnt = (int)min((int64_t)64, q1 - qb);
+          int64_t off = 0;
+          double xi = 0.0;
+          if (lane < cnt) {
+            const int32_t i = c.circ_rows[qb + lane];
+            off = c.rowptr[i] - i + (jb - s0);      // the row's entries of this chunk of knots
+            xi = in(i);
+          }
+          int q = 0;
+          for (; q + 4 <= cnt; q += 4) {
+            double v[4], x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int64_t o = readlane_i64(off, q + u);
+              x[u] = readlane_f64(xi, q + u);
+              v[u] = ok ? c.vblk[o + lane] : 0.0;
+            }
+            a0 += v[0] * x[0];
+            a1 += v[1] * x[1];
+            a0 += v[2] * x[2];
+            a1 += v[3] * x[3];
+          }
+          for (; q < cnt; ++q) {
+            const int64_t o = readlane_i64(off, q);
+            const double x = readlane_f64(xi, q);
+            if (ok) a0 += c.vblk[o + lane] * x;
+          }
+        }
+        if (ok) sink(j, c.dg[j] * in(j) + (a0 + a1));
+      }
     }
+    return;
   }
-  for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
-  return acc;
+  const int sub = tid & (kLanes - 1);
+  for (int64_t base = (int64_t)blockIdx.x * kRowsPerPass; base < c.N; base += (int64_t)gridDim.x * kRowsPerPass) {
+    const int64_t i = base + tid / kLanes;
+    double acc = 0.0;
+    if (i < c.N) {                           // uniform within the row's lanes
+      if (OPK == OP_CSR) {
+        const int64_t lo = c.rowptr[i], hi = c.rowptr[i + 1];
+        for (int64_t k = lo + sub; k < hi; k += kLanes) acc += c.val[k] * in(c.cols[k]);
+      } else {
+        const int64_t lo = c.rowptr[i] - i, len = c.rowptr[i + 1] - c.rowptr[i] - 1;
+        const int64_t so = c.so[i];
+        // four entries per lane per pass, every load issued before the products
+        for (int64_t jb = 0; jb < len; jb += 4 * kLanes) {
+          double v[4], x[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int64_t j = jb + sub + kLanes * u;
+            v[u] = 0.0;
+            x[u] = 0.0;
+            if (j < len) {
+              v[u] = c.vblk[lo + j];
+              x[u] = in(so + j);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc += v[u] * x[u];
+        }
+      }
+    }
+    for (int off = kLanes / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanes);
+    if (sub == 0 && i < c.N) sink(i, OPK == OP_CSR ? acc : c.dg[i] * in(i) + acc);
+  }
 }
 
-__global__ __launch_bounds__(kSpThreads) void init_kernel(SolveCtx c, const double* __restrict__ b,
-                                                          int use_guess) {
-  __shared__ double s16[16];
-  const int sub = threadIdx.x & (kLanesPerRow - 1);
-  const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x / kLanesPerRow);
-  // r = b - C x (x = 0 unless a guess is given)
-  const double ax = use_guess ? row_sum(c, row, c.x, nullptr, 0.0, sub) : 0.0;
+// x-independent start: r = b - A x (x = 0 unless a guess is given, whose
+// product the caller left in t), partial sums of (b, b) and (r, r).
+__global__ __launch_bounds__(kThreads) void init_kernel(SolveCtx c, const double* __restrict__ b, int use_guess) {
+  __shared__ double s4[4];
   double pbb = 0.0, prr = 0.0;
-  if (sub == 0 && row < c.N) {
-    const double ri = b[row] - ax;
-    if (!use_guess) c.x[row] = 0.0;
-    c.r[row] = ri;
-    c.r0[row] = ri;
-    c.p[row] = 0.0;
-    c.v[row] = 0.0;
-    pbb = b[row] * b[row];
-    prr = ri * ri;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < c.N; i += (int64_t)gridDim.x * kThreads) {
+    const double ri = b[i] - (use_guess ? c.t[i] : 0.0);
+    if (!use_guess) c.x[i] = 0.0;
+    c.r[i] = ri;
+    c.r0[i] = ri;
+    c.p[i] = 0.0;
+    c.v[i] = 0.0;
+    pbb += b[i] * b[i];
+    prr += ri * ri;
   }
-  const double sbb = block_sum<16>(pbb, s16);
-  const double srr = block_sum<16>(prr, s16);
+  const double sbb = block_sum(pbb, s4);
+  const double srr = block_sum(prr, s4);
   if (threadIdx.x == 0) {
     c.part_i[blockIdx.x] = sbb;
-    c.part_i[c.nblocks + blockIdx.x] = srr;
+    c.part_i[kGrid + blockIdx.x] = srr;
   }
+}
+
+// t = A x (the product of a starting guess).
+template <int OPK>
+__global__ __launch_bounds__(kThreads) void guess_product_kernel(SolveCtx c) {
+  struct Sink {
+    const SolveCtx& c;
+    __device__ void operator()(int64_t i, double y) { c.t[i] = y; }
+  } sink{c};
+  apply_op<OPK>(c, In<false>{c.x, nullptr, 0.0}, sink);
 }
 
 // The scalars after an x, r update (or after init when FIRST): the stopping
@@ -141,13 +259,12 @@ struct Next {
   bool done, fail;
 };
 
-template <int NW>
 __device__ Next next_state(const SolveCtx& c, bool first, double rtol, double* s) {
   const double* sc = c.sc;
   Next z{};
   if (first) {
-    z.bb = sum_parts<NW>(c.part_i, c.nblocks, s);
-    z.rr = sum_parts<NW>(c.part_i + c.nblocks, c.nblocks, s);
+    z.bb = sum_parts(c.part_i, s);
+    z.rr = sum_parts(c.part_i + kGrid, s);
     z.rho = z.rr;                    // (r0, r) with r0 = r
     z.beta = 0.0;
     z.tol2 = rtol * rtol * z.bb;
@@ -156,8 +273,8 @@ __device__ Next next_state(const SolveCtx& c, bool first, double rtol, double* s
     z.fail = false;
     return z;
   }
-  z.rr = sum_parts<NW>(c.part_x, c.vblocks, s);
-  z.rho = sum_parts<NW>(c.part_x + c.vblocks, c.vblocks, s);
+  z.rr = sum_parts(c.part_x, s);
+  z.rho = sum_parts(c.part_x + kGrid, s);
   z.bb = sc[S_BB];
   z.tol2 = sc[S_TOL2];
   z.beta = (z.rho / sc[S_RHO_PREV]) * (sc[S_ALPHA] / sc[S_OMEGA]);
@@ -193,56 +310,59 @@ __global__ __launch_bounds__(kThreads) void update_p_kernel(SolveCtx c, int firs
   if (threadIdx.x == 0) stop = (!first && c.sc[S_DONE] != 0.0) ? 1 : 0;
   __syncthreads();
   if (stop) return;
-  const Next z = next_state<4>(c, first != 0, rtol, s4);
+  const Next z = next_state(c, first != 0, rtol, s4);
   if (blockIdx.x == 0 && threadIdx.x == 0) record(c.sc, z, first != 0);
   if (z.done) return;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= c.N) return;
   const double omega = first ? 1.0 : c.sc[S_OMEGA];
-  c.p[i] = c.r[i] + z.beta * (c.p[i] - omega * c.v[i]);
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < c.N; i += (int64_t)gridDim.x * kThreads)
+    c.p[i] = c.r[i] + z.beta * (c.p[i] - omega * c.v[i]);
 }
 
-// v = C p, partial sums of (r0, v)
-__global__ __launch_bounds__(kSpThreads) void spmv_v_kernel(SolveCtx c) {
-  __shared__ double s16[16];
+// v = A p, partial sums of (r0, v)
+template <int OPK>
+__global__ __launch_bounds__(kThreads) void spmv_v_kernel(SolveCtx c) {
+  __shared__ double s4[4];
   if (c.sc[S_DONE] != 0.0) return;
-  const int sub = threadIdx.x & (kLanesPerRow - 1);
-  const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x / kLanesPerRow);
-  const double vi = row_sum(c, row, c.p, nullptr, 0.0, sub);
-  double prv = 0.0;
-  if (sub == 0 && row < c.N) {
-    c.v[row] = vi;
-    prv = c.r0[row] * vi;
-  }
-  const double sv = block_sum<16>(prv, s16);
+  struct Sink {
+    const SolveCtx& c;
+    double prv;
+    __device__ void operator()(int64_t i, double y) {
+      c.v[i] = y;
+      prv += c.r0[i] * y;
+    }
+  } sink{c, 0.0};
+  apply_op<OPK>(c, In<false>{c.p, nullptr, 0.0}, sink);
+  const double sv = block_sum(sink.prv, s4);
   if (threadIdx.x == 0) c.part_v[blockIdx.x] = sv;
 }
 
-// alpha = rho / (r0, v); t = C s with s = r - alpha v, partial sums of (t, s) and (t, t)
-__global__ __launch_bounds__(kSpThreads) void spmv_t_kernel(SolveCtx c) {
-  __shared__ double s16[16];
+// alpha = rho / (r0, v); t = A s with s = r - alpha v, partial sums of (t, s) and (t, t)
+template <int OPK>
+__global__ __launch_bounds__(kThreads) void spmv_t_kernel(SolveCtx c) {
+  __shared__ double s4[4];
   if (c.sc[S_DONE] != 0.0) return;
-  const double rv = sum_parts<16>(c.part_v, c.nblocks, s16);
+  const double rv = sum_parts(c.part_v, s4);
   const double alpha = c.sc[S_RHO] / rv;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     c.sc[S_RV] = rv;
     c.sc[S_ALPHA] = alpha;
   }
-  const int sub = threadIdx.x & (kLanesPerRow - 1);
-  const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x / kLanesPerRow);
-  const double ti = row_sum(c, row, c.r, c.v, alpha, sub);
-  double pts = 0.0, ptt = 0.0;
-  if (sub == 0 && row < c.N) {
-    c.t[row] = ti;
-    const double si = c.r[row] - alpha * c.v[row];
-    pts = ti * si;
-    ptt = ti * ti;
-  }
-  const double sts = block_sum<16>(pts, s16);
-  const double stt = block_sum<16>(ptt, s16);
+  struct Sink {
+    const SolveCtx& c;
+    double alpha, pts, ptt;
+    __device__ void operator()(int64_t i, double y) {
+      c.t[i] = y;
+      const double si = c.r[i] - alpha * c.v[i];
+      pts += y * si;
+      ptt += y * y;
+    }
+  } sink{c, alpha, 0.0, 0.0};
+  apply_op<OPK>(c, In<true>{c.r, c.v, alpha}, sink);
+  const double sts = block_sum(sink.pts, s4);
+  const double stt = block_sum(sink.ptt, s4);
   if (threadIdx.x == 0) {
     c.part_t[blockIdx.x] = sts;
-    c.part_t[c.nblocks + blockIdx.x] = stt;
+    c.part_t[kGrid + blockIdx.x] = stt;
   }
 }
 
@@ -251,8 +371,8 @@ __global__ __launch_bounds__(kSpThreads) void spmv_t_kernel(SolveCtx c) {
 __global__ __launch_bounds__(kThreads) void update_xr_kernel(SolveCtx c) {
   __shared__ double s4[4];
   if (c.sc[S_DONE] != 0.0) return;
-  const double ts = sum_parts<4>(c.part_t, c.nblocks, s4);
-  const double tt = sum_parts<4>(c.part_t + c.nblocks, c.nblocks, s4);
+  const double ts = sum_parts(c.part_t, s4);
+  const double tt = sum_parts(c.part_t + kGrid, s4);
   const double omega = (tt > 0.0) ? ts / tt : 0.0;
   const double alpha = c.sc[S_ALPHA];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -261,21 +381,20 @@ __global__ __launch_bounds__(kThreads) void update_xr_kernel(SolveCtx c) {
     c.sc[S_OMEGA] = omega;
     c.sc[S_RHO_PREV] = c.sc[S_RHO];    // update_p replaces S_RHO while its workgroups read this
   }
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   double prr = 0.0, prho = 0.0;
-  if (i < c.N) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < c.N; i += (int64_t)gridDim.x * kThreads) {
     const double si = c.r[i] - alpha * c.v[i];
     c.x[i] = c.x[i] + alpha * c.p[i] + omega * si;
     const double ri = si - omega * c.t[i];
     c.r[i] = ri;
-    prr = ri * ri;
-    prho = c.r0[i] * ri;
+    prr += ri * ri;
+    prho += c.r0[i] * ri;
   }
-  const double srr = block_sum<4>(prr, s4);
-  const double srho = block_sum<4>(prho, s4);
+  const double srr = block_sum(prr, s4);
+  const double srho = block_sum(prho, s4);
   if (threadIdx.x == 0) {
     c.part_x[blockIdx.x] = srr;
-    c.part_x[c.vblocks + blockIdx.x] = srho;
+    c.part_x[kGrid + blockIdx.x] = srho;
   }
 }
 
@@ -287,7 +406,7 @@ __global__ __launch_bounds__(kThreads) void status_kernel(SolveCtx c, int first,
     if (threadIdx.x < S_COUNT) c.status[threadIdx.x] = c.sc[threadIdx.x];
     return;
   }
-  const Next z = next_state<4>(c, first != 0, rtol, s4);
+  const Next z = next_state(c, first != 0, rtol, s4);
   if (threadIdx.x == 0) {
     for (int k = 0; k < S_COUNT; ++k) c.status[k] = c.sc[k];
     record(c.status, z, first != 0);
@@ -298,6 +417,24 @@ __global__ void gather_kernel(const int64_t* __restrict__ perm, const double* __
                               double* __restrict__ dst, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[perm[i]];
+}
+
+// The circle-blocked values of C from its CSR: a 16-lane group per row puts
+// C_ii into dg and the stencil entries at rowptr[i] - i + (column - so_i).
+__global__ __launch_bounds__(kThreads) void form_blocked_kernel(const int64_t* __restrict__ rowptr,
+                                                                const int32_t* __restrict__ cols,
+                                                                const double* __restrict__ val,
+                                                                const int32_t* __restrict__ so, int64_t N,
+                                                                double* __restrict__ vblk, double* __restrict__ dg) {
+  const int sub = threadIdx.x & (kLanes - 1);
+  const int64_t i = (int64_t)blockIdx.x * kRowsPerPass + threadIdx.x / kLanes;
+  if (i >= N) return;
+  const int64_t lo = rowptr[i], hi = rowptr[i + 1];
+  for (int64_t k = lo + sub; k < hi; k += kLanes) {
+    const int32_t col = cols[k];
+    if (col == i) dg[i] = val[k];
+    else vblk[lo - i + (col - so[i])] = val[k];
+  }
 }
 
 // Dense [A | b] of order np >= N for the operator A (C or C^T) in CSR,
@@ -333,8 +470,8 @@ __global__ __launch_bounds__(kThreads) void dense_finish_kernel(
     rr += ri * ri;
     bb += b[i] * b[i];
   }
-  rr = block_sum<4>(rr, s4);
-  bb = block_sum<4>(bb, s4);
+  rr = block_sum(rr, s4);
+  bb = block_sum(bb, s4);
   if (threadIdx.x == 0) {
     out[0] = rr;
     out[1] = bb;
@@ -367,53 +504,165 @@ void ensure_transpose(pdd_cover cover) {
   D.have_transpose = true;
 }
 
+// Circle-blocked structure of C on the device (see the top of this file),
+// when every row holds its diagonal and one circle's stencil in column
+// order; otherwise (rule AVERAGED) blocked_ok stays false.  Caller holds the
+// cover's lock.
+void ensure_blocked(pdd_cover cover) {
+  DeviceCover& D = cover->D;
+  if (D.have_blocked) return;
+  const HostCover& H = cover->H;
+  const int64_t N = H.N();
+  bool ok = H.pairs == nullptr;
+  std::vector<int32_t> so(N, 0);
+  std::vector<int64_t> coff(H.nc + 1, 0);
+  for (int64_t i = 0; ok && i < N; ++i) {
+    const int64_t lo = H.rowptr[i], len = H.rowptr[i + 1] - lo;
+    const int32_t m = H.assigned[i];
+    if (m < 0) {                           // boundary row: C_ii alone
+      ok = len == 1 && H.cols[lo] == i;
+      continue;
+    }
+    const int64_t s0 = H.knot_off[m], s1 = H.knot_off[m + 1];
+    ok = len == s1 - s0 + 1 && (i < s0 || i >= s1);
+    for (int64_t k = lo, j = s0; ok && k < lo + len; ++k) {
+      if (H.cols[k] == i) continue;
+      ok = H.cols[k] == j++;
+    }
+    so[i] = (int32_t)s0;
+    ++coff[m + 1];
+  }
+  if (ok) {
+    for (int32_t m = 0; m < H.nc; ++m) coff[m + 1] += coff[m];
+    std::vector<int32_t> rows(coff[H.nc]);
+    std::vector<int64_t> fill(coff.begin(), coff.end() - 1);
+    for (int64_t i = 0; i < N; ++i)
+      if (H.assigned[i] >= 0) rows[fill[H.assigned[i]]++] = (int32_t)i;
+    D.blk_so.upload(so);
+    D.blk_circ_off.upload(coff);
+    D.blk_circ_rows.upload(rows);
+  }
+  D.blocked_ok = ok;
+  D.have_blocked = true;
+}
+
+// The operator of a solve in the form its kernels read, formed on first use
+// (the structure per cover, the values per system) and synchronised so that
+// solves on other streams see it complete.  Blocked C serves both C and C^T;
+// otherwise C^T needs its CSR pattern and values.
+void prepare_operator(pdd_system sys, bool transpose, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(sys->cover->solve_mu);
+  DeviceCover& D = sys->cover->D;
+  const HostCover& H = sys->cover->H;
+  const int64_t N = H.N(), nnz = H.rowptr.back();
+  ensure_blocked(sys->cover);
+  if (D.blocked_ok) {
+    if (sys->have_vblk) return;
+    sys->vblk.alloc(std::max<int64_t>(1, nnz - N) * sizeof(double));
+    sys->dg.alloc(std::max<int64_t>(1, N) * sizeof(double));
+    if (N > 0)
+      hipLaunchKernelGGL(form_blocked_kernel, dim3((unsigned)((N + kRowsPerPass - 1) / kRowsPerPass)),
+                         dim3(kThreads), 0, st, D.rowptr.ptr<int64_t>(), D.cols.ptr<int32_t>(),
+                         sys->val.ptr<double>(), D.blk_so.ptr<int32_t>(), N, sys->vblk.ptr<double>(),
+                         sys->dg.ptr<double>());
+    PDD_HIP(hipGetLastError());
+    PDD_HIP(hipStreamSynchronize(st));
+    sys->have_vblk = true;
+    return;
+  }
+  if (!transpose) return;
+  ensure_transpose(sys->cover);
+  if (sys->val_t.bytes() == 0) {     // C^T values, formed once per system
+    sys->val_t.alloc(std::max<int64_t>(1, nnz) * sizeof(double));
+    if (nnz > 0)
+      hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st,
+                         D.rt_perm.ptr<int64_t>(), sys->val.ptr<double>(), sys->val_t.ptr<double>(), nnz);
+    PDD_HIP(hipGetLastError());
+    PDD_HIP(hipStreamSynchronize(st));
+  }
+}
+
+// Whether the form a solve needs exists already (the allocation-free entry
+// point cannot form it).  Caller holds the cover's lock.
+bool operator_ready(pdd_system sys, bool transpose) {
+  const DeviceCover& D = sys->cover->D;
+  if (!D.have_blocked) return false;
+  if (D.blocked_ok) return sys->have_vblk;
+  return !transpose || (D.have_transpose && sys->val_t.bytes() > 0);
+}
+
 namespace {
 
 // Doubles of the BiCGStab work area for N unknowns: r, r0, p, v, t, the
-// partial sums of the sparse and vector kernels, the scalars and the host's
-// record.
-int64_t work_doubles(int64_t N) {
-  const int64_t nb = (N + kRowsPerBlock - 1) / kRowsPerBlock, vb = (N + kThreads - 1) / kThreads;
-  return 5 * N + 5 * nb + 2 * vb + 2 * S_COUNT;
-}
+// partial sums of the kernels, the scalars and the host's record.
+int64_t work_doubles(int64_t N) { return 5 * N + 7 * (int64_t)kGrid + 2 * S_COUNT; }
 
-// Points the context at C (or C^T, whose pattern and values must exist) and
+// Points the context at the operator (prepared by prepare_operator) and
 // carves the work area w (work_doubles(N) doubles) into its vectors.
 void bind(SolveCtx& c, pdd_system sys, bool transpose, double* u, double* w) {
   const DeviceCover& D = sys->cover->D;
   const int64_t N = sys->cover->H.N();
-  c.rowptr = transpose ? D.rt_rowptr.ptr<int64_t>() : D.rowptr.ptr<int64_t>();
-  c.cols = transpose ? D.rt_cols.ptr<int32_t>() : D.cols.ptr<int32_t>();
-  c.val = transpose ? sys->val_t.ptr<double>() : sys->val.ptr<double>();
+  if (D.blocked_ok) {
+    c.kind = transpose ? OP_CIRCLES : OP_ROWS;
+    c.rowptr = D.rowptr.ptr<int64_t>();
+    c.vblk = sys->vblk.ptr<double>();
+    c.dg = sys->dg.ptr<double>();
+    c.so = D.blk_so.ptr<int32_t>();
+    c.knot_off = D.knot_off.ptr<int64_t>();
+    c.circ_off = D.blk_circ_off.ptr<int64_t>();
+    c.circ_rows = D.blk_circ_rows.ptr<int32_t>();
+    c.nc = sys->cover->H.nc;
+  } else {
+    c.kind = OP_CSR;
+    c.rowptr = transpose ? D.rt_rowptr.ptr<int64_t>() : D.rowptr.ptr<int64_t>();
+    c.cols = transpose ? D.rt_cols.ptr<int32_t>() : D.cols.ptr<int32_t>();
+    c.val = transpose ? sys->val_t.ptr<double>() : sys->val.ptr<double>();
+  }
   c.N = N;
   c.x = u;
-  c.nblocks = (int)((N + kRowsPerBlock - 1) / kRowsPerBlock);
-  c.vblocks = (int)((N + kThreads - 1) / kThreads);
   c.r = w;
   c.r0 = c.r + N;
   c.p = c.r0 + N;
   c.v = c.p + N;
   c.t = c.v + N;
   c.part_i = c.t + N;
-  c.part_v = c.part_i + 2 * (int64_t)c.nblocks;
-  c.part_t = c.part_v + c.nblocks;
-  c.part_x = c.part_t + 2 * (int64_t)c.nblocks;
-  c.sc = c.part_x + 2 * (int64_t)c.vblocks;
+  c.part_v = c.part_i + 2 * kGrid;
+  c.part_t = c.part_v + kGrid;
+  c.part_x = c.part_t + 2 * kGrid;
+  c.sc = c.part_x + 2 * kGrid;
   c.status = c.sc + S_COUNT;
+}
+
+template <int OPK>
+void launch_iterations(const SolveCtx& c, hipStream_t st, int first, int count, double rtol) {
+  for (int k = 0; k < count; ++k) {
+    hipLaunchKernelGGL(update_p_kernel, dim3(kGrid), dim3(kThreads), 0, st, c, k == 0 ? first : 0, rtol);
+    hipLaunchKernelGGL(spmv_v_kernel<OPK>, dim3(kGrid), dim3(kThreads), 0, st, c);
+    hipLaunchKernelGGL(spmv_t_kernel<OPK>, dim3(kGrid), dim3(kThreads), 0, st, c);
+    hipLaunchKernelGGL(update_xr_kernel, dim3(kGrid), dim3(kThreads), 0, st, c);
+  }
+}
+
+// r = b - A x (x = 0, or the guess in x), r0 = r.
+void launch_init(const SolveCtx& c, const double* b, bool guess, hipStream_t st) {
+  if (guess) {
+    if (c.kind == OP_CSR) hipLaunchKernelGGL(guess_product_kernel<OP_CSR>, dim3(kGrid), dim3(kThreads), 0, st, c);
+    else if (c.kind == OP_ROWS) hipLaunchKernelGGL(guess_product_kernel<OP_ROWS>, dim3(kGrid), dim3(kThreads), 0, st, c);
+    else hipLaunchKernelGGL(guess_product_kernel<OP_CIRCLES>, dim3(kGrid), dim3(kThreads), 0, st, c);
+  }
+  hipLaunchKernelGGL(init_kernel, dim3(kGrid), dim3(kThreads), 0, st, c, b, guess ? 1 : 0);
+  PDD_HIP(hipGetLastError());
 }
 
 // Enqueues the next batch of at most kItersPerSync iterations after `enq`
 // enqueued ones, then the status kernel that writes the host's record to
 // c.status; returns the new count.
 int enqueue_batch(const SolveCtx& c, hipStream_t st, int enq, int max_iter, double rtol) {
-  const dim3 rb(c.nblocks), vb(c.vblocks);
   const int batch = std::min(kItersPerSync, max_iter - enq);
-  for (int k = 0; k < batch; ++k) {
-    hipLaunchKernelGGL(update_p_kernel, vb, dim3(kThreads), 0, st, c, enq + k == 0 ? 1 : 0, rtol);
-    hipLaunchKernelGGL(spmv_v_kernel, rb, dim3(kSpThreads), 0, st, c);
-    hipLaunchKernelGGL(spmv_t_kernel, rb, dim3(kSpThreads), 0, st, c);
-    hipLaunchKernelGGL(update_xr_kernel, vb, dim3(kThreads), 0, st, c);
-  }
+  const int first = enq == 0 ? 1 : 0;
+  if (c.kind == OP_CSR) launch_iterations<OP_CSR>(c, st, first, batch, rtol);
+  else if (c.kind == OP_ROWS) launch_iterations<OP_ROWS>(c, st, first, batch, rtol);
+  else launch_iterations<OP_CIRCLES>(c, st, first, batch, rtol);
   enq += batch;
   hipLaunchKernelGGL(status_kernel, dim3(1), dim3(kThreads), 0, st, c, enq == 0 ? 1 : 0, rtol);
   PDD_HIP(hipGetLastError());
@@ -449,6 +698,18 @@ pdd_status direct_impl(pdd_system sys, const double* b, double* u, bool transpos
   if (N == 0) {
     if (info) *info = pdd_solve_info{0, 1, 0.0};
     return PDD_OK;
+  }
+  if (transpose) {                   // the CSR of C^T (small: N <= 4096)
+    std::lock_guard<std::mutex> lk(sys->cover->solve_mu);
+    ensure_transpose(sys->cover);
+    const int64_t nnz = sys->cover->H.rowptr.back();
+    if (sys->val_t.bytes() == 0) {
+      sys->val_t.alloc(std::max<int64_t>(1, nnz) * sizeof(double));
+      hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st,
+                         D.rt_perm.ptr<int64_t>(), sys->val.ptr<double>(), sys->val_t.ptr<double>(), nnz);
+      PDD_HIP(hipGetLastError());
+      PDD_HIP(hipStreamSynchronize(st));
+    }
   }
   const int64_t* rowptr = transpose ? D.rt_rowptr.ptr<int64_t>() : D.rowptr.ptr<int64_t>();
   const int32_t* cols = transpose ? D.rt_cols.ptr<int32_t>() : D.cols.ptr<int32_t>();
@@ -517,23 +778,12 @@ pdd_status finish(const double* host, pdd_solve_info* info, const char* who) {
 pdd_status solve_impl(pdd_system sys, const double* rhs, double* u, int32_t transpose,
                       const pdd_solve_opts* opts, hipStream_t st, pdd_solve_info* info) {
   const HostCover& H = sys->cover->H;
-  DeviceCover& D = sys->cover->D;
-  const int64_t N = H.N(), nnz = H.rowptr.back();
+  const int64_t N = H.N();
   const SolveParams P = params(opts);
-  if (transpose) {
-    std::lock_guard<std::mutex> lk(sys->cover->solve_mu);
-    ensure_transpose(sys->cover);
-    if (sys->val_t.bytes() == 0) {     // C^T values, formed once per system
-      sys->val_t.alloc(nnz * sizeof(double));
-      hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st,
-                         D.rt_perm.ptr<int64_t>(), sys->val.ptr<double>(), sys->val_t.ptr<double>(), nnz);
-      PDD_HIP(hipGetLastError());
-      PDD_HIP(hipStreamSynchronize(st));   // complete before another stream's solve can see it
-    }
-  }
   const double* b = rhs ? rhs : sys->b.ptr<double>();
   if (P.method == PDD_SOLVE_DIRECT_SMALL) return direct_impl(sys, b, u, transpose != 0, st, info);
   if (P.method != PDD_SOLVE_BICGSTAB) return fail(PDD_EINVAL, "pdd_solve_G: unknown method");
+  prepare_operator(sys, transpose != 0, st);
   const size_t wbytes = sizeof(double) * (size_t)work_doubles(N);
   // scratch from the cover's pool, returned when this call ends
   int dev = 0;
@@ -566,7 +816,7 @@ pdd_status solve_impl(pdd_system sys, const double* rhs, double* u, int32_t tran
   if (scr->work.bytes() < wbytes) scr->work.alloc(wbytes);
   SolveCtx c{};
   bind(c, sys, transpose != 0, u, scr->work.ptr<double>());
-  hipLaunchKernelGGL(init_kernel, dim3(c.nblocks), dim3(kSpThreads), 0, st, c, b, P.guess ? 1 : 0);
+  launch_init(c, b, P.guess, st);
   // Batches of kItersPerSync iterations; the convergence record of batch k is
   // copied to pinned host memory and read while batch k + 1 already runs (the
   // iteration kernels return at once after convergence, so a batch enqueued
@@ -645,11 +895,11 @@ pdd_status solve_noalloc_impl(pdd_system sys, const double* rhs, double* u, int3
     return fail(PDD_EINVAL, "pdd_solve_G_noalloc: " + std::to_string(N) +
                                 " unknowns need " + std::to_string(work_doubles(N)) +
                                 " doubles of work area, more than its " + std::to_string(kScratchDoubles));
-  if (transpose) {
+  {
     std::lock_guard<std::mutex> lk(sys->cover->solve_mu);
-    if (!sys->cover->D.have_transpose || sys->val_t.bytes() == 0)
-      return fail(PDD_EINVAL, "pdd_solve_G_noalloc: C^T has not been formed for this system "
-                              "(one pdd_solve_G call with transpose = 1 forms it)");
+    if (!operator_ready(sys, transpose != 0))
+      return fail(PDD_EINVAL, "pdd_solve_G_noalloc: the solve form of this system's operator has not "
+                              "been built (one pdd_solve_G call in the same direction builds it)");
   }
   int dev = 0;
   PDD_HIP(hipGetDevice(&dev));
@@ -657,7 +907,7 @@ pdd_status solve_noalloc_impl(pdd_system sys, const double* rhs, double* u, int3
   SolveCtx c{};
   bind(c, sys, transpose != 0, u, scratch_ptr(dev));
   const double* b = rhs ? rhs : sys->b.ptr<double>();
-  hipLaunchKernelGGL(init_kernel, dim3(c.nblocks), dim3(kSpThreads), 0, st, c, b, P.guess ? 1 : 0);
+  launch_init(c, b, P.guess, st);
   // one stream synchronisation per batch of kItersPerSync iterations
   double host[S_COUNT];
   int enq = 0;

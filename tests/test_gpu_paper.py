@@ -62,8 +62,12 @@ def test_section4_assembly_parity_sampled():
             wrap.add(m)
     circles |= set(int(m) for m in rng.choice(sorted(wrap), size=min(4, len(wrap)), replace=False))
     _say(f"[gpu] checking floating circles {sorted(circles)}")
-    frac = sampled_parity(prob, ref_cover, cfg["mc"], val, b, sorted(circles), pick_mc_knots(ref_cover, rng, 3))
-    assert frac > 0.6
+    frac = sampled_parity(prob, ref_cover, cfg["mc"], val, b, sorted(circles), pick_mc_knots(ref_cover, rng, 32))
+    _say(f"[gpu] Section 4 workload: MC r_i within 1e-9 on {frac:.3f} of 32 knots")
+    # every entry is within 3 standard errors; a knot's r_i misses 1e-9 only
+    # when one of its paths takes a different exit (last-ulp differences of
+    # the host's and the device's libm over about 1350 steps per path)
+    assert frac >= 0.75
 
 
 def test_section4_solution_error():

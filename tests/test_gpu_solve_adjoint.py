@@ -189,3 +189,37 @@ def test_system_csr_matches_pattern_and_values(rule):
     assert np.array_equal(rowptr, rp_h) and np.array_equal(cols, cols_h)
     val2, b2, se2, _ = (t.cpu().numpy() for t in sysm.copy())
     assert np.array_equal(val, val2) and np.array_equal(b, b2) and np.array_equal(se, se2)
+
+
+@pytest.mark.parametrize("chunked", [False, True])
+def test_adjoint_uneven_buckets_matches_oracle(chunked):
+    """The adjoint on the four collocation sizes of the uneven-resolution
+    family (n = 576, 1024, 2304, 4096; the two largest need the wide panel
+    classes and the largest adjoint LDS layout), with the factors kept and
+    with them recomputed chunk by chunk, against the oracle's adjoint."""
+    pdd, torch = _gpu()
+    from helpers_parity import check_circle_gradient, gradient_terms
+    cfg = workloads.mixed_small()
+    prob = cfg["problem"]
+    _say(f"[gpu] adjoint, uneven buckets, chunked={chunked}")
+    cv = pdd.Cover(prob["domain"], cfg["cover"])
+    sysm = pdd.System(cv, prob, cfg["mc"], keep_factors=True)
+    if chunked:
+        budget = sysm.stats.factor_bytes // 3
+        sysm = pdd.System(cv, prob, cfg["mc"], keep_factors=True, hbm_budget_bytes=int(budget))
+        assert sysm.stats.recompute == 1
+    u, _ = sysm.solve(rtol=1e-13)
+    rng = np.random.default_rng(17)
+    lam = torch.tensor(rng.standard_normal(cv.N), device="cuda")
+    g = {k: v.cpu().numpy() for k, v in sysm.backward(u, lam).items()}
+    ref_cover = geometry.build_cover(prob["domain"], cfg["cover"])
+    xy, off, ids = cv.nodes()
+    u_h, lam_h = u.cpu().numpy(), lam.cpu().numpy()
+    sizes = []
+    for f, m in enumerate(ids):
+        grid = spectral.local_grid(ref_cover.Nr[m], ref_cover.Ntheta[m])
+        samples = spectral.node_samples(prob, grid, *ref_cover.centres[m], ref_cover.radii[m])
+        ref, slack = gradient_terms(ref_cover, m, samples, u_h, lam_h)
+        check_circle_gradient(ref, slack, {k: g[k][off[f]:off[f + 1]] for k in ref})
+        sizes.append(int(off[f + 1] - off[f]))
+    assert sorted(sizes) == [576, 1024, 2304, 4096]
