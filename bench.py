@@ -42,9 +42,12 @@ PEAK_HBM_GBS = 8000.0
 #   per Euler step: two normals by Box-Muller (log, sqrt, sin+cos, 3 mul) = 54;
 #     the update X + b h + sigma sqrt(h) N (2 x 3 FMA) = 12; the circle test
 #     (2 sub, 1 mul, 1 FMA, 1 cmp) = 6; the box test (4 cmp) = 4       -> 76
-#     with variable coefficients add the fields at X (CONST: 0), the Cholesky
-#     factor of a (2 sqrt, 1 div, 1 FMA = 5), Y e^{c h} (exp + mul = 21) and
-#     Z + f Y h (2 FMA = 4)
+#     with variable coefficients add the fields at X (per SINSUM term: the
+#     phase 2 pi (k . x) + phi (2 FMA = 4), sin 20, the product-sum 2 -> 26;
+#     a derived source f = -(L u + c u) adds per term of u its sin and cos 30
+#     and the six jet sums (6 FMA = 12) -> 46, plus the combination 7 FMA = 14),
+#     the Cholesky factor of a (2 sqrt, 1 div, 1 FMA = 5), Y e^{c h} (exp +
+#     mul = 21) and Z + f Y h (2 FMA = 4)
 #   per exit: segment/circle crossing (about 16 FMA/mul + sqrt + div = 20),
 #     exit point and weight (2 FMA = 4), the Z payoff (1 add)            -> 25
 #   per exit on Gamma_m: the angle (atan2 30 + unwrap 4), then per arc knot
@@ -101,10 +104,28 @@ def bicgstab_bytes_per_iter(N, nnz):
     return 16.0 * nnz + (32.0 + 24.0 + 24.0 + 64.0) * N
 
 
-def mc_ops(stats, arc_mean, variable):
+def field_ops_per_point(prob):
+    """FP64 operations of evaluating the coefficient fields of eq. 1 at one
+    path point (zero for constant coefficients; see the table above)."""
+    names = ("axx", "axy", "ayy", "bx", "by", "c")
+    if all(prob[k]["kind"] == "const" for k in names) and prob["f"]["kind"] == "const":
+        return 0
+    ops = 0
+    for k in names:
+        if prob[k]["kind"] == "sinsum":
+            ops += 26 * len(prob[k]["amp"])
+    f = prob["f"]
+    if f["kind"] == "sinsum":
+        ops += 26 * len(f["amp"])
+    elif f["kind"] == "derived_f" and f["u"]["kind"] == "sinsum":
+        ops += 46 * len(f["u"]["amp"]) + 14
+    return ops + MC_OPS_STEP_VARIABLE_EXTRA
+
+
+def mc_ops(stats, arc_mean, field_ops):
     """Algorithmic FP64 operations of one Monte Carlo phase (see the table at
-    the top of this file)."""
-    per_step = MC_OPS_STEP_CONST + (MC_OPS_STEP_VARIABLE_EXTRA if variable else 0)
+    the top of this file); field_ops from field_ops_per_point."""
+    per_step = MC_OPS_STEP_CONST + field_ops
     gam = float(stats.gamma_exits)
     bnd = float(stats.paths) - gam
     return (per_step * float(stats.path_steps) + MC_OPS_EXIT * float(stats.paths)
@@ -186,9 +207,15 @@ def run_gpu(cfg, steps, warmup, with_adjoint=True, budget=0, plan="autotuned", u
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    results = [step() for _ in range(steps)]
+    results, marks = [], []
+    for _ in range(steps):
+        results.append(step())
+        marks.append(time.perf_counter())      # each step ends in a host synchronisation
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
+    t1 = time.perf_counter()
+    dt = (t1 - t0) / steps
+    for r, a, b in zip(results, [t0] + marks[:-1], marks):
+        r["wall_ms"] = (b - a) * 1e3
     for r in results:
         if "events" in r:
             e = r.pop("events")
@@ -392,7 +419,7 @@ def cpu_baseline_subprocess(workload, frac):
 
 # ------------------------------------------------------------------- report
 
-def phase_rooflines(cover, cfg, results, with_adj, variable):
+def phase_rooflines(cover, cfg, results, with_adj):
     """One roofline entry per phase, each from times measured in this run."""
     import numpy as np
     st = [r["stats"] for r in results]
@@ -411,7 +438,7 @@ def phase_rooflines(cover, cfg, results, with_adj, variable):
         _, rc, asg, own = cover.knots()
         cnt = np.bincount(own, minlength=int(info.n_circles))
         arc_mean = float(np.mean(cnt[asg[rc == 1]]))
-        ops = mc_ops(st[-1], arc_mean, variable)
+        ops = mc_ops(st[-1], arc_mean, field_ops_per_point(cfg["problem"]))
         tf = ops / (ms_mc * 1e-3) / 1e12
         out["mc"] = {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": tf / PEAK_FP64_VECTOR_TFLOPS, "ms": ms_mc,
@@ -504,8 +531,7 @@ def main():
     ms_asm = med([s.ms_total for s in st])
     ms_spec = med([s.ms_build + s.ms_lu + s.ms_solve + s.ms_eval for s in st])
     path_steps = st[-1].path_steps
-    variable = args.workload == "config2"
-    roof = phase_rooflines(cover, cfg, results, with_adj, variable)
+    roof = phase_rooflines(cover, cfg, results, with_adj)
     # the headline roofline: the phase that takes the most time per step
     dom = max(roof, key=lambda k: roof[k]["ms"])
     kernels = {
@@ -545,6 +571,7 @@ def main():
         "phase_ms": {k: med([getattr(s, "ms_" + k) for s in st])
                      for k in ("sample", "build", "lu", "eval", "mc", "total")},
         "build_cover_s": t_cover,
+        "step_wall_ms": [round(r["wall_ms"], 1) for r in results],
         "schedule": {"plan": args.plan, "mixed_buckets": bool(st[-1].mixed_buckets),
                      "grid_cap": int(st[-1].grid_cap), "groups": int(st[-1].n_groups),
                      "graph_replays": int(st[-1].graph_replays), "lu_launches": int(st[-1].n_launch_spectral)},

@@ -62,6 +62,19 @@ typedef struct pdd_system_s* pdd_system;
 
 const char* pdd_last_error(void);
 
+/*
+ * Device memory.  Blocks of 4 MiB and more that the library releases (when a
+ * system is destroyed, or at the end of a call that used work areas) are kept
+ * in a per-device cache and reused by later calls of the same sizes, instead
+ * of going back to the HIP runtime: repeated assemblies of one problem then
+ * allocate nothing new.  A block enters the cache only after its device has
+ * been synchronised; the cache holds at most half of the device's memory; an
+ * allocation that fails empties it and tries again.
+ * pdd_release_cached_memory frees every cached block (all devices) and
+ * returns the number of bytes freed.  No compute happens here.
+ */
+int64_t pdd_release_cached_memory(void);
+
 /* ---------------------------------------------------------------- problem */
 
 enum { PDD_DOMAIN_BOX = 0, PDD_DOMAIN_DISK = 1 };

@@ -26,7 +26,7 @@ EXPORTED = [
     "pdd_cover_pattern", "pdd_cover_nodes", "pdd_destroy_cover", "pdd_assemble_G",
     "pdd_system_copy", "pdd_system_get_stats", "pdd_solve_G", "pdd_assemble_G_backward",
     "pdd_destroy_system", "pdd_ras_build", "pdd_ras_get_parts", "pdd_ras_apply", "pdd_destroy_ras",
-    "pdd_solve_gmres", "pdd_solve_G_noalloc", "pdd_system_csr",
+    "pdd_solve_gmres", "pdd_solve_G_noalloc", "pdd_system_csr", "pdd_release_cached_memory",
 ]
 
 
@@ -129,6 +129,8 @@ def lib():
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     dp = C.POINTER(C.c_double)
     L.pdd_last_error.restype = C.c_char_p
+    L.pdd_release_cached_memory.argtypes = []
+    L.pdd_release_cached_memory.restype = C.c_int64
     L.pdd_eval_field.argtypes = [C.POINTER(Problem), i32, vp, i64, vp, vp]
     L.pdd_build_cover.argtypes = [C.POINTER(Domain), i32, dp, dp, C.POINTER(i32), C.POINTER(i32),
                                   C.POINTER(i32), C.POINTER(CoverOpts), C.POINTER(vp)]
@@ -155,10 +157,16 @@ def lib():
     L.pdd_destroy_ras.restype = None
     L.pdd_solve_gmres.argtypes = [vp, vp, vp, vp, C.POINTER(GmresOpts), vp, C.POINTER(SolveInfo)]
     for name in EXPORTED:
-        if name not in ("pdd_last_error", "pdd_destroy_cover", "pdd_destroy_system", "pdd_destroy_ras"):
+        if name not in ("pdd_last_error", "pdd_destroy_cover", "pdd_destroy_system", "pdd_destroy_ras",
+                        "pdd_release_cached_memory"):
             getattr(L, name).restype = C.c_int32
     _lib = L
     return L
+
+
+def release_cached_memory():
+    """Frees the library's cache of released device blocks; returns bytes."""
+    return int(lib().pdd_release_cached_memory())
 
 
 def _check(code, what=""):

@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "cover.h"
@@ -22,6 +24,108 @@ thread_local std::string g_last_error;
 pdd_status fail(pdd_status code, const std::string& msg) {
   g_last_error = msg;
   return code;
+}
+
+// ------------------------------------------------------ device block cache
+
+namespace {
+
+struct BlockCache {
+  std::mutex mu;
+  std::unordered_multimap<size_t, void*> free_blocks[64];   // per device, by rounded size
+  size_t cached[64] = {};
+  size_t cap[64] = {};
+};
+
+BlockCache& block_cache() {
+  static BlockCache* c = new BlockCache();                   // lives until the process ends
+  return *c;
+}
+
+size_t round_block(size_t bytes) {
+  const size_t g = size_t(2) << 20;
+  return (bytes + g - 1) / g * g;
+}
+
+// Frees the cached blocks of device d (caller holds the lock, d current).
+size_t drop_cached(BlockCache& c, int d) {
+  size_t n = 0;
+  for (auto& kv : c.free_blocks[d]) {
+    (void)hipFree(kv.second);
+    n += kv.first;
+  }
+  c.free_blocks[d].clear();
+  c.cached[d] = 0;
+  return n;
+}
+
+}  // namespace
+
+void* device_alloc(size_t bytes, int& device) {
+  PDD_HIP(hipGetDevice(&device));
+  const bool big = bytes >= kCacheMinBytes && device >= 0 && device < 64;
+  const size_t size = big ? round_block(bytes) : bytes;
+  BlockCache& c = block_cache();
+  if (big) {
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.free_blocks[device].find(size);
+    if (it != c.free_blocks[device].end()) {
+      void* p = it->second;
+      c.free_blocks[device].erase(it);
+      c.cached[device] -= size;
+      return p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, size);
+  if (e == hipErrorOutOfMemory && big) {       // give the cache back and try once more
+    (void)hipGetLastError();
+    {
+      std::lock_guard<std::mutex> lk(c.mu);
+      drop_cached(c, device);
+    }
+    e = hipMalloc(&p, size);
+  }
+  if (e != hipSuccess) throw HipError(e, "hipMalloc(" + std::to_string(bytes) + " bytes)");
+  return p;
+}
+
+void device_free(void* p, size_t bytes, int device) {
+  int cur = -1;
+  const bool big = bytes >= kCacheMinBytes && device >= 0 && device < 64 &&
+                   hipGetDevice(&cur) == hipSuccess && cur == device;
+  if (!big) {
+    (void)hipFree(p);
+    return;
+  }
+  const size_t size = round_block(bytes);
+  BlockCache& c = block_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  if (c.cap[device] == 0) {
+    size_t fr = 0, total = 0;
+    c.cap[device] = hipMemGetInfo(&fr, &total) == hipSuccess ? total / 2 : (size_t(16) << 30);
+  }
+  if (c.cached[device] + size > c.cap[device] || hipDeviceSynchronize() != hipSuccess) {
+    (void)hipFree(p);
+    return;
+  }
+  c.free_blocks[device].emplace(size, p);
+  c.cached[device] += size;
+}
+
+size_t device_cache_release() {
+  BlockCache& c = block_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return 0;
+  size_t n = 0;
+  for (int d = 0; d < 64; ++d) {
+    if (c.free_blocks[d].empty()) continue;
+    if (hipSetDevice(d) != hipSuccess) continue;
+    n += drop_cached(c, d);
+  }
+  (void)hipSetDevice(cur);
+  return n;
 }
 
 // ------------------------------------------------------------ device tables
@@ -206,6 +310,8 @@ using namespace pdd;
 // ------------------------------------------------------------------- C ABI
 
 extern "C" {
+
+int64_t pdd_release_cached_memory(void) { return (int64_t)pdd::device_cache_release(); }
 
 const char* pdd_last_error(void) { return g_last_error.c_str(); }
 

@@ -30,6 +30,19 @@ struct HipError : std::runtime_error {
     if (e_ != hipSuccess) throw ::pdd::HipError(e_, #call);             \
   } while (0)
 
+// Device memory of the library.  Blocks of at least kCacheMinBytes return to a
+// per-device cache when released and are handed out again for the same
+// rounded size, so repeated assemblies of one problem (factors, values, work
+// areas: tens of GB) do not go through hipMalloc / hipFree every time -- the
+// runtime's release of such blocks slows down by orders of magnitude after a
+// few cycles.  A released block is cached only after its device is
+// synchronised (the guarantee hipFree gives), the cache holds at most half of
+// the device's memory, and a failed allocation empties it and retries.
+constexpr size_t kCacheMinBytes = size_t(4) << 20;
+void* device_alloc(size_t bytes, int& device);          // throws HipError
+void device_free(void* p, size_t bytes, int device);
+size_t device_cache_release();                          // frees every cached block; returns bytes
+
 // Owning device allocation.
 class DevBuf {
  public:
@@ -38,18 +51,14 @@ class DevBuf {
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p_) (void)hipFree(p_);
+    if (p_) device_free(p_, bytes_, dev_);
     p_ = nullptr;
     bytes_ = 0;
   }
   void alloc(size_t bytes) {
     release();
     if (bytes == 0) return;
-    hipError_t e = hipMalloc(&p_, bytes);
-    if (e != hipSuccess) {
-      p_ = nullptr;
-      throw HipError(e, "hipMalloc(" + std::to_string(bytes) + " bytes)");
-    }
+    p_ = device_alloc(bytes, dev_);
     bytes_ = bytes;
   }
   template <class T>
@@ -64,6 +73,7 @@ class DevBuf {
  private:
   void* p_ = nullptr;
   size_t bytes_ = 0;
+  int dev_ = -1;
 };
 
 struct BucketData {

@@ -222,3 +222,4 @@ def test_scale_workload_bench_configuration():
     assert np.linalg.norm(C.T @ lam.cpu().numpy() - g) <= 1e-11 * np.linalg.norm(g)
     _say(f"[gpu] scale (bench configuration): BiCGStab {info.iterations}/{info_t.iterations}, "
          f"MC r_i within 1e-9: {frac:.2f}")
+
