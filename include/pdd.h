@@ -244,7 +244,8 @@ enum { PDD_PLAN_BATCHED = 0, PDD_PLAN_PER_CIRCLE = 1, PDD_PLAN_AUTOTUNED = 2 };
  * one sequence of persistent LU launches over all its matrices whatever their
  * size (per 128-column step: panel, U-row and trailing-update launches; then
  * the back substitution), and one evaluation launch per bucket.
- *   PDD_PLAN_BATCHED    groups as given by mixed_buckets / grid_cap / use_graph;
+ *   PDD_PLAN_BATCHED    groups as given by mixed_buckets / grid_cap / use_graph /
+ *                       no_lookahead;
  *   PDD_PLAN_PER_CIRCLE the plain loop: one circle per group;
  *   PDD_PLAN_AUTOTUNED  the library times the candidate schedules on a sample
  *                       of each bucket on first use with a cover and keeps the
@@ -270,7 +271,10 @@ typedef struct pdd_assemble_opts {
                               graph and replay it for groups of the same shape; only
                               when such groups follow (transient factor buffers and
                               more than one group), otherwise launched directly      */
-  int32_t reserved;
+  int32_t no_lookahead;    /* 0: the U-row tiles right of the next panel run on a
+                              second stream beside the next step's panel
+                              (look-ahead); 1: every LU launch in order on one
+                              stream                                                  */
 } pdd_assemble_opts;
 
 /*
@@ -331,6 +335,8 @@ typedef struct pdd_system_stats {
   int32_t graph_replays;   /* LU launch sequences replayed from a captured graph     */
   float ms_autotune;       /* time spent tuning in this call (0 when cached)         */
   int64_t gamma_exits;     /* Monte Carlo paths that exited on the interface Gamma_m  */
+  int32_t lu_lookahead;    /* 1: the LU launches used the look-ahead stream           */
+  int32_t reserved;
 } pdd_system_stats;
 
 pdd_status pdd_system_get_stats(pdd_system sys, pdd_system_stats* out);

@@ -79,7 +79,7 @@ class McOpts(C.Structure):
 class AssembleOpts(C.Structure):
     _fields_ = [("plan", C.c_int32), ("keep_factors", C.c_int32), ("hbm_budget_bytes", C.c_int64),
                 ("mixed_buckets", C.c_int32), ("grid_cap", C.c_int32), ("use_graph", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("no_lookahead", C.c_int32)]
 
 
 PLANS = {"batched": 0, "per_circle": 1, "autotuned": 2}
@@ -93,7 +93,8 @@ class SystemStats(C.Structure):
                                          "ms_mc", "ms_total")] + \
                [("factor_bytes", C.c_int64), ("recompute", C.c_int32), ("n_groups", C.c_int32),
                 ("mixed_buckets", C.c_int32), ("grid_cap", C.c_int32), ("graph_replays", C.c_int32),
-                ("ms_autotune", C.c_float), ("gamma_exits", C.c_int64)]
+                ("ms_autotune", C.c_float), ("gamma_exits", C.c_int64), ("lu_lookahead", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -329,7 +330,8 @@ class System:
     """Assembled C (CSR on the cover's pattern), r and standard errors, on the device."""
 
     def __init__(self, cover, problem, mc, samples=None, keep_factors=False, plan="batched",
-                 hbm_budget_bytes=0, mixed_buckets=True, grid_cap=0, use_graph=False, stream=None):
+                 hbm_budget_bytes=0, mixed_buckets=True, grid_cap=0, use_graph=False, lookahead=True,
+                 stream=None):
         import torch
         L = lib()
         self.cover = cover
@@ -343,7 +345,8 @@ class System:
             keep.append(hpc)
             mo.h_per_circle = _dptr(hpc)
         ao = AssembleOpts(PLANS[plan], int(bool(keep_factors)), int(hbm_budget_bytes),
-                          int(bool(mixed_buckets)), int(grid_cap), int(bool(use_graph)), 0)
+                          int(bool(mixed_buckets)), int(grid_cap), int(bool(use_graph)),
+                          int(not lookahead))
         sm = None
         if samples is not None:
             for k, v in samples.items():

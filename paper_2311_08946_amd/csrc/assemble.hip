@@ -189,6 +189,7 @@ struct Schedule {
   bool mixed = true;
   int grid_cap = 0;          // multiple of the compute units; 0 = one workgroup per tile
   bool graph = false;
+  bool lookahead = true;     // U-row tiles of step s beside the panel of step s + 1
 };
 
 // Groups of circles whose factors are resident together.
@@ -335,7 +336,7 @@ struct GroupRun {
         if (pk.counts == counts && pk.fs == fs) seen = pk.plan;
     e = hooks ? hooks->begin(PH_LU) : -1;
     if (seen) {
-      launches += seen->launch(st, grid_cap());
+      launches += seen->launch(st, grid_cap(), sched.lookahead);
     } else if (!same) {
       std::vector<LuItem> its;
       char* w = static_cast<char*>(work.buf.ptr<void>());
@@ -368,20 +369,20 @@ struct GroupRun {
       if (sched.graph) {
         if (!cap_stream) PDD_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
         PDD_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
-        last_plan->launch(cap_stream, grid_cap());
+        last_plan->launch(cap_stream, grid_cap(), sched.lookahead);
         PDD_HIP(hipStreamEndCapture(cap_stream, &graph));
         PDD_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
         PDD_HIP(hipGraphLaunch(exec, st));
         launches += 1;
       } else {
-        launches += last_plan->launch(st, grid_cap());
+        launches += last_plan->launch(st, grid_cap(), sched.lookahead);
       }
     } else if (exec) {
       PDD_HIP(hipGraphLaunch(exec, st));
       ++replays;
       launches += 1;
     } else {
-      launches += last_plan->launch(st, grid_cap());
+      launches += last_plan->launch(st, grid_cap(), sched.lookahead);
     }
     if (hooks) hooks->end(e);
     if (val) {
@@ -412,7 +413,7 @@ struct GroupRun {
 // median kept.  With one bucket the mixed and per-bucket groupings are the
 // same schedule and only the grid caps are compared.
 void autotune(const DeviceCover& D, const NodeSamples& S, int64_t budget, hipStream_t st, bool& mixed,
-              int& cap) {
+              int& cap, bool& lookahead) {
   constexpr int kSampleMax = 2048;
   constexpr int64_t kSampleBytes = (int64_t)8 << 30;
   std::vector<std::vector<Slice>> sample_mixed(1), sample_sep;
@@ -443,10 +444,12 @@ void autotune(const DeviceCover& D, const NodeSamples& S, int64_t budget, hipStr
   const int caps[3] = {0, 1, 2};
   const bool one_bucket = sample_sep.size() <= 1;
   for (int mx = 1; mx >= (one_bucket ? 1 : 0); --mx)
+    for (int la = 1; la >= 0; --la)
     for (int ci = 0; ci < 3; ++ci) {
       Schedule sc;
       sc.mixed = mx != 0;
       sc.grid_cap = caps[ci];
+      sc.lookahead = la != 0;
       const auto& groups = sc.mixed ? sample_mixed : sample_sep;
       GroupRun run(D, st, sc);
       auto once = [&]() {
@@ -472,6 +475,7 @@ void autotune(const DeviceCover& D, const NodeSamples& S, int64_t budget, hipStr
         best = ms[1];
         mixed = sc.mixed;
         cap = sc.grid_cap;
+        lookahead = sc.lookahead;
       }
     }
   (void)budget;
@@ -591,16 +595,18 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
   sched.mixed = opts ? opts->mixed_buckets != 0 : true;
   sched.grid_cap = opts ? std::max(0, opts->grid_cap) : 0;
   sched.graph = opts ? opts->use_graph != 0 : false;
+  sched.lookahead = opts ? opts->no_lookahead == 0 : true;
   float ms_tune = 0.0f;
   if (plan == PDD_PLAN_AUTOTUNED) {
     if (!D.tuned) {
       const auto t0 = std::chrono::steady_clock::now();
-      autotune(D, S, budget, st, D.tuned_mixed, D.tuned_cap);
+      autotune(D, S, budget, st, D.tuned_mixed, D.tuned_cap, D.tuned_lookahead);
       D.tuned = true;
       ms_tune = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     sched.mixed = D.tuned_mixed;
     sched.grid_cap = D.tuned_cap;
+    sched.lookahead = D.tuned_lookahead;
   }
   // The Monte Carlo and boundary rows run on a second stream, concurrently
   // with the floating rows; both write disjoint rows of the CSR arrays.
@@ -741,6 +747,7 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
   s.n_groups = (int32_t)groups.size();
   s.mixed_buckets = sched.mixed ? 1 : 0;
   s.grid_cap = sched.grid_cap;
+  s.lu_lookahead = sched.lookahead ? 1 : 0;
   s.graph_replays = run.replays;
   s.ms_autotune = ms_tune;
   s.n_launch_mc = n_launch_mc;

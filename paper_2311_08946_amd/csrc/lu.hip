@@ -9,13 +9,17 @@
 // is reached), four launches per step over the whole batch:
 //   * lu_pupd_kernel (one workgroup per matrix and 128-row tile of the
 //     panel): A[K0:n, K0:K0+128] -= L[K0:n, 0:K0] U[0:K0, K0:K0+128];
-//   * lu_panel_kernel (one workgroup per matrix): factorises the step's panel
-//     by sub-panels of NB columns held in registers (thread t owns rows
-//     k0 + t + 512 s), column by column with a workgroup-wide pivot search,
-//     each followed by its interchanges, its block row of U and the update of
-//     the rest of the panel; it then stores the step's composed row
+//   * lu_panel_own_kernel (one workgroup per matrix, a thread per panel row;
+//     orders up to 1024): factorises the step's panel without moving rows --
+//     each thread keeps its row and tracks the row's position in the pivoted
+//     order -- in groups of 32 columns held in registers, column by column
+//     with a workgroup-wide pivot search, then the group's U12 rows and the
+//     MFMA update of the rest of the panel; the rows that moved are written
+//     to their positions once at the end.  It stores the step's composed row
 //     permutation and the inverses of the 32 x 32 diagonal blocks of L11 and
-//     U11 in a per-matrix work area;
+//     U11 in a per-matrix work area.  Larger orders use lu_panel_wide_kernel
+//     (sub-panels of NB columns in registers, thread t owning rows
+//     k0 + t + 512 s, interchanges applied after each sub-panel);
 //   * lu_urow_kernel<LEFT> (one workgroup per matrix and 128-column tile
 //     left of the panel): applies the step's interchanges to L; one more
 //     workgroup per matrix forms L11^-1 from the inverses of its 32 x 32
@@ -39,6 +43,7 @@
 // 128 x 128 workgroup tiles and K streamed through LDS in chunks of 32, the
 // next chunk's global loads issued before the current chunk's MFMAs.
 #include <algorithm>
+#include <utility>
 #include <vector>
 
 #include "runtime.h"
@@ -56,6 +61,14 @@ constexpr int kWave = 64;
 constexpr int kTB = 32;         // triangular block
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+// Matrix data is reached through pointers held in the work lists; they are
+// declared in the global address space so that the compiler emits global
+// (not flat) memory instructions: a flat load also counts against the LDS
+// wait counter, so every LDS wait would wait for the global prefetches too.
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) int32_t gint;
 
 struct GemmLds {
   double Lt[kGK][kGT + kPad];   // -A[r, k] chunk, transposed
@@ -70,8 +83,8 @@ struct GemmLds {
 // left factor Lb (leading dimension ldl); the right factor may be the output
 // block itself (every read precedes the final barrier, every write follows it).
 template <bool SET>
-__device__ __attribute__((always_inline)) void gemm_op(double* __restrict__ A, int ld, int r0, int r1, int c0, int c1,
-                                                        int k0, int k1, const double* Lb, int ldl, int lro, int lko,
+__device__ __attribute__((always_inline)) void gemm_op(gdouble* __restrict__ A, int ld, int r0, int r1, int c0, int c1,
+                                                        int k0, int k1, const gdouble* Lb, int ldl, int lro, int lko,
                                                         GemmLds& s) {
   // element offsets from A fit in 32 bits (n * ld < 2^31)
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -169,7 +182,7 @@ __device__ __attribute__((always_inline)) void gemm_op(double* __restrict__ A, i
   __syncthreads();
 }
 
-__device__ __attribute__((always_inline)) void gemm_sub(double* __restrict__ A, int ld, int r0, int r1, int c0, int c1,
+__device__ __attribute__((always_inline)) void gemm_sub(gdouble* __restrict__ A, int ld, int r0, int r1, int c0, int c1,
                                                          int k0, int k1, GemmLds& s) {
   gemm_op<false>(A, ld, r0, r1, c0, c1, k0, k1, A, ld, 0, 0, s);
 }
@@ -180,7 +193,7 @@ __device__ __attribute__((always_inline)) void gemm_sub(double* __restrict__ A, 
 // streams its own 16-row strips -- left factor in the MFMA A layout and the
 // strip of C loaded straight from global memory, no barrier between strips.
 // Ends with a barrier.
-__device__ __attribute__((always_inline)) void strip_update(double* __restrict__ A, int ld, int r0, int r1,
+__device__ __attribute__((always_inline)) void strip_update(gdouble* __restrict__ A, int ld, int r0, int r1,
                                                              int c0, int c1, int k0, int k1,
                                                              double (*sU)[kGT + kPad]) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -252,7 +265,7 @@ struct TriLds {
 // T = (unit lower triangle of A[a:a+w, a:a+w])^-1 if LOWER, else
 // (upper triangle with diagonal)^-1.  Ends with a barrier.
 template <int NB, bool LOWER>
-__device__ __attribute__((always_inline)) void tri_inverse(const double* __restrict__ A, int ld, int a,
+__device__ __attribute__((always_inline)) void tri_inverse(const gdouble* __restrict__ A, int ld, int a,
                                                             int w, TriLds& t) {
   const int tid = threadIdx.x;
   for (int idx = tid; idx < NB * NB; idx += kThreads) {
@@ -291,7 +304,7 @@ __device__ __attribute__((always_inline)) void tri_inverse(const double* __restr
 // Both inverses of one kTB x kTB diagonal block: t.inv <- (unit lower)^-1 by
 // wavefront 0 and t.inv2 <- (upper with diagonal)^-1 by wavefront 1, at the
 // same time.  Ends with a barrier.
-__device__ __attribute__((always_inline)) void tri_inverse_pair(const double* __restrict__ A, int ld, int a,
+__device__ __attribute__((always_inline)) void tri_inverse_pair(const gdouble* __restrict__ A, int ld, int a,
                                                                  int w, TriLds& t) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int idx = tid; idx < kTB * kTB; idx += kThreads) {
@@ -332,7 +345,7 @@ __device__ __attribute__((always_inline)) void tri_inverse_pair(const double* __
 // B layout, multiplied by T read from LDS as the products need it (few live
 // registers), and written back in place.  Ends with a barrier.
 template <int NB>
-__device__ __attribute__((always_inline)) void tri_apply(double* __restrict__ A, int ld, int a, int w,
+__device__ __attribute__((always_inline)) void tri_apply(gdouble* __restrict__ A, int ld, int a, int w,
                                                           int c0, int c1, const TriLds& t) {
   constexpr int BI = NB / 16, KS = NB / 4;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -383,6 +396,23 @@ struct LuWork {
 };
 static_assert(sizeof(LuWork) % 8 == 0, "the inverses of U's blocks follow LuWork");
 
+typedef __attribute__((address_space(1))) LuWork gwork;
+
+// A work-list entry as the kernels see it (global address space pointers).
+struct GItem {
+  gdouble* A;
+  gint* piv;
+  gint* status;
+  gwork* work;
+  gdouble* uinv;
+  int32_t n, ld, nrhs, cls;
+};
+
+__device__ __forceinline__ GItem gitem(const LuItem& it) {
+  return GItem{(gdouble*)it.A, (gint*)it.piv, (gint*)it.status, (gwork*)it.work, (gdouble*)it.uinv,
+               it.n, it.ld, it.nrhs, it.cls};
+}
+
 namespace {
 
 // Composes the interchanges (base + t) <-> piv[t], t = 0..cnt-1 in order
@@ -430,7 +460,7 @@ struct PermLds {
 // Applies a composed permutation to columns [lo, hi) except [skip0, skip1):
 // the touched rows are staged through `scratch` (2 kOuter x 32 doubles) in
 // blocks of 32 columns and written back permuted.  Ends with a barrier.
-__device__ __attribute__((always_inline)) void apply_perm(double* __restrict__ A, int ld, const PermLds& pl,
+__device__ __attribute__((always_inline)) void apply_perm(gdouble* __restrict__ A, int ld, const PermLds& pl,
                                                            int lo, int hi, int skip0, int skip1,
                                                            double* __restrict__ scratch) {
   const int tid = threadIdx.x;
@@ -495,10 +525,10 @@ struct PanelLds {
 // constant in the unrolled loop, so the register file is never indexed
 // dynamically.  Pivot: largest magnitude, lowest row index on ties.
 template <int ROWS, int NB>
-__device__ __attribute__((always_inline)) void factor_subpanel(double* __restrict__ A, int ld, int n,
+__device__ __attribute__((always_inline)) void factor_subpanel(gdouble* __restrict__ A, int ld, int n,
                                                                 int k0, int pw, int K0,
                                                                 int* __restrict__ s_piv,
-                                                                int32_t* __restrict__ piv,
+                                                                gint* __restrict__ piv,
                                                                 PanelLds<NB>& pl, int& singular) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double P[ROWS][NB];
@@ -627,11 +657,11 @@ struct PanelShared {
 };
 
 template <int ROWS, int NB>
-__device__ __attribute__((always_inline)) void panel_body(const LuItem& it, int K0, PanelShared<NB>& sh) {
+__device__ __attribute__((always_inline)) void panel_body(const GItem& it, int K0, PanelShared<NB>& sh) {
   constexpr int TB = NB < 16 ? 16 : NB;
-  double* A = it.A;
+  gdouble* A = it.A;
   const int n = it.n, ld = it.ld;
-  LuWork* W = it.work;
+  gwork* W = it.work;
   const int tid = threadIdx.x;
   const int kb = min(kOuter, n - K0);
   int singular = 0;
@@ -681,6 +711,347 @@ __device__ __attribute__((always_inline)) void panel_body(const LuItem& it, int 
   if (tid == 0 && (K0 == 0 || singular)) *it.status = singular;
 }
 
+// ---------------------------------------------------------------------------
+// Panel with row ownership (panel heights up to kOwnMax).  Thread t keeps
+// physical row K0 + t of the panel for the whole step and tracks that row's
+// position in the pivoted order; rows are not interchanged while the panel
+// is factorised.  The pivot of column K0 + c is the largest magnitude among
+// the rows at positions >= c (the lowest position on ties) -- the row that
+// partial pivoting with interchanges picks -- and every row sees the same
+// operations in the same order, so the factors are those of the interchange
+// form.  Columns are taken in groups of kTB: a group is factorised in
+// registers (one barrier per column), its diagonal block is inverted in LDS,
+// its pivot rows of the trailing panel columns become U12 = L11^-1 A12 and
+// the remaining rows take the rank-kTB update on MFMA.  At the end the rows
+// that moved are written to their positions once, and the step's composed
+// permutation is recorded for the other columns.
+
+constexpr int kOwnMax = 1024;
+constexpr int kSW = kOuter - kTB;            // trailing panel columns of a group (at most)
+
+// The phases of a group use the LDS in turn (about 27 KB in all, so that
+// up to five workgroups share a CU).
+struct OwnLds {
+  union {
+    struct {                                   // column factorisation
+      double cand[2][kOwnMax / kWave][kTB];   // each wavefront's best candidate row
+      double cv[2][kOwnMax / kWave];
+      int cpos[2][kOwnMax / kWave];
+      int crow[2][kOwnMax / kWave];
+    } f;
+    TriLds t;                                  // the group's diagonal block and its inverses
+    double S[kTB][kSW + kPad];                 // U12: the group's pivot rows of the trailing columns
+    struct {                                   // the step's permutation record
+      short who[kOwnMax];                      // the physical row (- K0) at each position
+      short slot[kOwnMax];                     // moved rows: index in the record
+      int wcount[kOwnMax / kWave];
+    } g;
+  } u;
+  short pos[kOwnMax];                          // position of physical row K0 + t
+  int prow[kTB];                               // physical rows (- K0) of the group's pivots
+};
+
+// Both inverses of the kTB x kTB block in t.blk (identity-padded beyond w):
+// t.inv <- (unit lower)^-1, t.inv2 <- (upper with diagonal)^-1.  Lanes 0..31
+// of wavefront 0 take the lower triangle and 32 lanes of wavefront 1 (of
+// wavefront 0 when it is alone) the upper one, in reversed index order so
+// that both run the same forward substitution.  Ends with a barrier.
+__device__ __attribute__((always_inline)) void own_block_inverses(int w, TriLds& t, int nw) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const bool lo = wv == 0 && lane < kTB;
+  const int uw = nw > 1 ? 1 : 0, ul0 = nw > 1 ? 0 : kTB;
+  const bool up = wv == uw && lane >= ul0 && lane < ul0 + kTB;
+  if (lo || up) {
+    constexpr int R = kTB + 1;               // row stride of the LDS blocks
+    const int j = lo ? lane : lane - ul0;
+    // B(i, k) = blk[o + s i + s k / R ...]: lower: blk[i][k]; upper: blk[31 - i][31 - k]
+    const double* bb = lo ? &t.blk[0][0] : &t.blk[kTB - 1][kTB - 1];
+    const int bs = lo ? 1 : -1;
+    double* xx = lo ? &t.inv[0][j] : &t.inv2[kTB - 1][j];
+    const int target = lo ? j : kTB - 1 - j;
+#pragma unroll 1
+    for (int i = 0; i < kTB; ++i) {
+      double v = (i == target) ? 1.0 : 0.0;
+      const double* brow = bb + bs * R * i;
+#pragma unroll 8
+      for (int k = 0; k < i; ++k) v -= brow[bs * k] * xx[bs * R * k];
+      xx[bs * R * i] = lo ? v : v / brow[bs * i];
+    }
+#pragma unroll 1
+    for (int i = 0; i < kTB; ++i)
+      if (i >= w || j >= w) (lo ? t.inv : t.inv2)[i][j] = 0.0;
+  }
+  __syncthreads();
+}
+
+// Column C of a group (C < gw): pivot search, interchange of positions and
+// the rank-1 update of the group's later columns; one barrier.  A template
+// per column so that the register row P is only ever indexed by constants.
+template <int C>
+__device__ __attribute__((always_inline)) void own_column(double (&P)[kTB], int& pos, int& singular, int gw, int g0r,
+                                                          int K0, gint* __restrict__ piv, bool own, bool live,
+                                                          gdouble* __restrict__ wrow, int nw, OwnLds& sh) {
+  if (C >= gw) return;                       // uniform
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int cr = g0r + C, buf = C & 1;
+  const bool cand = own && pos >= cr;
+  const double a = fabs(P[C]);
+  const double wmax = wave_max(cand ? a : -1.0);
+  const unsigned long long msk = __ballot(cand && a == wmax);
+  int wl = -1;
+  if (msk != 0ull) {
+    wl = __builtin_ctzll(msk);
+    if (msk & (msk - 1ull)) {                // ties inside the wavefront: lowest position
+      int best = __builtin_amdgcn_readlane(pos, wl);
+      for (unsigned long long r = msk & (msk - 1ull); r != 0ull; r &= r - 1ull) {
+        const int l = __builtin_ctzll(r);
+        const int p = __builtin_amdgcn_readlane(pos, l);
+        if (p < best) { best = p; wl = l; }
+      }
+    }
+  }
+  if (lane == wl) {
+#pragma unroll
+    for (int cc = C; cc < kTB; ++cc) sh.u.f.cand[buf][w][cc] = P[cc];
+    sh.u.f.cv[buf][w] = a;
+    sh.u.f.cpos[buf][w] = pos;
+    sh.u.f.crow[buf][w] = tid;
+  }
+  if (wl < 0 && lane == 0) sh.u.f.cv[buf][w] = -1.0;
+  __syncthreads();
+  // the workgroup's pivot: lane v reads wavefront v's record, then the same
+  // maximum / lowest-position selection across the lanes
+  // (the three records are read at once, in bounds for every lane, and
+  // masked afterwards)
+  const int vl = lane & (kOwnMax / kWave - 1);
+  const double ov_raw = sh.u.f.cv[buf][vl];
+  const int opos_raw = sh.u.f.cpos[buf][vl];
+  const int orow = sh.u.f.crow[buf][vl];
+  const double ov = lane < nw ? ov_raw : -1.0;
+  const double gv = wave_max(ov);
+  const unsigned long long gm = __ballot(lane < nw && ov == gv);
+  int gwv = gm ? __builtin_ctzll(gm) : 0;
+  const int opos = lane < nw ? opos_raw : 0x7fffffff;
+  int gp = __builtin_amdgcn_readlane(opos, gwv);
+  if (gm & (gm - 1ull)) {                    // ties between wavefronts: lowest position
+    for (unsigned long long r = gm & (gm - 1ull); r != 0ull; r &= r - 1ull) {
+      const int l = __builtin_ctzll(r);
+      const int p = __builtin_amdgcn_readlane(opos, l);
+      if (p < gp) { gp = p; gwv = l; }
+    }
+  }
+  const bool ok = gv > 0.0;                  // uniform
+  if (!ok) singular = 1;
+  const int ppos = ok ? gp : cr;
+  const bool is_piv = ok ? tid == __builtin_amdgcn_readlane(orow, gwv) : (own && pos == cr);
+  const int npos = is_piv ? cr : (pos == cr ? ppos : pos);
+  if (ok && own && npos > cr) {
+    // the pivot row in aligned chunks of 8, each chunk's four 16-byte LDS
+    // loads issued together
+    const dbl2* __restrict__ pr2 = reinterpret_cast<const dbl2*>(sh.u.f.cand[buf][gwv]);
+    double l = 0.0;
+#pragma unroll
+    for (int q = C / 8; q < kTB / 8; ++q) {
+      const dbl2 v0 = pr2[4 * q], v1 = pr2[4 * q + 1], v2 = pr2[4 * q + 2], v3 = pr2[4 * q + 3];
+      const double pv[8] = {v0.x, v0.y, v1.x, v1.y, v2.x, v2.y, v3.x, v3.y};
+      if (q == C / 8) {
+        l = P[C] * (1.0 / pv[C % 8]);
+        P[C] = l;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (8 * q + j > C) P[8 * q + j] -= l * pv[j];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  pos = npos;
+  if (tid == 0) piv[K0 + cr] = K0 + ppos;
+  if (live) wrow[C] = P[C];                  // final for every row from here on
+}
+
+template <int... Cs>
+__device__ __attribute__((always_inline)) void own_columns(std::integer_sequence<int, Cs...>, double (&P)[kTB],
+                                                           int& pos, int& singular, int gw, int g0r, int K0,
+                                                           gint* __restrict__ piv, bool own, bool live,
+                                                           gdouble* __restrict__ wrow, int nw, OwnLds& sh) {
+  (own_column<Cs>(P, pos, singular, gw, g0r, K0, piv, own, live, wrow, nw, sh), ...);
+}
+
+__device__ __attribute__((always_inline)) void panel_own_body(const GItem& it, int K0, OwnLds& sh) {
+  gdouble* __restrict__ A = it.A;
+  const int n = it.n, ld = it.ld;
+  gwork* W = it.work;
+  const int nthr = blockDim.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = nthr >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int m = n - K0, kb = min(kOuter, m);
+  const bool own = tid < m;
+  const gdouble* arow = A + (size_t)(K0 + (own ? tid : 0)) * ld;
+  int pos = own ? tid : 0x7fff;
+  int singular = 0;
+#pragma unroll 1
+  for (int gi = 0, g0r = 0; g0r < kb; ++gi, g0r += kTB) {
+    const int gw = min(kTB, kb - g0r), g0 = K0 + g0r;
+    const bool live = own && pos >= g0r;     // not pivoted in an earlier group
+    // (rows not live and columns past gw hold values that are never used;
+    // the address is clamped inside the row, the value not masked, so that
+    // every load is in flight at once)
+    double P[kTB];
+#pragma unroll
+    for (int c = 0; c < kTB; ++c) P[c] = arow[g0 + min(c, gw - 1)];
+    // each column stored as soon as it is final (the registers of the
+    // finished columns are free for the rest of the group)
+    gdouble* wrow = A + (size_t)(K0 + (own ? tid : 0)) * ld + g0;
+    own_columns(std::make_integer_sequence<int, kTB>{}, P, pos, singular, gw, g0r, K0, it.piv, own, live, wrow, nw,
+                sh);
+    __syncthreads();                         // the candidate rows are read; the LDS is reused
+    // the group's pivot rows form the diagonal block (read back from the row
+    // each thread has just stored), identity-padded beyond gw
+    if (own && pos >= g0r && pos < g0r + gw) {
+      const int i = pos - g0r;
+#pragma unroll
+      for (int c = 0; c < kTB; ++c) sh.u.t.blk[i][c] = c < gw ? wrow[c] : 0.0;
+      sh.prow[i] = tid;
+    }
+    for (int idx = gw * kTB + tid; idx < kTB * kTB; idx += nthr)
+      sh.u.t.blk[idx >> 5][idx & 31] = ((idx >> 5) == (idx & 31)) ? 1.0 : 0.0;
+    if (own) sh.pos[tid] = (short)pos;
+    __syncthreads();
+    own_block_inverses(gw, sh.u.t, nw);
+    for (int idx = tid; idx < kTB * kTB; idx += nthr) {
+      it.uinv[(g0 / kTB) * kTB * kTB + idx] = sh.u.t.inv2[idx >> 5][idx & 31];
+      W->inv[gi][idx >> 5][idx & 31] = sh.u.t.inv[idx >> 5][idx & 31];
+    }
+    __syncthreads();                         // the inverses are stored (E2 reads L11^-1 back)
+    const int c0 = g0 + gw, wt = K0 + kb - c0;
+    if (wt > 0) {
+      // the pivot rows of the trailing columns ...
+      for (int idx = tid; idx < kTB * kSW; idx += nthr) {
+        const int i = idx / kSW, j = idx - i * kSW;
+        sh.u.S[i][j] = (i < gw && j < wt) ? A[(size_t)(K0 + sh.prow[i]) * ld + c0 + j] : 0.0;
+      }
+      __syncthreads();
+      // ... become U12 = L11^-1 A12 (in LDS and in place) ...
+      const gdouble* __restrict__ linv = &W->inv[gi][0][0];
+      for (int cb = 16 * w; cb < wt; cb += 16 * nw) {
+        const int col = cb + li;
+        const bool cok = col < wt;
+        double xb[kTB / 4];
+#pragma unroll
+        for (int ks = 0; ks < kTB / 4; ++ks) xb[ks] = cok ? sh.u.S[4 * ks + lk][col] : 0.0;
+        dbl4 acc[2];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) acc[bi] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < kTB / 4; ++ks)
+#pragma unroll
+          for (int bi = 0; bi < 2; ++bi)
+            acc[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(linv[(16 * bi + li) * kTB + 4 * ks + lk], xb[ks], acc[bi],
+                                                           0, 0, 0);
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = 16 * bi + 4 * v + lk;
+            if (cok && r < gw) {
+              sh.u.S[r][col] = acc[bi][v];
+              A[(size_t)(K0 + sh.prow[r]) * ld + c0 + col] = acc[bi][v];
+            }
+          }
+      }
+      __syncthreads();
+      // ... and the rows not yet pivoted take A[r, c0:] -= L[r, group] U12,
+      // 16-row strips per wavefront, every load of a strip issued at once
+      // (pivoted rows are left untouched)
+      const int plive = g0r + gw, KS = (gw + 3) >> 2, CB = (wt + 15) >> 4;
+#pragma unroll 1
+      for (int rs = 16 * w; rs < m; rs += 16 * nw) {
+        const bool aok = rs + li < m && sh.pos[rs + li] >= plive;
+        if (__ballot(aok) == 0ull) continue;
+        double a[kTB / 4];
+#pragma unroll
+        for (int ks = 0; ks < kTB / 4; ++ks) {
+          const bool ok = aok && ks < KS && 4 * ks + lk < gw;
+          const double v = A[ok ? (size_t)(K0 + rs + li) * ld + g0 + 4 * ks + lk : 0];
+          a[ks] = ok ? -v : 0.0;
+        }
+        unsigned rmask = 0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = rs + 4 * v + lk;
+          rmask |= (r < m && sh.pos[r] >= plive) ? (1u << v) : 0u;
+        }
+        const size_t cbase = (size_t)(K0 + rs + lk) * ld + c0 + li;
+        // entries outside the block read A[0] and are never stored (each
+        // output entry depends only on its own input entry)
+        dbl4 acc[kSW / 16];
+#pragma unroll
+        for (int cb = 0; cb < kSW / 16; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const bool ok = cb < CB && ((rmask >> v) & 1u) && 16 * cb + li < wt;
+            acc[cb][v] = A[ok ? cbase + (size_t)(4 * v) * ld + 16 * cb : 0];
+          }
+#pragma unroll
+        for (int ks = 0; ks < kTB / 4; ++ks) {
+          if (ks < KS) {
+#pragma unroll
+            for (int cb = 0; cb < kSW / 16; ++cb)
+              if (cb < CB)
+                acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], sh.u.S[4 * ks + lk][16 * cb + li], acc[cb], 0,
+                                                               0, 0);
+          }
+        }
+#pragma unroll
+        for (int cb = 0; cb < kSW / 16; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (cb < CB && ((rmask >> v) & 1u) && 16 * cb + li < wt) A[cbase + (size_t)(4 * v) * ld + 16 * cb] = acc[cb][v];
+      }
+      __syncthreads();
+    }
+  }
+  // the rows that moved go to their positions, 32 columns at a time (every
+  // read of a block precedes every write of it)
+  const bool moved = own && pos != tid;
+#pragma unroll 1
+  for (int g0r = 0; g0r < kb; g0r += kTB) {
+    const int gw = min(kTB, kb - g0r);
+    double P[kTB];
+#pragma unroll
+    for (int c = 0; c < kTB; ++c) P[c] = arow[K0 + g0r + min(c, gw - 1)];
+    __syncthreads();
+    if (moved) {
+      gdouble* __restrict__ wr = A + (size_t)(K0 + pos) * ld + K0 + g0r;
+#pragma unroll
+      for (int c = 0; c < kTB; ++c)
+        if (c < gw) wr[c] = P[c];
+    }
+  }
+  // the step's permutation for the other columns: row K0 + t receives the
+  // old contents of row K0 + who[t]
+  __syncthreads();                           // the LDS is reused
+  if (own) sh.u.g.who[pos] = (short)tid;
+  const unsigned long long mm = __ballot(moved);
+  if (lane == 0) sh.u.g.wcount[w] = __popcll(mm);
+  __syncthreads();
+  int base = 0;
+  for (int v = 0; v < w; ++v) base += sh.u.g.wcount[v];
+  if (moved) sh.u.g.slot[tid] = (short)(base + __popcll(mm & ((1ull << lane) - 1ull)));
+  __syncthreads();
+  const int par = (K0 / kOuter) & 1;
+  if (moved) {
+    const int e = sh.u.g.slot[tid];
+    W->rows[par][e] = K0 + tid;
+    W->src[par][e] = sh.u.g.slot[sh.u.g.who[tid]];
+  }
+  if (tid == 0) {
+    int total = 0;
+    for (int v = 0; v < nw; ++v) total += sh.u.g.wcount[v];
+    W->count[par] = total;
+    if (K0 == 0 || singular) *it.status = singular;
+  }
+}
+
 // One 16 x 16 output tile of alpha P Q (inner dimension K) by one wavefront
 // on MFMA, operands read straight from global memory in the MFMA layouts:
 // P(i, k) = p[i ld + k] for i < rows and k < cols, zero elsewhere (likewise
@@ -688,13 +1059,13 @@ __device__ __attribute__((always_inline)) void panel_body(const LuItem& it, int 
 // valid address `safe` instead, so that every load is issued before the
 // first product.  The tile is stored to c (leading dimension lc).
 struct Opnd {
-  const double* p;
+  const gdouble* p;
   int ld, rows, cols;
 };
 
 template <int K>
-__device__ __attribute__((always_inline)) void wave_tile(Opnd P, Opnd Q, double alpha, double* c, int lc,
-                                                          const double* safe) {
+__device__ __attribute__((always_inline)) void wave_tile(Opnd P, Opnd Q, double alpha, gdouble* c, int lc,
+                                                          const gdouble* safe) {
   const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
   double a[K / 4], b[K / 4];
 #pragma unroll
@@ -724,10 +1095,10 @@ __device__ __attribute__((always_inline)) void wave_tile(Opnd P, Opnd Q, double 
 //   3: P = L[2:4, 0:2] X[0:2, 0:2] into X[0:2, 2:4];
 //   4: X[2:4, 0:2] = -X[2:4, 2:4] P;   5: X[0:2, 2:4] = 0.
 // Ends with a barrier.
-__device__ __attribute__((always_inline)) void linv_body(const LuItem& it, int K0) {
+__device__ __attribute__((always_inline)) void linv_body(const GItem& it, int K0) {
   const int n = it.n, ld = it.ld;
-  LuWork* W = it.work;
-  double* __restrict__ X = &W->linv[(K0 / kOuter) & 1][0][0];
+  gwork* W = it.work;
+  gdouble* __restrict__ X = &W->linv[(K0 / kOuter) & 1][0][0];
   const int tid = threadIdx.x, w = tid >> 6;
   const int kb = min(kOuter, n - K0);
   auto L = [&](int a, int b) {            // block (a, b), a > b, of L11
@@ -792,11 +1163,11 @@ __device__ __attribute__((always_inline)) void linv_body(const LuItem& it, int K
 // already carry this step's interchanges, so the left tiles run in an earlier
 // launch -- and become rows [K0, K0 + kb) of U.
 template <bool LEFT>
-__device__ __attribute__((always_inline)) void urow_body(const LuItem& it, int K0, int t, MatLds& u,
+__device__ __attribute__((always_inline)) void urow_body(const GItem& it, int K0, int t, MatLds& u,
                                                           PermLds& perm) {
-  double* A = it.A;
+  gdouble* A = it.A;
   const int n = it.n, ld = it.ld;
-  const LuWork* W = it.work;
+  const gwork* W = it.work;
   const int tid = threadIdx.x;
   const int kb = min(kOuter, n - K0);
   if (LEFT && t == K0 / kGT) {           // the last unit of the LEFT launch
@@ -823,7 +1194,7 @@ __device__ __attribute__((always_inline)) void urow_body(const LuItem& it, int K
 
 // Row tile t of the step's panel: the contributions of all earlier steps,
 // A[K0 + 128 t .., K0 : K0 + kb] -= L[.., 0 : K0] U[0 : K0, K0 : K0 + kb].
-__device__ __attribute__((always_inline)) void pupd_body(const LuItem& it, int K0, int t, GemmLds& g) {
+__device__ __attribute__((always_inline)) void pupd_body(const GItem& it, int K0, int t, GemmLds& g) {
   const int n = it.n;
   const int kb = min(kOuter, n - K0);
   const int ra = K0 + t * kGT;
@@ -834,8 +1205,8 @@ __device__ __attribute__((always_inline)) void pupd_body(const LuItem& it, int K
 // bottom in blocks of kOuter rows aligned with the factorisation: the
 // diagonal block is solved by its 32-row triangles (stored inverses on MFMA)
 // and MFMA updates inside the block ...
-__device__ __attribute__((always_inline)) void bdiag_body(const LuItem& it, int k0, MatLds& u) {
-  double* A = it.A;
+__device__ __attribute__((always_inline)) void bdiag_body(const GItem& it, int k0, MatLds& u) {
+  gdouble* A = it.A;
   const int n = it.n, ld = it.ld, nrhs = it.nrhs;
   const int tid = threadIdx.x;
   const int k1 = min(n, k0 + kOuter);
@@ -853,7 +1224,7 @@ __device__ __attribute__((always_inline)) void bdiag_body(const LuItem& it, int 
 }
 
 // ... and its contribution is removed from the 128-row tile t above it.
-__device__ __attribute__((always_inline)) void bupd_body(const LuItem& it, int k0, int t, GemmLds& g) {
+__device__ __attribute__((always_inline)) void bupd_body(const GItem& it, int k0, int t, GemmLds& g) {
   const int n = it.n;
   const int k1 = min(n, k0 + kOuter);
   const int r0 = t * kGT;
@@ -885,26 +1256,29 @@ __device__ __forceinline__ int xcd_index() {
   return ((int)blockIdx.x & 7) * t8 + ((int)blockIdx.x >> 3);
 }
 
-__device__ __forceinline__ int back_block(const LuItem& it, int step) {
+__device__ __forceinline__ int back_block(const GItem& it, int step) {
   return ((it.n + kOuter - 1) / kOuter - 1 - step) * kOuter;
 }
 
-// The panel kernel: four wavefronts per SIMD (two workgroups per CU) where
-// the register sub-panel is small (ROWS <= 2), two where it is not.
+// The register-panel kernel of the taller panels (orders above kOwnMax).
 template <int ROWS, int NB>
 __device__ __attribute__((always_inline)) void panel_launch(const LuItem* __restrict__ items,
                                                             const int32_t* __restrict__ pre, int count, int step,
                                                             PanelShared<NB>& sh) {
   const int gi = blockIdx.x;                 // one workgroup per matrix
   if (gi >= pre[count]) return;
-  panel_body<ROWS, NB>(items[owner(pre, count, gi)], step * kOuter, sh);
+  panel_body<ROWS, NB>(gitem(items[owner(pre, count, gi)]), step * kOuter, sh);
 }
 
-template <int ROWS, int NB>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void lu_panel_kernel(
-    const LuItem* __restrict__ items, const int32_t* __restrict__ pre, int count, int step) {
-  __shared__ PanelShared<NB> sh;
-  panel_launch<ROWS, NB>(items, pre, count, step, sh);
+// Row-ownership panel: one workgroup per matrix, a thread per panel row
+// (the launch's block size covers the tallest panel of the step).
+__global__ __launch_bounds__(kOwnMax) void lu_panel_own_kernel(const LuItem* __restrict__ items,
+                                                               const int32_t* __restrict__ pre, int count,
+                                                               int step) {
+  __shared__ __attribute__((aligned(16))) OwnLds sh;
+  const int gi = blockIdx.x;                 // one workgroup per matrix
+  if (gi >= pre[count]) return;
+  panel_own_body(gitem(items[owner(pre, count, gi)]), step * kOuter, sh);
 }
 
 template <int ROWS, int NB>
@@ -929,12 +1303,12 @@ __global__ __launch_bounds__(kThreads) void lu_urow_kernel(const LuItem* __restr
     const int gi = xcd_index();
     if (gi >= total) return;
     const int m = owner(pre, count, gi);
-    urow_body<LEFT>(items[m], step * kOuter, gi - pre[m] + OFF, u, perm);
+    urow_body<LEFT>(gitem(items[m]), step * kOuter, gi - pre[m] + OFF, u, perm);
     return;
   }
   for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
     const int m = owner(pre, count, gi);
-    urow_body<LEFT>(items[m], step * kOuter, gi - pre[m] + OFF, u, perm);
+    urow_body<LEFT>(gitem(items[m]), step * kOuter, gi - pre[m] + OFF, u, perm);
     __syncthreads();
   }
 }
@@ -948,12 +1322,12 @@ __global__ __launch_bounds__(kThreads) void lu_pupd_kernel(
     const int gi = xcd_index();
     if (gi >= total) return;
     const int m = owner(pre, count, gi);
-    pupd_body(items[m], step * kOuter, gi - pre[m], g);
+    pupd_body(gitem(items[m]), step * kOuter, gi - pre[m], g);
     return;
   }
   for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
     const int m = owner(pre, count, gi);
-    pupd_body(items[m], step * kOuter, gi - pre[m], g);
+    pupd_body(gitem(items[m]), step * kOuter, gi - pre[m], g);
   }
 }
 
@@ -962,7 +1336,7 @@ __global__ __launch_bounds__(kThreads) void lu_bdiag_kernel(const LuItem* __rest
   __shared__ MatLds u;
   const int gi = blockIdx.x;                 // one workgroup per matrix
   if (gi >= pre[count]) return;
-  const LuItem it = items[owner(pre, count, gi)];
+  const GItem it = gitem(items[owner(pre, count, gi)]);
   bdiag_body(it, back_block(it, step), u);
 }
 
@@ -975,13 +1349,13 @@ __global__ __launch_bounds__(kThreads) void lu_bupd_kernel(const LuItem* __restr
     const int gi = xcd_index();
     if (gi >= total) return;
     const int m = owner(pre, count, gi);
-    const LuItem it = items[m];
+    const GItem it = gitem(items[m]);
     bupd_body(it, back_block(it, step), gi - pre[m], g);
     return;
   }
   for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
     const int m = owner(pre, count, gi);
-    const LuItem it = items[m];
+    const GItem it = gitem(items[m]);
     bupd_body(it, back_block(it, step), gi - pre[m], g);
   }
 }
@@ -1039,6 +1413,14 @@ void LuPlan::build(const std::vector<LuItem>& its) {
       for (int m = 0; m < count; ++m) p[m + 1] = p[m] + lu_plan_tiles(its[m], kind, s);
       totals[(size_t)kind * nsteps + s] = p[count];
     }
+  // block size of the row-ownership panels: the step's tallest panel
+  own_threads.assign((size_t)2 * nsteps, kWave);
+  for (const auto& it : its)
+    if (it.cls <= 1)
+      for (int s = 0; s * kOuter < it.n; ++s) {
+        int32_t& t = own_threads[(size_t)it.cls * nsteps + s];
+        t = std::max(t, (it.n - s * kOuter + kWave - 1) / kWave * kWave);
+      }
   d_items.upload(items);
   d_pre.upload(pre);
   if (!side) PDD_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
@@ -1051,7 +1433,7 @@ void LuPlan::build(const std::vector<LuItem>& its) {
   }
 }
 
-int LuPlan::launch(hipStream_t st, int grid_cap) const {
+int LuPlan::launch(hipStream_t st, int grid_cap, bool lookahead) const {
   const LuItem* di = d_items.ptr<LuItem>();
   int launches = 0;
   typedef void (*Kern)(const LuItem*, const int32_t*, int, int);
@@ -1076,15 +1458,23 @@ int LuPlan::launch(hipStream_t st, int grid_cap) const {
   int rest = -1;
   for (int s = 0; s < nsteps; ++s) {
     go(LU_PUPD, s, lu_pupd_kernel<false>, lu_pupd_kernel<true>, st);
-    go(LU_PANEL0, s, lu_panel_kernel<1, 16>, nullptr, st);
-    go(LU_PANEL1, s, lu_panel_kernel<2, 16>, nullptr, st);
+    for (int kind = LU_PANEL0; kind <= LU_PANEL1; ++kind) {
+      const int total = totals[(size_t)kind * nsteps + s];
+      if (total == 0) continue;
+      const int32_t* dp = d_pre.ptr<int32_t>() + ((size_t)kind * nsteps + s) * (count + 1);
+      hipLaunchKernelGGL(lu_panel_own_kernel, dim3(total), dim3(own_threads[(size_t)(kind - LU_PANEL0) * nsteps + s]),
+                         0, st, di, dp, count, s);
+      ++launches;
+    }
     go(LU_PANEL2, s, lu_panel_wide_kernel<4, 16>, nullptr, st);
     go(LU_PANEL3, s, lu_panel_wide_kernel<8, 8>, nullptr, st);
     go(LU_LSWAP, s, lu_urow_kernel<false, true>, lu_urow_kernel<true, true>, st);
     if (rest >= 0) PDD_HIP(hipStreamWaitEvent(st, ev_rest[rest], 0));
     rest = -1;
     go(LU_UROW0, s, lu_urow_kernel<false, false, 0>, lu_urow_kernel<true, false, 0>, st);
-    if (totals[(size_t)LU_UREST * nsteps + s] > 0) {
+    if (!lookahead) {
+      go(LU_UREST, s, lu_urow_kernel<false, false, 1>, lu_urow_kernel<true, false, 1>, st);
+    } else if (totals[(size_t)LU_UREST * nsteps + s] > 0) {
       PDD_HIP(hipEventRecord(ev_main[s], st));
       PDD_HIP(hipStreamWaitEvent(side, ev_main[s], 0));
       go(LU_UREST, s, lu_urow_kernel<false, false, 1>, lu_urow_kernel<true, false, 1>, side);

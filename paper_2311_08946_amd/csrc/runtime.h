@@ -107,6 +107,7 @@ struct DeviceCover {
   bool tuned = false;                   // schedule chosen by the autotuner for this cover
   bool tuned_mixed = true;
   int tuned_cap = 0;
+  bool tuned_lookahead = true;
   std::vector<std::unique_ptr<BucketData>> buckets;
   void upload(const HostCover& H);
   ChunkDesc chunk(const BucketData& b, int32_t first, int32_t count) const;
@@ -133,6 +134,7 @@ struct LuPlan {
   int nsteps = 0;
   std::vector<int32_t> pre;      // [kind][step][count + 1]
   std::vector<int32_t> totals;   // [kind][step]
+  std::vector<int32_t> own_threads;   // [class 0, 1][step]: block size of the row-ownership panels
   DevBuf d_items, d_pre;
   // the second stream of the look-ahead and its per-step events
   hipStream_t side = nullptr;
@@ -142,11 +144,11 @@ struct LuPlan {
   LuPlan& operator=(const LuPlan&) = delete;
   ~LuPlan();
   void build(const std::vector<LuItem>& its);
-  // Issues the launch sequence on st (and the plan's second stream, joined
-  // back into st before the back substitution); grid_cap bounds the
-  // workgroups of the tiled launches (each workgroup strides over the list).
-  // Returns launches.
-  int launch(hipStream_t st, int grid_cap) const;
+  // Issues the launch sequence on st (with lookahead, also on the plan's
+  // second stream, joined back into st before the back substitution);
+  // grid_cap bounds the workgroups of the tiled launches (each workgroup
+  // strides over the list).  Returns launches.
+  int launch(hipStream_t st, int grid_cap, bool lookahead = true) const;
 };
 
 // Device bytes of one circle's factors in a bucket (matrix, pivots, row
