@@ -53,6 +53,7 @@ namespace pdd {
 namespace {
 
 constexpr int kThreads = 512;
+constexpr int kGemmThreads = 256;  // the tiled product launches (pre-update, U rows, back updates)
 constexpr int kOuter = 128;
 constexpr int kGT = 128;        // update tile (rows and columns)
 constexpr int kGK = 32;         // K chunk
@@ -76,115 +77,133 @@ struct GemmLds {
 };
 
 // A[r0:r1, c0:c1] -= A[r0:r1, k0:k1] A[k0:k1, c0:c1]; the three blocks are
-// disjoint.  Called by all threads of the workgroup; ends with a barrier.
+// disjoint.  Called by all NT threads of the workgroup; ends with a barrier.
+// NT = 512: 4 x 2 wavefronts of 32 x 64 outputs; NT = 256: 2 x 2 wavefronts
+// of 64 x 64 (twice the MFMAs per LDS operand read, and two workgroups share
+// a CU, so that one's tile loads and stores overlap the other's products).
 // Addresses are one per-lane base pointer plus workgroup-uniform offsets, and
 // the edge tests are per-lane bit masks, to keep register use low.
 // SET: A[r0:r1, c0:c1] = Lb[r - lro, k - lko] A[k0:k1, c0:c1] with a separate
 // left factor Lb (leading dimension ldl); the right factor may be the output
 // block itself (every read precedes the final barrier, every write follows it).
-template <bool SET>
+template <bool SET, int NT>
 __device__ __attribute__((always_inline)) void gemm_op(gdouble* __restrict__ A, int ld, int r0, int r1, int c0, int c1,
                                                         int k0, int k1, const gdouble* Lb, int ldl, int lro, int lko,
                                                         GemmLds& s) {
+  constexpr int NW = NT / kWave, WC = 2, WR = NW / WC;
+  constexpr int RW = kGT / WR, CW = kGT / WC;        // outputs per wavefront
+  constexpr int BI = RW / 16, BJ = CW / 16;
+  // K chunk: 32 with 512 threads; 16 with 256, whose 64 x 64 accumulators
+  // leave registers for half as many prefetched operands
+  constexpr int KC = NT >= 512 ? kGK : kGK / 2;
+  constexpr int LP = NT / KC, LIT = kGT / LP;        // A[r, k] chunk: rows per pass, passes
+  constexpr int UP = NT / kGT, UIT = KC / UP;        // A[k, c] chunk
+  static_assert(BI * 4 <= 32 && LIT <= 32, "mask widths");
   // element offsets from A fit in 32 bits (n * ld < 2^31)
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wr = w >> 1, wc = w & 1;       // 4 x 2 wavefronts: 32 rows x 64 columns each
+  const int wr = w / WC, wc = w % WC;
   const int li = lane & 15, lk = lane >> 4;
-  const int lrow = tid >> 5, lcol = tid & 31;      // operand loads: A[r, k] chunk
-  const int urow = tid >> 7, ucol = tid & 127;     //                A[k, c] chunk
+  const int lrow = tid / KC, lcol = tid % KC;        // operand loads: A[r, k] chunk
+  const int urow = tid / kGT, ucol = tid % kGT;      //                A[k, c] chunk
   double* __restrict__ lt_st = &s.Lt[lcol][lrow];
   double* __restrict__ ut_st = &s.Ut[urow][ucol];
-  const double* __restrict__ lt_rd = &s.Lt[lk][32 * wr + li];
-  const double* __restrict__ ut_rd = &s.Ut[lk][64 * wc + li];
+  const double* __restrict__ lt_rd = &s.Lt[lk][RW * wr + li];
+  const double* __restrict__ ut_rd = &s.Ut[lk][CW * wc + li];
 #pragma unroll 1
   for (int rt = r0; rt < r1; rt += kGT) {
 #pragma unroll 1
     for (int ct = c0; ct < c1; ct += kGT) {
-      const int crow = rt + 32 * wr + lk, ccol = ct + 64 * wc + li;
+      const int crow = rt + RW * wr + lk, ccol = ct + CW * wc + li;
       const int coff = crow * ld + ccol;
       unsigned rmask = 0, cmask = 0;
 #pragma unroll
-      for (int t = 0; t < 8; ++t)        // t = 4 bi + v: row offset 16 bi + 4 v
+      for (int t = 0; t < 4 * BI; ++t)   // t = 4 bi + v: row offset 16 bi + 4 v
         rmask |= (crow + 16 * (t >> 2) + 4 * (t & 3) < r1) ? (1u << t) : 0u;
 #pragma unroll
-      for (int bj = 0; bj < 4; ++bj) cmask |= (ccol + 16 * bj < c1) ? (1u << bj) : 0u;
-      dbl4 acc[2][4];
+      for (int bj = 0; bj < BJ; ++bj) cmask |= (ccol + 16 * bj < c1) ? (1u << bj) : 0u;
+      // the product accumulates from zero; the tile itself is read only at
+      // the end, a block row at a time (few registers in flight)
+      dbl4 acc[BI][BJ];
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
+      for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-          for (int bj = 0; bj < 4; ++bj) {
-            if (SET) {
-              acc[bi][bj][v] = 0.0;
-            } else {
-              const bool ok = ((rmask >> (4 * bi + v)) & (cmask >> bj) & 1u) != 0;
-              const double cv = A[ok ? coff + (16 * bi + 4 * v) * ld + 16 * bj : 0];
-              acc[bi][bj][v] = ok ? cv : 0.0;
-            }
-          }
+        for (int bj = 0; bj < BJ; ++bj) acc[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
       const int loff = (rt - lro + lrow) * ldl + lcol - lko;
       const int uoff = urow * ld + ct + ucol;
       unsigned lmask = 0;
 #pragma unroll
-      for (int it = 0; it < 8; ++it) lmask |= (rt + lrow + 16 * it < r1) ? (1u << it) : 0u;
+      for (int it = 0; it < LIT; ++it) lmask |= (rt + lrow + LP * it < r1) ? (1u << it) : 0u;
       const bool ucol_ok = ct + ucol < c1;
-      double pl[8], pu[8];
+      double pl[LIT], pu[UIT];
       // out-of-range elements read A[0] (always valid) and are then zeroed
       auto fetch = [&](int kc) {
         const bool lk_ok = kc + lcol < k1;
 #pragma unroll
-        for (int it = 0; it < 8; ++it) {
+        for (int it = 0; it < LIT; ++it) {
           const bool okl = lk_ok && ((lmask >> it) & 1u);
-          const bool oku = ucol_ok && kc + urow + 4 * it < k1;
-          const double vl = Lb[okl ? loff + 16 * it * ldl + kc : 0];
-          const double vu = A[oku ? uoff + (kc + 4 * it) * ld : 0];
+          const double vl = Lb[okl ? loff + LP * it * ldl + kc : 0];
           pl[it] = okl ? vl : 0.0;
+        }
+#pragma unroll
+        for (int it = 0; it < UIT; ++it) {
+          const bool oku = ucol_ok && kc + urow + UP * it < k1;
+          const double vu = A[oku ? uoff + (kc + UP * it) * ld : 0];
           pu[it] = oku ? vu : 0.0;
         }
       };
       fetch(k0);
 #pragma unroll 1
-      for (int kc = k0; kc < k1; kc += kGK) {
+      for (int kc = k0; kc < k1; kc += KC) {
 #pragma unroll
-        for (int it = 0; it < 8; ++it) {
-          lt_st[16 * it] = SET ? pl[it] : -pl[it];
-          ut_st[4 * it * (kGT + kPad)] = pu[it];
-        }
+        for (int it = 0; it < LIT; ++it) lt_st[LP * it] = SET ? pl[it] : -pl[it];
+#pragma unroll
+        for (int it = 0; it < UIT; ++it) ut_st[UP * it * (kGT + kPad)] = pu[it];
         __syncthreads();
-        if (kc + kGK < k1) fetch(kc + kGK);
+        if (kc + KC < k1) fetch(kc + KC);
 #pragma unroll
-        for (int ks = 0; ks < kGK / 4; ++ks) {
-          double a[2], b[4];
+        for (int ks = 0; ks < KC / 4; ++ks) {
+          double a[BI], b[BJ];
 #pragma unroll
-          for (int bi = 0; bi < 2; ++bi) a[bi] = lt_rd[4 * ks * (kGT + kPad) + 16 * bi];
+          for (int bi = 0; bi < BI; ++bi) a[bi] = lt_rd[4 * ks * (kGT + kPad) + 16 * bi];
 #pragma unroll
-          for (int bj = 0; bj < 4; ++bj) b[bj] = ut_rd[4 * ks * (kGT + kPad) + 16 * bj];
+          for (int bj = 0; bj < BJ; ++bj) b[bj] = ut_rd[4 * ks * (kGT + kPad) + 16 * bj];
 #pragma unroll
-          for (int bi = 0; bi < 2; ++bi)
+          for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 4; ++bj)
+            for (int bj = 0; bj < BJ; ++bj)
               acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
         }
         __syncthreads();
       }
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
+      for (int bi = 0; bi < BI; ++bi) {
+        double cv[4][BJ];
+        if (!SET) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int bj = 0; bj < BJ; ++bj) {
+              const bool ok = ((rmask >> (4 * bi + v)) & (cmask >> bj) & 1u) != 0;
+              cv[v][bj] = A[ok ? coff + (16 * bi + 4 * v) * ld + 16 * bj : 0];
+            }
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
-          for (int bj = 0; bj < 4; ++bj) {
+          for (int bj = 0; bj < BJ; ++bj) {
             const bool ok = ((rmask >> (4 * bi + v)) & (cmask >> bj) & 1u) != 0;
-            if (ok) A[coff + (16 * bi + 4 * v) * ld + 16 * bj] = acc[bi][bj][v];
+            if (ok) A[coff + (16 * bi + 4 * v) * ld + 16 * bj] = SET ? acc[bi][bj][v] : cv[v][bj] + acc[bi][bj][v];
           }
+      }
     }
   }
   __syncthreads();
 }
 
+template <int NT>
 __device__ __attribute__((always_inline)) void gemm_sub(gdouble* __restrict__ A, int ld, int r0, int r1, int c0, int c1,
                                                          int k0, int k1, GemmLds& s) {
-  gemm_op<false>(A, ld, r0, r1, c0, c1, k0, k1, A, ld, 0, 0, s);
+  gemm_op<false, NT>(A, ld, r0, r1, c0, c1, k0, k1, A, ld, 0, 0, s);
 }
 
 // Narrow update A[r0:r1, c0:c1] -= A[r0:r1, k0:k1] A[k0:k1, c0:c1] for
@@ -468,14 +487,14 @@ __device__ __attribute__((always_inline)) void apply_perm(gdouble* __restrict__ 
   for (int c0 = lo; c0 < hi; c0 += 32) {
     const bool skip_block = (c0 >= skip0 && c0 + 32 <= skip1);
     if (!skip_block) {
-      for (int idx = tid; idx < nt * 32; idx += kThreads) {
+      for (int idx = tid; idx < nt * 32; idx += (int)blockDim.x) {
         const int e = idx >> 5, c = c0 + (idx & 31);
         if (c < hi && !(c >= skip0 && c < skip1)) scratch[idx] = A[pl.rows[e] * ld + c];
       }
     }
     __syncthreads();
     if (!skip_block) {
-      for (int idx = tid; idx < nt * 32; idx += kThreads) {
+      for (int idx = tid; idx < nt * 32; idx += (int)blockDim.x) {
         const int e = idx >> 5, cc = idx & 31, c = c0 + cc;
         if (c < hi && !(c >= skip0 && c < skip1)) A[pl.rows[e] * ld + c] = scratch[(pl.src[e] << 5) + cc];
       }
@@ -1178,7 +1197,7 @@ __device__ __attribute__((always_inline)) void urow_body(const GItem& it, int K0
   const int c1 = min(LEFT ? K0 : ld, c0 + kGT);
   const int par = (K0 / kOuter) & 1;
   if (tid == 0) perm.count = W->count[par];
-  for (int e = tid; e < 2 * kOuter; e += kThreads) {
+  for (int e = tid; e < 2 * kOuter; e += (int)blockDim.x) {
     perm.rows[e] = W->rows[par][e];
     perm.src[e] = W->src[par][e];
   }
@@ -1187,9 +1206,9 @@ __device__ __attribute__((always_inline)) void urow_body(const GItem& it, int K0
   if (LEFT) return;
   // the contributions of all earlier steps to these rows (left-looking: the
   // trailing matrix is never updated as a whole)
-  if (K0 > 0) gemm_sub(A, ld, K0, K0 + kb, c0, c1, 0, K0, u.g);
+  if (K0 > 0) gemm_sub<kGemmThreads>(A, ld, K0, K0 + kb, c0, c1, 0, K0, u.g);
   // U12 = L11^-1 A12 as one MFMA product with the inverse the LEFT launch formed
-  gemm_op<true>(A, ld, K0, K0 + kb, c0, c1, K0, K0 + kb, &W->linv[par][0][0], kOuter, K0, K0, u.g);
+  gemm_op<true, kGemmThreads>(A, ld, K0, K0 + kb, c0, c1, K0, K0 + kb, &W->linv[par][0][0], kOuter, K0, K0, u.g);
 }
 
 // Row tile t of the step's panel: the contributions of all earlier steps,
@@ -1198,7 +1217,7 @@ __device__ __attribute__((always_inline)) void pupd_body(const GItem& it, int K0
   const int n = it.n;
   const int kb = min(kOuter, n - K0);
   const int ra = K0 + t * kGT;
-  gemm_sub(it.A, it.ld, ra, min(n, ra + kGT), K0, K0 + kb, 0, K0, g);
+  gemm_sub<kGemmThreads>(it.A, it.ld, ra, min(n, ra + kGT), K0, K0 + kb, 0, K0, g);
 }
 
 // Back substitution U W = R' on columns [n, n + nrhs), right-looking from the
@@ -1218,7 +1237,7 @@ __device__ __attribute__((always_inline)) void bdiag_body(const GItem& it, int k
     tri_apply<kTB>(A, ld, a0, b1 - a0, n, n + nrhs, u.t);
     if (a0 > k0) {
       if (nrhs <= kGT) strip_update(A, ld, k0, a0, n, n + nrhs, a0, b1, u.g.Lt);
-      else gemm_sub(A, ld, k0, a0, n, n + nrhs, a0, b1, u.g);
+      else gemm_sub<kThreads>(A, ld, k0, a0, n, n + nrhs, a0, b1, u.g);
     }
   }
 }
@@ -1228,7 +1247,7 @@ __device__ __attribute__((always_inline)) void bupd_body(const GItem& it, int k0
   const int n = it.n;
   const int k1 = min(n, k0 + kOuter);
   const int r0 = t * kGT;
-  gemm_sub(it.A, it.ld, r0, min(k0, r0 + kGT), n, n + it.nrhs, k0, k1, g);
+  gemm_sub<kGemmThreads>(it.A, it.ld, r0, min(k0, r0 + kGT), n, n + it.nrhs, k0, k1, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -1294,7 +1313,7 @@ __global__ __launch_bounds__(kThreads) void lu_panel_wide_kernel(const LuItem* _
 // OFF: the list's first unit is tile OFF of the matrix (the first tile and
 // the rest of a step's U-row tiles are separate launches).
 template <bool PERSISTENT, bool LEFT, int OFF = 0>
-__global__ __launch_bounds__(kThreads) void lu_urow_kernel(const LuItem* __restrict__ items,
+__global__ __launch_bounds__(LEFT ? kThreads : kGemmThreads) __attribute__((amdgpu_waves_per_eu(2))) void lu_urow_kernel(const LuItem* __restrict__ items,
                                                            const int32_t* __restrict__ pre, int count, int step) {
   __shared__ MatLds u;
   __shared__ PermLds perm;
@@ -1314,7 +1333,7 @@ __global__ __launch_bounds__(kThreads) void lu_urow_kernel(const LuItem* __restr
 }
 
 template <bool PERSISTENT>
-__global__ __launch_bounds__(kThreads) void lu_pupd_kernel(
+__global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(2))) void lu_pupd_kernel(
     const LuItem* __restrict__ items, const int32_t* __restrict__ pre, int count, int step) {
   __shared__ GemmLds g;
   const int total = pre[count];
@@ -1341,7 +1360,7 @@ __global__ __launch_bounds__(kThreads) void lu_bdiag_kernel(const LuItem* __rest
 }
 
 template <bool PERSISTENT>
-__global__ __launch_bounds__(kThreads) void lu_bupd_kernel(const LuItem* __restrict__ items,
+__global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(2))) void lu_bupd_kernel(const LuItem* __restrict__ items,
                                                            const int32_t* __restrict__ pre, int count, int step) {
   __shared__ GemmLds g;
   const int total = pre[count];
@@ -1441,13 +1460,15 @@ int LuPlan::launch(hipStream_t st, int grid_cap, bool lookahead) const {
   auto go = [&](int kind, int s, Kern flat, Kern strided, hipStream_t q) {
     const int total = totals[(size_t)kind * nsteps + s];
     if (total == 0) return;
+    const bool gemm = kind == LU_PUPD || kind == LU_UROW0 || kind == LU_UREST || kind == LU_BUPD;
+    const int nthr = gemm ? kGemmThreads : kThreads;
     const int32_t* dp = d_pre.ptr<int32_t>() + ((size_t)kind * nsteps + s) * (count + 1);
     if (strided && grid_cap < total)
-      hipLaunchKernelGGL(strided, dim3(grid_cap), dim3(kThreads), 0, q, di, dp, count, s);
+      hipLaunchKernelGGL(strided, dim3(grid_cap), dim3(nthr), 0, q, di, dp, count, s);
     else if (strided)   // flat tiled launch: grid padded to a multiple of the 8 XCDs
-      hipLaunchKernelGGL(flat, dim3((total + 7) / 8 * 8), dim3(kThreads), 0, q, di, dp, count, s);
+      hipLaunchKernelGGL(flat, dim3((total + 7) / 8 * 8), dim3(nthr), 0, q, di, dp, count, s);
     else
-      hipLaunchKernelGGL(flat, dim3(total), dim3(kThreads), 0, q, di, dp, count, s);
+      hipLaunchKernelGGL(flat, dim3(total), dim3(nthr), 0, q, di, dp, count, s);
     ++launches;
   };
   // Look-ahead: the first U-row tile of step s (the columns of panel s + 1)
