@@ -520,6 +520,28 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// Wavefront maximum of a 32-bit unsigned value, in every lane: DPP maxima
+// inside each row of 16 lanes, then row_bcast15 / row_bcast31 carry the row
+// maxima into lane 63.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xb1, 0xf, 0xf, false));   // quad_perm [1,0,3,2]
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4e, 0xf, 0xf, false));   // quad_perm [2,3,0,1]
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false));  // row_half_mirror
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false));  // row_mirror
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast15
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast31
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Wavefront maximum of a 64-bit unsigned value: the high words, then the low
+// words of the lanes whose high word is the maximum.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+  const unsigned hi = (unsigned)(v >> 32), lo = (unsigned)v;
+  const unsigned mh = wave_max_u32(hi);
+  const unsigned ml = wave_max_u32(hi == mh ? lo : 0u);
+  return ((unsigned long long)mh << 32) | ml;
+}
+
 __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_f64<0xb1>(v));    // quad_perm [1, 0, 3, 2]
   v = fmax(v, dpp_f64<0x4e>(v));    // quad_perm [2, 3, 0, 1]
@@ -754,7 +776,7 @@ struct OwnLds {
   union {
     struct {                                   // column factorisation
       double cand[2][kOwnMax / kWave][kTB];   // each wavefront's best candidate row
-      double cv[2][kOwnMax / kWave];
+      unsigned long long ckey[2][kOwnMax / kWave];
       int cpos[2][kOwnMax / kWave];
       int crow[2][kOwnMax / kWave];
     } f;
@@ -770,32 +792,79 @@ struct OwnLds {
   int prow[kTB];                               // physical rows (- K0) of the group's pivots
 };
 
-// Both inverses of the kTB x kTB block in t.blk (identity-padded beyond w):
-// t.inv <- (unit lower)^-1, t.inv2 <- (upper with diagonal)^-1.  Lanes 0..31
-// of wavefront 0 take the lower triangle and 32 lanes of wavefront 1 (of
-// wavefront 0 when it is alone) the upper one, in reversed index order so
-// that both run the same forward substitution.  Ends with a barrier.
-__device__ __attribute__((always_inline)) void own_block_inverses(int w, TriLds& t, int nw) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const bool lo = wv == 0 && lane < kTB;
-  const int uw = nw > 1 ? 1 : 0, ul0 = nw > 1 ? 0 : kTB;
-  const bool up = wv == uw && lane >= ul0 && lane < ul0 + kTB;
-  if (lo || up) {
+typedef __attribute__((address_space(3))) double ldouble;
+
+// An LDS address the compiler treats as opaque: a per-lane choice between
+// two LDS arrays would otherwise be folded into every access as a pair of
+// constants (one register each).
+__device__ __forceinline__ ldouble* opaque_lds(ldouble* p) {
+  uint32_t a = (uint32_t)(size_t)p;
+  __asm__ volatile("" : "+v"(a));
+  return (ldouble*)(size_t)a;
+}
+
+// Step K of the register-resident triangular inverse (below).  Empty asm
+// statements pin the order: every x_i of step K passes through one after its
+// product, and the base address of B through one after them, so the loads
+// of step K + 1 are issued only after the products of step K (left alone,
+// the compiler issues all loads at once and spills their results).
+template <int K>
+__device__ __attribute__((always_inline)) void inv_step(double (&x)[kTB], const ldouble*& bb, bool lo) {
+  constexpr int R = kTB + 1;
+  // (division by one, exact, in the lower half: no branch)
+  x[K] = x[K] / (lo ? 1.0 : bb[R * K + K]);
+  // chunks of 8 products, each chunk's loads issued after the previous
+  // chunk's products
+#pragma unroll
+  for (int i0 = K + 1; i0 < kTB; i0 += 8) {
+    const ldouble* __restrict__ b = bb;
+#pragma unroll
+    for (int i = i0; i < i0 + 8 && i < kTB; ++i) x[i] -= b[R * i + K] * x[K];
+#pragma unroll
+    for (int i = i0; i < i0 + 8 && i < kTB; ++i) __asm__ volatile("" : "+v"(x[i]));
+    uint32_t a = (uint32_t)(size_t)bb;
+    __asm__ volatile("" : "+v"(a));
+    bb = (const ldouble*)(size_t)a;
+  }
+}
+
+template <int... Ks>
+__device__ __attribute__((always_inline)) void inv_steps(std::integer_sequence<int, Ks...>, double (&x)[kTB],
+                                                          const ldouble* bb, bool lo) {
+  (inv_step<Ks>(x, bb, lo), ...);
+}
+
+// Both inverses of the kTB x kTB block in t.blk (identity-padded beyond w,
+// and held reversed, t.inv2[i][k] = t.blk[31 - i][31 - k], on entry):
+// t.inv <- (unit lower)^-1, t.inv2 <- (upper with diagonal)^-1, by
+// wavefront 0: lane j < 32 forms column j of the lower inverse from t.blk,
+// lane 32 + j column j of the upper one in reversed index order from the
+// reversed copy, so that both run the same forward substitution with the
+// same LDS offsets (the upper result overwrites the copy after every read
+// of it: one wavefront runs in order).  The column is held in registers
+// and updated right-looking -- x_i -= B(i, k) x_k for every i > k as soon as
+// x_k is final -- which subtracts the same terms in the same order as the
+// row-by-row form, so the result is identical while the chain between
+// successive x_k is one product.  Ends with a barrier.
+__device__ __attribute__((always_inline)) void own_block_inverses(int w, TriLds& t) {
+  const int tid = threadIdx.x;
+  if (tid < 2 * kTB) {
     constexpr int R = kTB + 1;               // row stride of the LDS blocks
-    const int j = lo ? lane : lane - ul0;
-    // B(i, k) = blk[o + s i + s k / R ...]: lower: blk[i][k]; upper: blk[31 - i][31 - k]
-    const double* bb = lo ? &t.blk[0][0] : &t.blk[kTB - 1][kTB - 1];
-    const int bs = lo ? 1 : -1;
-    double* xx = lo ? &t.inv[0][j] : &t.inv2[kTB - 1][j];
-    const int target = lo ? j : kTB - 1 - j;
-#pragma unroll 1
-    for (int i = 0; i < kTB; ++i) {
-      double v = (i == target) ? 1.0 : 0.0;
-      const double* brow = bb + bs * R * i;
-#pragma unroll 8
-      for (int k = 0; k < i; ++k) v -= brow[bs * k] * xx[bs * R * k];
-      xx[bs * R * i] = lo ? v : v / brow[bs * i];
-    }
+    const bool lo = tid < kTB;
+    const int j = tid & (kTB - 1);
+    const int sg = lo ? 1 : -1;
+    // B(i, k) = bb[R i + k]: lower blk[i][k], upper blk[31 - i][31 - k]
+    const ldouble* __restrict__ bb = opaque_lds(lo ? (ldouble*)&t.blk[0][0] : (ldouble*)&t.inv2[0][0]);
+    int target = lo ? j : kTB - 1 - j;
+    __asm__ volatile("" : "+v"(target));     // (or the start columns are hoisted out of the group loop and spilled)
+    double x[kTB];
+#pragma unroll
+    for (int i = 0; i < kTB; ++i) x[i] = (i == target) ? 1.0 : 0.0;
+    inv_steps(std::make_integer_sequence<int, kTB>{}, x, bb, lo);
+    // lower: inv[i][j] = x_i; upper: inv2[31 - i][j] = x_i
+    ldouble* xo = opaque_lds(lo ? (ldouble*)&t.inv[0][j] : (ldouble*)&t.inv2[kTB - 1][j]);
+#pragma unroll
+    for (int i = 0; i < kTB; ++i) xo[sg * R * i] = x[i];
 #pragma unroll 1
     for (int i = 0; i < kTB; ++i)
       if (i >= w || j >= w) (lo ? t.inv : t.inv2)[i][j] = 0.0;
@@ -814,9 +883,13 @@ __device__ __attribute__((always_inline)) void own_column(double (&P)[kTB], int&
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int cr = g0r + C, buf = C & 1;
   const bool cand = own && pos >= cr;
+  // the candidate's key: the bits of |P[C]|, which order as unsigned
+  // integers as the magnitudes do; NaN (never a pivot) and rows that are not
+  // candidates have key 0
   const double a = fabs(P[C]);
-  const double wmax = wave_max(cand ? a : -1.0);
-  const unsigned long long msk = __ballot(cand && a == wmax);
+  const unsigned long long key = (cand && a == a) ? (unsigned long long)__double_as_longlong(a) : 0ull;
+  const unsigned long long wkey = wave_max_u64(key);
+  const unsigned long long msk = __ballot(cand && key == wkey);
   int wl = -1;
   if (msk != 0ull) {
     wl = __builtin_ctzll(msk);
@@ -832,23 +905,26 @@ __device__ __attribute__((always_inline)) void own_column(double (&P)[kTB], int&
   if (lane == wl) {
 #pragma unroll
     for (int cc = C; cc < kTB; ++cc) sh.u.f.cand[buf][w][cc] = P[cc];
-    sh.u.f.cv[buf][w] = a;
+    sh.u.f.ckey[buf][w] = key;
     sh.u.f.cpos[buf][w] = pos;
     sh.u.f.crow[buf][w] = tid;
   }
-  if (wl < 0 && lane == 0) sh.u.f.cv[buf][w] = -1.0;
+  if (wl < 0 && lane == 0) {                 // no candidate in this wavefront
+    sh.u.f.ckey[buf][w] = 0ull;
+    sh.u.f.cpos[buf][w] = 0x7fffffff;
+  }
   __syncthreads();
   // the workgroup's pivot: lane v reads wavefront v's record, then the same
   // maximum / lowest-position selection across the lanes
   // (the three records are read at once, in bounds for every lane, and
   // masked afterwards)
   const int vl = lane & (kOwnMax / kWave - 1);
-  const double ov_raw = sh.u.f.cv[buf][vl];
+  const unsigned long long okey_raw = sh.u.f.ckey[buf][vl];
   const int opos_raw = sh.u.f.cpos[buf][vl];
   const int orow = sh.u.f.crow[buf][vl];
-  const double ov = lane < nw ? ov_raw : -1.0;
-  const double gv = wave_max(ov);
-  const unsigned long long gm = __ballot(lane < nw && ov == gv);
+  const unsigned long long okey = lane < nw ? okey_raw : 0ull;
+  const unsigned long long gkey = wave_max_u64(okey);
+  const unsigned long long gm = __ballot(lane < nw && okey == gkey);
   int gwv = gm ? __builtin_ctzll(gm) : 0;
   const int opos = lane < nw ? opos_raw : 0x7fffffff;
   int gp = __builtin_amdgcn_readlane(opos, gwv);
@@ -859,7 +935,7 @@ __device__ __attribute__((always_inline)) void own_column(double (&P)[kTB], int&
       if (p < gp) { gp = p; gwv = l; }
     }
   }
-  const bool ok = gv > 0.0;                  // uniform
+  const bool ok = gkey != 0ull;              // uniform: a nonzero pivot exists
   if (!ok) singular = 1;
   const int ppos = ok ? gp : cr;
   const bool is_piv = ok ? tid == __builtin_amdgcn_readlane(orow, gwv) : (own && pos == cr);
@@ -896,6 +972,58 @@ __device__ __attribute__((always_inline)) void own_columns(std::integer_sequence
   (own_column<Cs>(P, pos, singular, gw, g0r, K0, piv, own, live, wrow, nw, sh), ...);
 }
 
+// The rows r < m of the panel at positions >= plive take
+// A[K0 + r, c0:c0+wt] -= A[K0 + r, g0:g0+kTB] U12 (U12 in sh.u.S), in
+// 16-row strips per wavefront; CB = ceil(wt / 16) column blocks, a
+// compile-time count so that the MFMA sequence has no branches.  Every load
+// of a strip is issued at once; entries outside the block read A[0] and are
+// never stored (each output entry depends only on its own input entry).
+template <int CB>
+__device__ __attribute__((always_inline)) void own_trailing(gdouble* __restrict__ A, int ld, int K0, int m, int g0,
+                                                            int c0, int wt, int plive, OwnLds& sh) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = (int)blockDim.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll 1
+  for (int rs = 16 * w; rs < m; rs += 16 * nw) {
+    const bool aok = rs + li < m && sh.pos[rs + li] >= plive;
+    if (__ballot(aok) == 0ull) continue;
+    double a[kTB / 4];
+#pragma unroll
+    for (int ks = 0; ks < kTB / 4; ++ks) {
+      const double v = A[aok ? (size_t)(K0 + rs + li) * ld + g0 + 4 * ks + lk : 0];
+      a[ks] = aok ? -v : 0.0;
+    }
+    unsigned rmask = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = rs + 4 * v + lk;
+      rmask |= (r < m && sh.pos[r] >= plive) ? (1u << v) : 0u;
+    }
+    const size_t cbase = (size_t)(K0 + rs + lk) * ld + c0 + li;
+    dbl4 acc[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const bool ok = ((rmask >> v) & 1u) && 16 * cb + li < wt;
+        acc[cb][v] = A[ok ? cbase + (size_t)(4 * v) * ld + 16 * cb : 0];
+      }
+#pragma unroll
+    for (int ks = 0; ks < kTB / 4; ++ks) {
+      double b[CB];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) b[cb] = sh.u.S[4 * ks + lk][16 * cb + li];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[cb], acc[cb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (((rmask >> v) & 1u) && 16 * cb + li < wt) A[cbase + (size_t)(4 * v) * ld + 16 * cb] = acc[cb][v];
+  }
+}
+
 __device__ __attribute__((always_inline)) void panel_own_body(const GItem& it, int K0, OwnLds& sh) {
   gdouble* __restrict__ A = it.A;
   const int n = it.n, ld = it.ld;
@@ -928,14 +1056,22 @@ __device__ __attribute__((always_inline)) void panel_own_body(const GItem& it, i
     if (own && pos >= g0r && pos < g0r + gw) {
       const int i = pos - g0r;
 #pragma unroll
-      for (int c = 0; c < kTB; ++c) sh.u.t.blk[i][c] = c < gw ? wrow[c] : 0.0;
+      for (int c = 0; c < kTB; ++c) {
+        const double v = c < gw ? wrow[c] : 0.0;
+        sh.u.t.blk[i][c] = v;
+        sh.u.t.inv2[kTB - 1 - i][kTB - 1 - c] = v;
+      }
       sh.prow[i] = tid;
     }
-    for (int idx = gw * kTB + tid; idx < kTB * kTB; idx += nthr)
-      sh.u.t.blk[idx >> 5][idx & 31] = ((idx >> 5) == (idx & 31)) ? 1.0 : 0.0;
+    for (int idx = gw * kTB + tid; idx < kTB * kTB; idx += nthr) {
+      const int i = idx >> 5, c = idx & 31;
+      const double v = i == c ? 1.0 : 0.0;
+      sh.u.t.blk[i][c] = v;
+      sh.u.t.inv2[kTB - 1 - i][kTB - 1 - c] = v;
+    }
     if (own) sh.pos[tid] = (short)pos;
     __syncthreads();
-    own_block_inverses(gw, sh.u.t, nw);
+    own_block_inverses(gw, sh.u.t);
     for (int idx = tid; idx < kTB * kTB; idx += nthr) {
       it.uinv[(g0 / kTB) * kTB * kTB + idx] = sh.u.t.inv2[idx >> 5][idx & 31];
       W->inv[gi][idx >> 5][idx & 31] = sh.u.t.inv[idx >> 5][idx & 31];
@@ -978,53 +1114,16 @@ __device__ __attribute__((always_inline)) void panel_own_body(const GItem& it, i
           }
       }
       __syncthreads();
-      // ... and the rows not yet pivoted take A[r, c0:] -= L[r, group] U12,
-      // 16-row strips per wavefront, every load of a strip issued at once
-      // (pivoted rows are left untouched)
-      const int plive = g0r + gw, KS = (gw + 3) >> 2, CB = (wt + 15) >> 4;
-#pragma unroll 1
-      for (int rs = 16 * w; rs < m; rs += 16 * nw) {
-        const bool aok = rs + li < m && sh.pos[rs + li] >= plive;
-        if (__ballot(aok) == 0ull) continue;
-        double a[kTB / 4];
-#pragma unroll
-        for (int ks = 0; ks < kTB / 4; ++ks) {
-          const bool ok = aok && ks < KS && 4 * ks + lk < gw;
-          const double v = A[ok ? (size_t)(K0 + rs + li) * ld + g0 + 4 * ks + lk : 0];
-          a[ks] = ok ? -v : 0.0;
-        }
-        unsigned rmask = 0;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = rs + 4 * v + lk;
-          rmask |= (r < m && sh.pos[r] >= plive) ? (1u << v) : 0u;
-        }
-        const size_t cbase = (size_t)(K0 + rs + lk) * ld + c0 + li;
-        // entries outside the block read A[0] and are never stored (each
-        // output entry depends only on its own input entry)
-        dbl4 acc[kSW / 16];
-#pragma unroll
-        for (int cb = 0; cb < kSW / 16; ++cb)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const bool ok = cb < CB && ((rmask >> v) & 1u) && 16 * cb + li < wt;
-            acc[cb][v] = A[ok ? cbase + (size_t)(4 * v) * ld + 16 * cb : 0];
-          }
-#pragma unroll
-        for (int ks = 0; ks < kTB / 4; ++ks) {
-          if (ks < KS) {
-#pragma unroll
-            for (int cb = 0; cb < kSW / 16; ++cb)
-              if (cb < CB)
-                acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], sh.u.S[4 * ks + lk][16 * cb + li], acc[cb], 0,
-                                                               0, 0);
-          }
-        }
-#pragma unroll
-        for (int cb = 0; cb < kSW / 16; ++cb)
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            if (cb < CB && ((rmask >> v) & 1u) && 16 * cb + li < wt) A[cbase + (size_t)(4 * v) * ld + 16 * cb] = acc[cb][v];
+      // ... and the rows not yet pivoted take A[r, c0:] -= L[r, group] U12
+      // (a group with trailing columns is always kTB wide)
+      const int CB = (wt + 15) >> 4;
+      switch (CB) {
+        case 1: own_trailing<1>(A, ld, K0, m, g0, c0, wt, g0r + gw, sh); break;
+        case 2: own_trailing<2>(A, ld, K0, m, g0, c0, wt, g0r + gw, sh); break;
+        case 3: own_trailing<3>(A, ld, K0, m, g0, c0, wt, g0r + gw, sh); break;
+        case 4: own_trailing<4>(A, ld, K0, m, g0, c0, wt, g0r + gw, sh); break;
+        case 5: own_trailing<5>(A, ld, K0, m, g0, c0, wt, g0r + gw, sh); break;
+        default: own_trailing<6>(A, ld, K0, m, g0, c0, wt, g0r + gw, sh); break;
       }
       __syncthreads();
     }
@@ -1036,8 +1135,10 @@ __device__ __attribute__((always_inline)) void panel_own_body(const GItem& it, i
   for (int g0r = 0; g0r < kb; g0r += kTB) {
     const int gw = min(kTB, kb - g0r);
     double P[kTB];
+    if (moved) {
 #pragma unroll
-    for (int c = 0; c < kTB; ++c) P[c] = arow[K0 + g0r + min(c, gw - 1)];
+      for (int c = 0; c < kTB; ++c) P[c] = arow[K0 + g0r + min(c, gw - 1)];
+    }
     __syncthreads();
     if (moved) {
       gdouble* __restrict__ wr = A + (size_t)(K0 + pos) * ld + K0 + g0r;
