@@ -101,7 +101,7 @@ struct DeviceCover {
   // contiguous knot range starting at blk_so[i]; blk_circ_rows lists the rows
   // of each circle (offsets blk_circ_off), which are the only rows whose
   // stencils hold that circle's knots.
-  DevBuf blk_so, blk_circ_off, blk_circ_rows;
+  DevBuf blk_so, blk_circ_off, blk_circ_rows, blk_circ_roff;   // blk_circ_roff: rowptr[i] - i per slot
   bool have_blocked = false;
   bool blocked_ok = false;
   bool tuned = false;                   // schedule chosen by the autotuner for this cover

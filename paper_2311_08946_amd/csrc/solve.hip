@@ -11,18 +11,20 @@
 // per row -- the stencil entries in knot order at rowptr[i] - i, the diagonal
 // apart -- so that a product reads 8 bytes per entry and no column indices:
 //   C x   : a 16-lane group per row, y_i = C_ii x_i + sum_j V_ij x[so_i + j],
-//           the gathers from x contiguous;
+//           the gathers from x contiguous; a wavefront takes 64 consecutive
+//           rows, their metadata in one round trip, and keeps the loads of
+//           16 rows in flight;
 //   C^T x : a wavefront per circle m, its lanes over the knots j of m,
 //           y_j = C_jj x_j + sum_{rows i of m} V_ij x_i, each row's entries
-//           one coalesced load and x_i one scalar load -- no atomics and no
-//           transposed copy.
+//           one coalesced load (16 rows' loads in flight) and x_i broadcast
+//           from the lane that loaded it -- no atomics and no transposed copy.
 // Rows of the averaged rule (eqs. 38-39) hold several stencils; those systems
 // keep the CSR form (and a transposed CSR copy for C^T).
 //
-// One iteration is four launches: p = r + beta (p - omega v); v = A p with
-// per-workgroup partial sums of (r0, v); t = A s with s = r - alpha v formed on
-// the fly and partial sums of (t, s), (t, t); the x and r updates with partial
-// sums of (r, r) and (r0, r).  Every kernel runs on a fixed grid of kGrid
+// One iteration is five launches: p = r + beta (p - omega v); v = A p with
+// per-workgroup partial sums of (r0, v); s = r - alpha v, stored over r; t = A s
+// with partial sums of (t, s), (t, t); the x and r updates with partial sums
+// of (r, r) and (r0, r).  Every kernel runs on a fixed grid of kGrid
 // workgroups striding over its rows or circles, and each workgroup first adds
 // the kGrid partial sums of the kernel before it -- every workgroup the same
 // partials in the same fixed order, so all derive the same scalars (alpha,
@@ -70,6 +72,7 @@ struct SolveCtx {
   const int64_t* knot_off; // OP_CIRCLES: knots of circle m are [knot_off[m], knot_off[m + 1])
   const int64_t* circ_off; // OP_CIRCLES: rows of circle m are circ_rows[circ_off[m] ..)
   const int32_t* circ_rows;
+  const int64_t* circ_roff; // OP_CIRCLES: rowptr[i] - i of the row at each circ_rows slot
   int32_t nc;
   int64_t N;
   double* x;
@@ -112,6 +115,7 @@ __device__ __forceinline__ double sum_parts(const double* __restrict__ part, dou
 // The input vector of a product: y (ALPHA = false) or y - alpha z.
 template <bool ALPHA>
 struct In {
+  static constexpr bool kTwoLoads = ALPHA;
   const double* y;
   const double* z;
   double alpha;
@@ -123,6 +127,11 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ int64_t shfl_i64(int64_t v, int l) {
+  const int lo = __shfl((int)v, l, 64), hi = __shfl((int)(v >> 32), l, 64);
+  return ((int64_t)hi << 32) | (unsigned)lo;
 }
 
 __device__ __forceinline__ int64_t readlane_i64(int64_t v, int l) {
@@ -138,7 +147,8 @@ __device__ __forceinline__ void apply_op(const SolveCtx& c, const X& in, Sink& s
   if (OPK == OP_CIRCLES) {
     // circle m: lanes over its knots j; its rows' offsets and inputs are
     // staged one per lane (64 rows at a time) and broadcast by readlane, so
-    // the loop issues only the coalesced loads of the rows' entries
+    // the loop issues only the coalesced loads of the rows' entries, sixteen
+    // rows' loads at a time
     const int lane = tid & 63;
     for (int m = blockIdx.x * (kThreads / 64) + (tid >> 6); m < c.nc; m += gridDim.x * (kThreads / 64)) {
       const int64_t s0 = c.knot_off[m], s1 = c.knot_off[m + 1];
@@ -146,18 +156,30 @@ __device__ __forceinline__ void apply_op(const SolveCtx& c, const X& in, Sink& s
       for (int64_t jb = s0; jb < s1; jb += 64) {
         const int64_t j = jb + lane;
         const bool ok = j < s1;
-        const int64_t jl = j - s0;
         double a0 = 0.0, a1 = 0.0;
         for (int64_t qb = q0; qb < q1; qb += 64) {
           const int cnt = (int)min((int64_t)64, q1 - qb);
           int64_t off = 0;
           double xi = 0.0;
           if (lane < cnt) {
-            const int32_t i = c.circ_rows[qb + lane];
-            off = c.rowptr[i] - i + (jb - s0);      // the row's entries of this chunk of knots
-            xi = in(i);
+            off = c.circ_roff[qb + lane] + (jb - s0);   // the row's entries of this chunk of knots
+            xi = in(c.circ_rows[qb + lane]);
           }
           int q = 0;
+          for (; q + 16 <= cnt; q += 16) {
+            double v[16], x[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+              const int64_t o = readlane_i64(off, q + u);
+              x[u] = readlane_f64(xi, q + u);
+              v[u] = ok ? c.vblk[o + lane] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 16; u += 2) {
+              a0 += v[u] * x[u];
+              a1 += v[u + 1] * x[u + 1];
+            }
+          }
           for (; q + 4 <= cnt; q += 4) {
             double v[4], x[4];
 #pragma unroll
@@ -182,37 +204,86 @@ __device__ __forceinline__ void apply_op(const SolveCtx& c, const X& in, Sink& s
     }
     return;
   }
+  if (OPK == OP_ROWS) {
+    // chunks of 64 consecutive rows per wavefront: the rows' metadata one per
+    // lane (one round trip), then batches of 16 rows -- a 16-lane group per
+    // row, four rows per group -- with every load of a batch issued at once
+    const int lane = tid & 63, sub = lane & (kLanes - 1), grp = lane / kLanes;
+    const int64_t wv = (int64_t)blockIdx.x * (kThreads / 64) + (tid >> 6);
+    const int64_t nwv = (int64_t)gridDim.x * (kThreads / 64);
+    for (int64_t r0 = wv * 64; r0 < c.N; r0 += nwv * 64) {
+      const int64_t ri = r0 + lane;
+      int64_t lo = 0, so = 0;
+      int len = 0;
+      double dterm = 0.0;
+      if (ri < c.N) {
+        const int64_t a = c.rowptr[ri], b = c.rowptr[ri + 1];
+        lo = a - ri;
+        len = (int)(b - a - 1);
+        so = c.so[ri];
+        dterm = c.dg[ri] * in(ri);
+      }
+      // (inputs formed from two vectors: half the rows per batch, so that
+      // the loads in flight fit in registers)
+      constexpr int NP = X::kTwoLoads ? 1 : 2;
+#pragma unroll 1
+      for (int bt = 0; bt < 64; bt += 4 * NP) {
+        int64_t lo_p[NP], so_p[NP];
+        int len_p[NP];
+        double acc[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {           // the group's row of pass p: bt + 4 p + grp
+          const int rr = bt + 4 * p + grp;
+          lo_p[p] = shfl_i64(lo, rr);
+          so_p[p] = shfl_i64(so, rr);
+          len_p[p] = __shfl(len, rr, 64);
+        }
+        // four entries per lane per row, every load issued before the products
+        for (int jb = 0;; jb += 4 * kLanes) {
+          double v[NP][4], x[NP][4];
+#pragma unroll
+          for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int j = jb + sub + kLanes * u;
+              const bool okj = j < len_p[p];
+              v[p][u] = okj ? c.vblk[lo_p[p] + j] : 0.0;
+              x[p][u] = okj ? in(so_p[p] + j) : 0.0;
+            }
+#pragma unroll
+          for (int p = 0; p < NP; ++p) {
+            double a = jb == 0 ? 0.0 : acc[p];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a += v[p][u] * x[p][u];
+            acc[p] = a;
+          }
+          int lmax = 0;
+#pragma unroll
+          for (int p = 0; p < NP; ++p) lmax = max(lmax, len_p[p]);
+          if (!__any(jb + 4 * kLanes < lmax)) break;    // rows longer than 64 entries are rare
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          double a = acc[p];
+          for (int o = kLanes / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, kLanes);
+          const int rr = bt + 4 * p + grp;
+          const double dt = __shfl(dterm, rr, 64);
+          if (sub == 0 && r0 + rr < c.N) sink(r0 + rr, dt + a);
+        }
+      }
+    }
+    return;
+  }
   const int sub = tid & (kLanes - 1);
   for (int64_t base = (int64_t)blockIdx.x * kRowsPerPass; base < c.N; base += (int64_t)gridDim.x * kRowsPerPass) {
     const int64_t i = base + tid / kLanes;
     double acc = 0.0;
     if (i < c.N) {                           // uniform within the row's lanes
-      if (OPK == OP_CSR) {
-        const int64_t lo = c.rowptr[i], hi = c.rowptr[i + 1];
-        for (int64_t k = lo + sub; k < hi; k += kLanes) acc += c.val[k] * in(c.cols[k]);
-      } else {
-        const int64_t lo = c.rowptr[i] - i, len = c.rowptr[i + 1] - c.rowptr[i] - 1;
-        const int64_t so = c.so[i];
-        // four entries per lane per pass, every load issued before the products
-        for (int64_t jb = 0; jb < len; jb += 4 * kLanes) {
-          double v[4], x[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int64_t j = jb + sub + kLanes * u;
-            v[u] = 0.0;
-            x[u] = 0.0;
-            if (j < len) {
-              v[u] = c.vblk[lo + j];
-              x[u] = in(so + j);
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) acc += v[u] * x[u];
-        }
-      }
+      const int64_t lo = c.rowptr[i], hi = c.rowptr[i + 1];
+      for (int64_t k = lo + sub; k < hi; k += kLanes) acc += c.val[k] * in(c.cols[k]);
     }
     for (int off = kLanes / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanes);
-    if (sub == 0 && i < c.N) sink(i, OPK == OP_CSR ? acc : c.dg[i] * in(i) + acc);
+    if (sub == 0 && i < c.N) sink(i, acc);
   }
 }
 
@@ -336,9 +407,10 @@ __global__ __launch_bounds__(kThreads) void spmv_v_kernel(SolveCtx c) {
   if (threadIdx.x == 0) c.part_v[blockIdx.x] = sv;
 }
 
-// alpha = rho / (r0, v); t = A s with s = r - alpha v, partial sums of (t, s) and (t, t)
-template <int OPK>
-__global__ __launch_bounds__(kThreads) void spmv_t_kernel(SolveCtx c) {
+// alpha = rho / (r0, v); s = r - alpha v, stored in place of r (r itself is
+// not needed again: the update forms the next r from s), so that the product
+// t = A s gathers one vector
+__global__ __launch_bounds__(kThreads) void form_s_kernel(SolveCtx c) {
   __shared__ double s4[4];
   if (c.sc[S_DONE] != 0.0) return;
   const double rv = sum_parts(c.part_v, s4);
@@ -347,17 +419,25 @@ __global__ __launch_bounds__(kThreads) void spmv_t_kernel(SolveCtx c) {
     c.sc[S_RV] = rv;
     c.sc[S_ALPHA] = alpha;
   }
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < c.N; i += (int64_t)gridDim.x * kThreads)
+    c.r[i] = c.r[i] - alpha * c.v[i];
+}
+
+// t = A s (s in r), partial sums of (t, s) and (t, t)
+template <int OPK>
+__global__ __launch_bounds__(kThreads) void spmv_t_kernel(SolveCtx c) {
+  __shared__ double s4[4];
+  if (c.sc[S_DONE] != 0.0) return;
   struct Sink {
     const SolveCtx& c;
-    double alpha, pts, ptt;
+    double pts, ptt;
     __device__ void operator()(int64_t i, double y) {
       c.t[i] = y;
-      const double si = c.r[i] - alpha * c.v[i];
-      pts += y * si;
+      pts += y * c.r[i];
       ptt += y * y;
     }
-  } sink{c, alpha, 0.0, 0.0};
-  apply_op<OPK>(c, In<true>{c.r, c.v, alpha}, sink);
+  } sink{c, 0.0, 0.0};
+  apply_op<OPK>(c, In<false>{c.r, nullptr, 0.0}, sink);
   const double sts = block_sum(sink.pts, s4);
   const double stt = block_sum(sink.ptt, s4);
   if (threadIdx.x == 0) {
@@ -366,8 +446,8 @@ __global__ __launch_bounds__(kThreads) void spmv_t_kernel(SolveCtx c) {
   }
 }
 
-// omega = (t, s) / (t, t); x += alpha p + omega s; r = s - omega t; partial
-// sums of (r, r) and (r0, r)
+// omega = (t, s) / (t, t); x += alpha p + omega s; r = s - omega t (s in r);
+// partial sums of (r, r) and (r0, r)
 __global__ __launch_bounds__(kThreads) void update_xr_kernel(SolveCtx c) {
   __shared__ double s4[4];
   if (c.sc[S_DONE] != 0.0) return;
@@ -383,7 +463,7 @@ __global__ __launch_bounds__(kThreads) void update_xr_kernel(SolveCtx c) {
   }
   double prr = 0.0, prho = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < c.N; i += (int64_t)gridDim.x * kThreads) {
-    const double si = c.r[i] - alpha * c.v[i];
+    const double si = c.r[i];
     c.x[i] = c.x[i] + alpha * c.p[i] + omega * si;
     const double ri = si - omega * c.t[i];
     c.r[i] = ri;
@@ -535,12 +615,18 @@ void ensure_blocked(pdd_cover cover) {
   if (ok) {
     for (int32_t m = 0; m < H.nc; ++m) coff[m + 1] += coff[m];
     std::vector<int32_t> rows(coff[H.nc]);
+    std::vector<int64_t> roff(coff[H.nc]);
     std::vector<int64_t> fill(coff.begin(), coff.end() - 1);
     for (int64_t i = 0; i < N; ++i)
-      if (H.assigned[i] >= 0) rows[fill[H.assigned[i]]++] = (int32_t)i;
+      if (H.assigned[i] >= 0) {
+        const int64_t q = fill[H.assigned[i]]++;
+        rows[q] = (int32_t)i;
+        roff[q] = H.rowptr[i] - i;
+      }
     D.blk_so.upload(so);
     D.blk_circ_off.upload(coff);
     D.blk_circ_rows.upload(rows);
+    D.blk_circ_roff.upload(roff);
   }
   D.blocked_ok = ok;
   D.have_blocked = true;
@@ -611,6 +697,7 @@ void bind(SolveCtx& c, pdd_system sys, bool transpose, double* u, double* w) {
     c.knot_off = D.knot_off.ptr<int64_t>();
     c.circ_off = D.blk_circ_off.ptr<int64_t>();
     c.circ_rows = D.blk_circ_rows.ptr<int32_t>();
+    c.circ_roff = D.blk_circ_roff.ptr<int64_t>();
     c.nc = sys->cover->H.nc;
   } else {
     c.kind = OP_CSR;
@@ -638,6 +725,7 @@ void launch_iterations(const SolveCtx& c, hipStream_t st, int first, int count, 
   for (int k = 0; k < count; ++k) {
     hipLaunchKernelGGL(update_p_kernel, dim3(kGrid), dim3(kThreads), 0, st, c, k == 0 ? first : 0, rtol);
     hipLaunchKernelGGL(spmv_v_kernel<OPK>, dim3(kGrid), dim3(kThreads), 0, st, c);
+    hipLaunchKernelGGL(form_s_kernel, dim3(kGrid), dim3(kThreads), 0, st, c);
     hipLaunchKernelGGL(spmv_t_kernel<OPK>, dim3(kGrid), dim3(kThreads), 0, st, c);
     hipLaunchKernelGGL(update_xr_kernel, dim3(kGrid), dim3(kThreads), 0, st, c);
   }
