@@ -33,10 +33,12 @@
 // launch of its own; the remaining tiles run on a second stream beside the
 // pre-update, panel and interchanges of step s + 1, which touch other
 // columns (the interchange record and L11^-1 are kept per step parity).
-// The back substitution U W = R' then runs from the bottom in 128-row blocks:
-// lu_bdiag_kernel solves a diagonal block (32-row triangles through the
+// The back substitution U W = R' then runs from the bottom in 128-row blocks,
+// left-looking: lu_bupd_kernel brings a block's right-hand sides up to date
+// with every solved block below it in one long-K product, then
+// lu_bdiag_kernel solves the diagonal block (32-row triangles through the
 // inverses of U's diagonal blocks, stored by the panel kernel, and MFMA
-// updates), lu_bupd_kernel updates the rows above it.
+// updates).
 // Every rectangular update A[r, c] -= A[r, k] A[k, c] goes through one FP64
 // MFMA routine (v_mfma_f64_16x16x4: A[i][k] in lane i + 16 k, B[k][j] in
 // lane j + 16 k, D[i][j] in register i / 4 of lane j + 16 (i mod 4)) with
@@ -477,30 +479,35 @@ struct PermLds {
 };
 
 // Applies a composed permutation to columns [lo, hi) except [skip0, skip1):
-// the touched rows are staged through `scratch` (2 kOuter x 32 doubles) in
-// blocks of 32 columns and written back permuted.  Ends with a barrier.
+// row rows[e] receives the old contents of row rows[src[e]].  In chunks of
+// columns whose moved entries fit in registers (32 per thread): every read
+// of a chunk precedes every write of it (one barrier), no LDS staging, and
+// the next chunk's reads (other columns) follow the writes at once.  Ends
+// with a barrier.
+template <int NT>
 __device__ __attribute__((always_inline)) void apply_perm(gdouble* __restrict__ A, int ld, const PermLds& pl,
-                                                           int lo, int hi, int skip0, int skip1,
-                                                           double* __restrict__ scratch) {
+                                                           int lo, int hi, int skip0, int skip1) {
+  constexpr int CH = NT >= 512 ? 64 : 32;          // columns per chunk
+  constexpr int V = 2 * kOuter * CH / NT;          // entries per thread
   const int tid = threadIdx.x;
   const int nt = pl.count;
-  for (int c0 = lo; c0 < hi; c0 += 32) {
-    const bool skip_block = (c0 >= skip0 && c0 + 32 <= skip1);
-    if (!skip_block) {
-      for (int idx = tid; idx < nt * 32; idx += (int)blockDim.x) {
-        const int e = idx >> 5, c = c0 + (idx & 31);
-        if (c < hi && !(c >= skip0 && c < skip1)) scratch[idx] = A[pl.rows[e] * ld + c];
-      }
+  for (int c0 = lo; c0 < hi; c0 += CH) {
+    double val[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const int idx = tid + NT * k, e = idx / CH, c = c0 + idx % CH;
+      const bool ok = e < nt && c < hi && !(c >= skip0 && c < skip1);
+      val[k] = A[ok ? pl.rows[pl.src[ok ? e : 0]] * ld + c : 0];
     }
     __syncthreads();
-    if (!skip_block) {
-      for (int idx = tid; idx < nt * 32; idx += (int)blockDim.x) {
-        const int e = idx >> 5, cc = idx & 31, c = c0 + cc;
-        if (c < hi && !(c >= skip0 && c < skip1)) A[pl.rows[e] * ld + c] = scratch[(pl.src[e] << 5) + cc];
-      }
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const int idx = tid + NT * k, e = idx / CH, c = c0 + idx % CH;
+      const bool ok = e < nt && c < hi && !(c >= skip0 && c < skip1);
+      if (ok) A[pl.rows[e] * ld + c] = val[k];
     }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 // Wavefront maximum of a double: DPP exchanges inside each row of 16 lanes
@@ -718,7 +725,7 @@ __device__ __attribute__((always_inline)) void panel_body(const GItem& it, int K
         compose_perm(sh.piv + (k0 - K0), k0, pw, sh.perm.rows, sh.perm.src, &sh.perm.count, sh.slot);
       __syncthreads();
       // the sub-panel's interchanges on the rest of the panel
-      apply_perm(A, ld, sh.perm, K0, K0 + kb, k0, k0 + pw, &sh.u.sU[0][0]);
+      apply_perm<kThreads>(A, ld, sh.perm, K0, K0 + kb, k0, k0 + pw);
       if (k0 + pw < g0 + gw) {
         tri_inverse<TB, true>(A, ld, k0, pw, sh.u.t);
         tri_apply<TB>(A, ld, k0, pw, k0 + pw, g0 + gw, sh.u.t);
@@ -1303,7 +1310,7 @@ __device__ __attribute__((always_inline)) void urow_body(const GItem& it, int K0
     perm.src[e] = W->src[par][e];
   }
   __syncthreads();
-  apply_perm(A, ld, perm, c0, c1, 0, 0, &u.g.Lt[0][0]);
+  apply_perm<LEFT ? kThreads : kGemmThreads>(A, ld, perm, c0, c1, 0, 0);
   if (LEFT) return;
   // the contributions of all earlier steps to these rows (left-looking: the
   // trailing matrix is never updated as a whole)
@@ -1321,10 +1328,10 @@ __device__ __attribute__((always_inline)) void pupd_body(const GItem& it, int K0
   gemm_sub<kGemmThreads>(it.A, it.ld, ra, min(n, ra + kGT), K0, K0 + kb, 0, K0, g);
 }
 
-// Back substitution U W = R' on columns [n, n + nrhs), right-looking from the
-// bottom in blocks of kOuter rows aligned with the factorisation: the
-// diagonal block is solved by its 32-row triangles (stored inverses on MFMA)
-// and MFMA updates inside the block ...
+// Back substitution U W = R' on columns [n, n + nrhs), from the bottom in
+// blocks of kOuter rows aligned with the factorisation: the diagonal block is
+// solved by its 32-row triangles (stored inverses on MFMA) and MFMA updates
+// inside the block ...
 __device__ __attribute__((always_inline)) void bdiag_body(const GItem& it, int k0, MatLds& u) {
   gdouble* A = it.A;
   const int n = it.n, ld = it.ld, nrhs = it.nrhs;
@@ -1343,12 +1350,13 @@ __device__ __attribute__((always_inline)) void bdiag_body(const GItem& it, int k
   }
 }
 
-// ... and its contribution is removed from the 128-row tile t above it.
-__device__ __attribute__((always_inline)) void bupd_body(const GItem& it, int k0, int t, GemmLds& g) {
+// ... after the contributions of every solved block below it are removed:
+// R'[k0:k1] -= U[k0:k1, k1:n] W[k1:n] (left-looking: one long-K product per
+// block instead of one short product per block above each solved one).
+__device__ __attribute__((always_inline)) void bupd_body(const GItem& it, int k0, GemmLds& g) {
   const int n = it.n;
   const int k1 = min(n, k0 + kOuter);
-  const int r0 = t * kGT;
-  gemm_sub<kGemmThreads>(it.A, it.ld, r0, min(k0, r0 + kGT), n, n + it.nrhs, k0, k1, g);
+  gemm_sub<kGemmThreads>(it.A, it.ld, k0, k1, n, n + it.nrhs, k1, n, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -1470,13 +1478,13 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(2)
     if (gi >= total) return;
     const int m = owner(pre, count, gi);
     const GItem it = gitem(items[m]);
-    bupd_body(it, back_block(it, step), gi - pre[m], g);
+    bupd_body(it, back_block(it, step), g);
     return;
   }
   for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
     const int m = owner(pre, count, gi);
     const GItem it = gitem(items[m]);
-    bupd_body(it, back_block(it, step), gi - pre[m], g);
+    bupd_body(it, back_block(it, step), g);
   }
 }
 
@@ -1509,7 +1517,7 @@ int lu_plan_tiles(const LuItem& it, int kind, int step) {
     case LU_UREST: return std::max(0, (ld - K0 - kb + kGT - 1) / kGT - 1);
     case LU_PUPD: return K0 > 0 ? (n - K0 + kGT - 1) / kGT : 0;
     case LU_BDIAG: return 1;
-    default: return (nsteps - 1 - step);        // LU_BUPD: row tiles above the block
+    default: return step > 0 ? 1 : 0;           // LU_BUPD: the block (none for the bottom one)
   }
 }
 
@@ -1606,8 +1614,8 @@ int LuPlan::launch(hipStream_t st, int grid_cap, bool lookahead) const {
   }
   if (rest >= 0) PDD_HIP(hipStreamWaitEvent(st, ev_rest[rest], 0));
   for (int s = 0; s < nsteps; ++s) {
-    go(LU_BDIAG, s, lu_bdiag_kernel, nullptr, st);
     go(LU_BUPD, s, lu_bupd_kernel<false>, lu_bupd_kernel<true>, st);
+    go(LU_BDIAG, s, lu_bdiag_kernel, nullptr, st);
   }
   return launches;
 }
