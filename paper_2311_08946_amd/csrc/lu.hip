@@ -138,44 +138,77 @@ __device__ __attribute__((always_inline)) void gemm_op(gdouble* __restrict__ A, 
       const bool ucol_ok = ct + ucol < c1;
       double pl[LIT], pu[UIT];
       // out-of-range elements read A[0] (always valid) and are then zeroed
+      // fetch issues the chunk's loads (raw values: out-of-range entries
+      // read the valid A[0]); stage zeroes those entries on their way into
+      // LDS -- masking at the load would make the wavefront wait for the
+      // prefetch before the products that were to hide it
       auto fetch = [&](int kc) {
         const bool lk_ok = kc + lcol < k1;
 #pragma unroll
         for (int it = 0; it < LIT; ++it) {
           const bool okl = lk_ok && ((lmask >> it) & 1u);
-          const double vl = Lb[okl ? loff + LP * it * ldl + kc : 0];
-          pl[it] = okl ? vl : 0.0;
+          pl[it] = Lb[okl ? loff + LP * it * ldl + kc : 0];
         }
 #pragma unroll
         for (int it = 0; it < UIT; ++it) {
           const bool oku = ucol_ok && kc + urow + UP * it < k1;
-          const double vu = A[oku ? uoff + (kc + UP * it) * ld : 0];
-          pu[it] = oku ? vu : 0.0;
+          pu[it] = A[oku ? uoff + (kc + UP * it) * ld : 0];
         }
       };
-      fetch(k0);
-#pragma unroll 1
-      for (int kc = k0; kc < k1; kc += KC) {
+      auto stage = [&](int off, int kc) {  // the chunk fetched at kc into LDS rows [off, off + KC)
+        const bool lk_ok = kc + lcol < k1;
 #pragma unroll
-        for (int it = 0; it < LIT; ++it) lt_st[LP * it] = SET ? pl[it] : -pl[it];
+        for (int it = 0; it < LIT; ++it) {
+          const bool okl = lk_ok && ((lmask >> it) & 1u);
+          lt_st[off * (kGT + kPad) + LP * it] = okl ? (SET ? pl[it] : -pl[it]) : 0.0;
+        }
 #pragma unroll
-        for (int it = 0; it < UIT; ++it) ut_st[UP * it * (kGT + kPad)] = pu[it];
-        __syncthreads();
-        if (kc + KC < k1) fetch(kc + KC);
+        for (int it = 0; it < UIT; ++it) {
+          const bool oku = ucol_ok && kc + urow + UP * it < k1;
+          ut_st[off * (kGT + kPad) + UP * it * (kGT + kPad)] = oku ? pu[it] : 0.0;
+        }
+      };
+      auto products = [&](int off) {       // the MFMAs of the chunk in LDS rows [off, off + KC)
 #pragma unroll
         for (int ks = 0; ks < KC / 4; ++ks) {
           double a[BI], b[BJ];
 #pragma unroll
-          for (int bi = 0; bi < BI; ++bi) a[bi] = lt_rd[4 * ks * (kGT + kPad) + 16 * bi];
+          for (int bi = 0; bi < BI; ++bi) a[bi] = lt_rd[(off + 4 * ks) * (kGT + kPad) + 16 * bi];
 #pragma unroll
-          for (int bj = 0; bj < BJ; ++bj) b[bj] = ut_rd[4 * ks * (kGT + kPad) + 16 * bj];
+          for (int bj = 0; bj < BJ; ++bj) b[bj] = ut_rd[(off + 4 * ks) * (kGT + kPad) + 16 * bj];
 #pragma unroll
           for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
             for (int bj = 0; bj < BJ; ++bj)
               acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
         }
+      };
+      fetch(k0);
+      if (2 * KC <= kGK) {
+        // two LDS buffers (rows [0, KC) and [KC, 2 KC)): the next chunk is
+        // staged while the other wavefronts may still read the current one,
+        // one barrier per chunk
+        stage(0, k0);
         __syncthreads();
+        int cur = 0;
+#pragma unroll 1
+        for (int kc = k0; kc < k1; kc += KC) {
+          const bool more = kc + KC < k1;
+          if (more) fetch(kc + KC);
+          products(cur);
+          if (more) stage(KC - cur, kc + KC);
+          __syncthreads();
+          cur = KC - cur;
+        }
+      } else {
+#pragma unroll 1
+        for (int kc = k0; kc < k1; kc += KC) {
+          stage(0, kc);
+          __syncthreads();
+          if (kc + KC < k1) fetch(kc + KC);
+          products(0);
+          __syncthreads();
+        }
       }
 #pragma unroll
       for (int bi = 0; bi < BI; ++bi) {

@@ -216,11 +216,12 @@ void launch_colloc_build(const BucketTables& T, const ChunkDesc& C, const NodeSa
 // weights in rho times Ntheta-point periodic cardinals in theta; folded onto
 // the unknowns they give e (interior) and eps (ring):
 //   C[i, Xi_m] = e^T W[:, :M] - eps^T H,   r_i = e^T W[:, M],   C_ii = 1.
-// Knots go in chunks of 32; for each chunk E W is a (32 x n) (n x (M+1))
-// product: E is formed in LDS 32 columns at a time from the radial and
-// angular weights, W's rows are staged beside it, and the four wavefronts
-// accumulate E W on MFMA (wavefront w: knots 16 (w mod 2) .., every other
-// 16-column block).
+// Knots go in chunks of 32; for each chunk [E | -eps] [W ; H] is a
+// (32 x (n + Ntheta)) ((n + Ntheta) x (M+1)) product (H zero in column M):
+// E and -eps are formed in LDS 32 columns at a time from the radial and
+// angular weights, the rows of W and H are staged beside them, and the four
+// wavefronts accumulate the product on MFMA (wavefront w: knots
+// 16 (w mod 2) .., every other 16-column block).
 namespace {
 constexpr int kEK = 32;           // knots per chunk
 constexpr int kEQ = 32;           // interior nodes per staged block
@@ -228,7 +229,7 @@ constexpr int kEMaxCB = 5;        // column blocks per wavefront: nrhs <= 160
 constexpr int kEThreads = 256;
 }
 
-__global__ __launch_bounds__(kEThreads) void eval_scatter_kernel(BucketTables T, ChunkDesc C,
+__global__ __launch_bounds__(kEThreads) __attribute__((amdgpu_waves_per_eu(2))) void eval_scatter_kernel(BucketTables T, ChunkDesc C,
                                                                  const double* __restrict__ A0,
                                                                  int64_t stride, double* __restrict__ val,
                                                                  double* __restrict__ bvec) {
@@ -306,6 +307,20 @@ __global__ __launch_bounds__(kEThreads) void eval_scatter_kernel(BucketTables T,
     dbl4 acc[kEMaxCB];
 #pragma unroll
     for (int u = 0; u < kEMaxCB; ++u) acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+    auto mma = [&]() {
+#pragma unroll
+      for (int ks = 0; ks < kEQ / 4; ++ks) {
+        const double a = Eb[(16 * rb + li) * (kEQ + 1) + 4 * ks + lk];
+#pragma unroll
+        for (int u = 0; u < kEMaxCB; ++u) {
+          const int cb = cb0 + 2 * u;
+          if (cb < NCB) {
+            const double bb = Wb[(4 * ks + lk) * (NC + 1) + 16 * cb + li];
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[u], 0, 0, 0);
+          }
+        }
+      }
+    };
     for (int q0 = 0; q0 < n; q0 += kEQ) {
       const int qn = min(kEQ, n - q0);
       // E block: e_t(q) = lx[t][k] lt[t][l'] + lx[t][Nc - k] lt[t][l' + Nt/2]
@@ -328,18 +343,23 @@ __global__ __launch_bounds__(kEThreads) void eval_scatter_kernel(BucketTables T,
         Wb[qq * (NC + 1) + c] = (qq < qn && c < nrhs) ? A[(int64_t)(q0 + qq) * ld + n + c] : 0.0;
       }
       __syncthreads();
-#pragma unroll
-      for (int ks = 0; ks < kEQ / 4; ++ks) {
-        const double a = Eb[(16 * rb + li) * (kEQ + 1) + 4 * ks + lk];
-#pragma unroll
-        for (int u = 0; u < kEMaxCB; ++u) {
-          const int cb = cb0 + 2 * u;
-          if (cb < NCB) {
-            const double bb = Wb[(4 * ks + lk) * (NC + 1) + 16 * cb + li];
-            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[u], 0, 0, 0);
-          }
-        }
+      mma();
+      __syncthreads();
+    }
+    // the boundary-ring correction -eps H of the knot columns (c < M) as more
+    // blocks of the same product: E block -eps[t][l], W block H[l][c]
+    for (int l0 = 0; l0 < Nt; l0 += kEQ) {
+      const int ln = min(kEQ, Nt - l0);
+      for (int idx = tid; idx < kEK * kEQ; idx += kEThreads) {
+        const int t = idx / kEQ, qq = idx - t * kEQ;
+        Eb[t * (kEQ + 1) + qq] = qq < ln ? -eps[t * st + l0 + qq] : 0.0;
       }
+      for (int idx = tid; idx < kEQ * NC; idx += kEThreads) {
+        const int qq = idx / NC, c = idx - qq * NC;
+        Wb[qq * (NC + 1) + c] = (qq < ln && c < M) ? T.H[(int64_t)(l0 + qq) * M + c] : 0.0;
+      }
+      __syncthreads();
+      mma();
       __syncthreads();
     }
     // D layout: acc[u][v] is knot 16 rb + 4 v + lk, column 16 cb + li
@@ -352,10 +372,9 @@ __global__ __launch_bounds__(kEThreads) void eval_scatter_kernel(BucketTables T,
         for (int v = 0; v < 4; ++v) {
           const int t = 16 * rb + 4 * v + lk;
           if (t < cnt) {
-            double x = acc[u][v];
+            const double x = acc[u][v];
             const int i = C.fk_ids[base + t];
             if (c < M) {
-              for (int l = 0; l < Nt; ++l) x -= eps[t * st + l] * T.H[(int64_t)l * M + c];
               const int64_t lo = C.knot_off[m];
               const int shift = (i < lo) ? 1 : 0;
               val[C.rowptr[i] + shift + c] = x;
