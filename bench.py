@@ -421,6 +421,29 @@ def cpu_baseline_subprocess(workload, frac):
 
 # ------------------------------------------------------------------- report
 
+def measured_traffic(workload, phase):
+    """HBM bytes per step of a phase, from the rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary committed under profiles/ (calibrated against a copy kernel), or
+    None when there is none for this workload and phase, or when the kernel
+    source it was taken on has changed since (its SHA-256 is recorded)."""
+    import hashlib
+    import re
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", f"hbm_traffic_{phase}_{workload}.md")
+    src = {"lu": "lu.hip"}.get(phase)
+    if src is None or not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_sha = re.search(r"source_sha256: ([0-9a-f]{64})", text)
+    m_b = re.search(r"bytes_per_step: ([0-9]+)", text)
+    if not (m_sha and m_b):
+        return None
+    with open(os.path.join(here, "paper_2311_08946_amd", "csrc", src), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != m_sha.group(1):
+            return None
+    return float(m_b.group(1))
+
+
 def phase_rooflines(cover, cfg, results, with_adj):
     """One roofline entry per phase, each from times measured in this run."""
     import numpy as np
@@ -540,12 +563,12 @@ def main():
         "lu": f"batched LU + triangular solves of {n_float} circles (lu_pupd/lu_panel/lu_urow/lu_bdiag/"
               "lu_bupd launch sequence, HIP events around it on the calling stream)",
         "mc": "paths_kernel (Euler-Maruyama paths, one per lane) on the side stream",
-        "bicgstab": "BiCGStab on C and C^T (update_p/spmv_v/spmv_t/update_xr per iteration)",
+        "bicgstab": "BiCGStab on C and C^T (update_p/spmv_v/form_s/spmv_t/update_xr per iteration)",
         "adjoint": "adjoint_kernel over the stored factors",
     }
     roofline = dict(roof[dom])
     roofline["kernel"] = kernels[dom]
-    roofline["traffic"] = None
+    roofline["traffic"] = measured_traffic(args.workload, dom)
     out = {
         "metric": "G assembly circles/s + MC path-steps/s at fixed error; fwd+adjoint seconds",
         "value": n_circles / dt,

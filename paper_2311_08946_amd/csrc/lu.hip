@@ -1001,7 +1001,6 @@ __device__ __attribute__((always_inline)) void own_column(double (&P)[kTB], int&
   }
   pos = npos;
   if (tid == 0) piv[K0 + cr] = K0 + ppos;
-  if (live) wrow[C] = P[C];                  // final for every row from here on
 }
 
 template <int... Cs>
@@ -1085,19 +1084,24 @@ __device__ __attribute__((always_inline)) void panel_own_body(const GItem& it, i
     double P[kTB];
 #pragma unroll
     for (int c = 0; c < kTB; ++c) P[c] = arow[g0 + min(c, gw - 1)];
-    // each column stored as soon as it is final (the registers of the
-    // finished columns are free for the rest of the group)
     gdouble* wrow = A + (size_t)(K0 + (own ? tid : 0)) * ld + g0;
     own_columns(std::make_integer_sequence<int, kTB>{}, P, pos, singular, gw, g0r, K0, it.piv, own, live, wrow, nw,
                 sh);
+    // the group's columns back in place, a row's 32 values together (a store
+    // per finished column writes 8 bytes of a line at a time: several times
+    // the bytes in HBM write traffic)
+    if (live) {
+#pragma unroll
+      for (int c = 0; c < kTB; ++c)
+        if (c < gw) wrow[c] = P[c];
+    }
     __syncthreads();                         // the candidate rows are read; the LDS is reused
-    // the group's pivot rows form the diagonal block (read back from the row
-    // each thread has just stored), identity-padded beyond gw
+    // the group's pivot rows form the diagonal block, identity-padded beyond gw
     if (own && pos >= g0r && pos < g0r + gw) {
       const int i = pos - g0r;
 #pragma unroll
       for (int c = 0; c < kTB; ++c) {
-        const double v = c < gw ? wrow[c] : 0.0;
+        const double v = c < gw ? P[c] : 0.0;
         sh.u.t.blk[i][c] = v;
         sh.u.t.inv2[kTB - 1 - i][kTB - 1 - c] = v;
       }
