@@ -430,7 +430,7 @@ def measured_traffic(workload, phase):
     import re
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", f"hbm_traffic_{phase}_{workload}.md")
-    src = {"lu": "lu.hip"}.get(phase)
+    src = {"lu": "lu.hip", "bicgstab": "solve.hip"}.get(phase)
     if src is None or not os.path.exists(path):
         return None
     text = open(path).read()
@@ -557,6 +557,8 @@ def main():
     ms_spec = med([s.ms_build + s.ms_lu + s.ms_solve + s.ms_eval for s in st])
     path_steps = st[-1].path_steps
     roof = phase_rooflines(cover, cfg, results, with_adj)
+    for ph in roof:
+        roof[ph]["traffic"] = measured_traffic(args.workload, ph)
     # the headline roofline: the phase that takes the most time per step
     dom = max(roof, key=lambda k: roof[k]["ms"])
     kernels = {
@@ -568,7 +570,6 @@ def main():
     }
     roofline = dict(roof[dom])
     roofline["kernel"] = kernels[dom]
-    roofline["traffic"] = measured_traffic(args.workload, dom)
     out = {
         "metric": "G assembly circles/s + MC path-steps/s at fixed error; fwd+adjoint seconds",
         "value": n_circles / dt,
