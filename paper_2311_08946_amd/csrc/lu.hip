@@ -78,23 +78,18 @@ struct GemmLds {
   double Ut[kGK][kGT + kPad];   //  A[k, c] chunk
 };
 
-// A[r0:r1, c0:c1] -= A[r0:r1, k0:k1] A[k0:k1, c0:c1]; the three blocks are
-// disjoint.  Called by all NT threads of the workgroup; ends with a barrier.
-// NT = 512: 4 x 2 wavefronts of 32 x 64 outputs; NT = 256: 2 x 2 wavefronts
-// of 64 x 64 (twice the MFMAs per LDS operand read, and two workgroups share
-// a CU, so that one's tile loads and stores overlap the other's products).
-// Addresses are one per-lane base pointer plus workgroup-uniform offsets, and
-// the edge tests are per-lane bit masks, to keep register use low.
-// SET: A[r0:r1, c0:c1] = Lb[r - lro, k - lko] A[k0:k1, c0:c1] with a separate
-// left factor Lb (leading dimension ldl); the right factor may be the output
-// block itself (every read precedes the final barrier, every write follows it).
-template <bool SET, int NT>
-__device__ __attribute__((always_inline)) void gemm_op(gdouble* __restrict__ A, int ld, int r0, int r1, int c0, int c1,
-                                                        int k0, int k1, const gdouble* Lb, int ldl, int lro, int lko,
-                                                        GemmLds& s) {
-  constexpr int NW = NT / kWave, WC = 2, WR = NW / WC;
-  constexpr int RW = kGT / WR, CW = kGT / WC;        // outputs per wavefront
-  constexpr int BI = RW / 16, BJ = CW / 16;
+// One output tile of the product below: rows [rt, min(r1, rt + RT)), columns
+// [ct, min(c1, ct + CT)) with RT = WR 16 BI and CT = (NW / WR) 16 BJ -- WR x
+// (NW / WR) wavefronts of 16 BI x 16 BJ outputs each.  The operand chunks are
+// staged in LDS at the full 128 x 128 tile's shape either way (entries beyond
+// the tile are zero); the shape only sets how many MFMAs each wavefront runs.
+template <bool SET, int NT, int WR, int BI, int BJ>
+__device__ __attribute__((always_inline)) void gemm_tile(gdouble* __restrict__ A, int ld, int rt, int r1, int ct,
+                                                          int c1, int k0, int k1, const gdouble* Lb, int ldl,
+                                                          int lro, int lko, GemmLds& s) {
+  constexpr int NW = NT / kWave, WC = NW / WR;
+  constexpr int RW = 16 * BI, CW = 16 * BJ;          // outputs per wavefront
+  static_assert(WR * RW <= kGT && WC * CW <= kGT && WR * WC == NW, "tile shape");
   // K chunk: 32 with 512 threads; 16 with 256, whose 64 x 64 accumulators
   // leave registers for half as many prefetched operands
   constexpr int KC = NT >= 512 ? kGK : kGK / 2;
@@ -111,126 +106,165 @@ __device__ __attribute__((always_inline)) void gemm_op(gdouble* __restrict__ A, 
   double* __restrict__ ut_st = &s.Ut[urow][ucol];
   const double* __restrict__ lt_rd = &s.Lt[lk][RW * wr + li];
   const double* __restrict__ ut_rd = &s.Ut[lk][CW * wc + li];
-#pragma unroll 1
-  for (int rt = r0; rt < r1; rt += kGT) {
-#pragma unroll 1
-    for (int ct = c0; ct < c1; ct += kGT) {
-      const int crow = rt + RW * wr + lk, ccol = ct + CW * wc + li;
-      const int coff = crow * ld + ccol;
-      unsigned rmask = 0, cmask = 0;
+  const int crow = rt + RW * wr + lk, ccol = ct + CW * wc + li;
+  const int coff = crow * ld + ccol;
+  unsigned rmask = 0, cmask = 0;
 #pragma unroll
-      for (int t = 0; t < 4 * BI; ++t)   // t = 4 bi + v: row offset 16 bi + 4 v
-        rmask |= (crow + 16 * (t >> 2) + 4 * (t & 3) < r1) ? (1u << t) : 0u;
+  for (int t = 0; t < 4 * BI; ++t)   // t = 4 bi + v: row offset 16 bi + 4 v
+    rmask |= (crow + 16 * (t >> 2) + 4 * (t & 3) < r1) ? (1u << t) : 0u;
 #pragma unroll
-      for (int bj = 0; bj < BJ; ++bj) cmask |= (ccol + 16 * bj < c1) ? (1u << bj) : 0u;
-      // the product accumulates from zero; the tile itself is read only at
-      // the end, a block row at a time (few registers in flight)
-      dbl4 acc[BI][BJ];
+  for (int bj = 0; bj < BJ; ++bj) cmask |= (ccol + 16 * bj < c1) ? (1u << bj) : 0u;
+  // the product accumulates from zero; the tile itself is read only at
+  // the end, a block row at a time (few registers in flight)
+  dbl4 acc[BI][BJ];
+#pragma unroll
+  for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < BJ; ++bj) acc[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const int loff = (rt - lro + lrow) * ldl + lcol - lko;
+  const int uoff = urow * ld + ct + ucol;
+  unsigned lmask = 0;
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) lmask |= (rt + lrow + LP * it < r1) ? (1u << it) : 0u;
+  const bool ucol_ok = ct + ucol < c1;
+  double pl[LIT], pu[UIT];
+  // fetch issues the chunk's loads (raw values: out-of-range entries read
+  // the valid A[0]); stage zeroes those entries on their way into LDS --
+  // masking at the load would make the wavefront wait for the prefetch
+  // before the products that were to hide it
+  auto fetch = [&](int kc) {
+    const bool lk_ok = kc + lcol < k1;
+#pragma unroll
+    for (int it = 0; it < LIT; ++it) {
+      const bool okl = lk_ok && ((lmask >> it) & 1u);
+      pl[it] = Lb[okl ? loff + LP * it * ldl + kc : 0];
+    }
+#pragma unroll
+    for (int it = 0; it < UIT; ++it) {
+      const bool oku = ucol_ok && kc + urow + UP * it < k1;
+      pu[it] = A[oku ? uoff + (kc + UP * it) * ld : 0];
+    }
+  };
+  auto stage = [&](int off, int kc) {  // the chunk fetched at kc into LDS rows [off, off + KC)
+    const bool lk_ok = kc + lcol < k1;
+#pragma unroll
+    for (int it = 0; it < LIT; ++it) {
+      const bool okl = lk_ok && ((lmask >> it) & 1u);
+      lt_st[off * (kGT + kPad) + LP * it] = okl ? (SET ? pl[it] : -pl[it]) : 0.0;
+    }
+#pragma unroll
+    for (int it = 0; it < UIT; ++it) {
+      const bool oku = ucol_ok && kc + urow + UP * it < k1;
+      ut_st[off * (kGT + kPad) + UP * it * (kGT + kPad)] = oku ? pu[it] : 0.0;
+    }
+  };
+  auto products = [&](int off) {       // the MFMAs of the chunk in LDS rows [off, off + KC)
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      double a[BI], b[BJ];
+#pragma unroll
+      for (int bi = 0; bi < BI; ++bi) a[bi] = lt_rd[(off + 4 * ks) * (kGT + kPad) + 16 * bi];
+#pragma unroll
+      for (int bj = 0; bj < BJ; ++bj) b[bj] = ut_rd[(off + 4 * ks) * (kGT + kPad) + 16 * bj];
 #pragma unroll
       for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < BJ; ++bj) acc[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
-      const int loff = (rt - lro + lrow) * ldl + lcol - lko;
-      const int uoff = urow * ld + ct + ucol;
-      unsigned lmask = 0;
-#pragma unroll
-      for (int it = 0; it < LIT; ++it) lmask |= (rt + lrow + LP * it < r1) ? (1u << it) : 0u;
-      const bool ucol_ok = ct + ucol < c1;
-      double pl[LIT], pu[UIT];
-      // out-of-range elements read A[0] (always valid) and are then zeroed
-      // fetch issues the chunk's loads (raw values: out-of-range entries
-      // read the valid A[0]); stage zeroes those entries on their way into
-      // LDS -- masking at the load would make the wavefront wait for the
-      // prefetch before the products that were to hide it
-      auto fetch = [&](int kc) {
-        const bool lk_ok = kc + lcol < k1;
-#pragma unroll
-        for (int it = 0; it < LIT; ++it) {
-          const bool okl = lk_ok && ((lmask >> it) & 1u);
-          pl[it] = Lb[okl ? loff + LP * it * ldl + kc : 0];
-        }
-#pragma unroll
-        for (int it = 0; it < UIT; ++it) {
-          const bool oku = ucol_ok && kc + urow + UP * it < k1;
-          pu[it] = A[oku ? uoff + (kc + UP * it) * ld : 0];
-        }
-      };
-      auto stage = [&](int off, int kc) {  // the chunk fetched at kc into LDS rows [off, off + KC)
-        const bool lk_ok = kc + lcol < k1;
-#pragma unroll
-        for (int it = 0; it < LIT; ++it) {
-          const bool okl = lk_ok && ((lmask >> it) & 1u);
-          lt_st[off * (kGT + kPad) + LP * it] = okl ? (SET ? pl[it] : -pl[it]) : 0.0;
-        }
-#pragma unroll
-        for (int it = 0; it < UIT; ++it) {
-          const bool oku = ucol_ok && kc + urow + UP * it < k1;
-          ut_st[off * (kGT + kPad) + UP * it * (kGT + kPad)] = oku ? pu[it] : 0.0;
-        }
-      };
-      auto products = [&](int off) {       // the MFMAs of the chunk in LDS rows [off, off + KC)
-#pragma unroll
-        for (int ks = 0; ks < KC / 4; ++ks) {
-          double a[BI], b[BJ];
-#pragma unroll
-          for (int bi = 0; bi < BI; ++bi) a[bi] = lt_rd[(off + 4 * ks) * (kGT + kPad) + 16 * bi];
-#pragma unroll
-          for (int bj = 0; bj < BJ; ++bj) b[bj] = ut_rd[(off + 4 * ks) * (kGT + kPad) + 16 * bj];
-#pragma unroll
-          for (int bi = 0; bi < BI; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < BJ; ++bj)
-              acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
-        }
-      };
-      fetch(k0);
-      if (2 * KC <= kGK) {
-        // two LDS buffers (rows [0, KC) and [KC, 2 KC)): the next chunk is
-        // staged while the other wavefronts may still read the current one,
-        // one barrier per chunk
-        stage(0, k0);
-        __syncthreads();
-        int cur = 0;
-#pragma unroll 1
-        for (int kc = k0; kc < k1; kc += KC) {
-          const bool more = kc + KC < k1;
-          if (more) fetch(kc + KC);
-          products(cur);
-          if (more) stage(KC - cur, kc + KC);
-          __syncthreads();
-          cur = KC - cur;
-        }
-      } else {
-#pragma unroll 1
-        for (int kc = k0; kc < k1; kc += KC) {
-          stage(0, kc);
-          __syncthreads();
-          if (kc + KC < k1) fetch(kc + KC);
-          products(0);
-          __syncthreads();
-        }
-      }
-#pragma unroll
-      for (int bi = 0; bi < BI; ++bi) {
-        double cv[4][BJ];
-        if (!SET) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-#pragma unroll
-            for (int bj = 0; bj < BJ; ++bj) {
-              const bool ok = ((rmask >> (4 * bi + v)) & (cmask >> bj) & 1u) != 0;
-              cv[v][bj] = A[ok ? coff + (16 * bi + 4 * v) * ld + 16 * bj : 0];
-            }
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-          for (int bj = 0; bj < BJ; ++bj) {
-            const bool ok = ((rmask >> (4 * bi + v)) & (cmask >> bj) & 1u) != 0;
-            if (ok) A[coff + (16 * bi + 4 * v) * ld + 16 * bj] = SET ? acc[bi][bj][v] : cv[v][bj] + acc[bi][bj][v];
-          }
-      }
+        for (int bj = 0; bj < BJ; ++bj)
+          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
     }
+  };
+  fetch(k0);
+  if (2 * KC <= kGK) {
+    // two LDS buffers (rows [0, KC) and [KC, 2 KC)): the next chunk is
+    // staged while the other wavefronts may still read the current one,
+    // one barrier per chunk
+    stage(0, k0);
+    __syncthreads();
+    int cur = 0;
+#pragma unroll 1
+    for (int kc = k0; kc < k1; kc += KC) {
+      const bool more = kc + KC < k1;
+      if (more) fetch(kc + KC);
+      products(cur);
+      if (more) stage(KC - cur, kc + KC);
+      __syncthreads();
+      cur = KC - cur;
+    }
+  } else {
+#pragma unroll 1
+    for (int kc = k0; kc < k1; kc += KC) {
+      stage(0, kc);
+      __syncthreads();
+      if (kc + KC < k1) fetch(kc + KC);
+      products(0);
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int bi = 0; bi < BI; ++bi) {
+    double cv[4][BJ];
+    if (!SET) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int bj = 0; bj < BJ; ++bj) {
+          const bool ok = ((rmask >> (4 * bi + v)) & (cmask >> bj) & 1u) != 0;
+          cv[v][bj] = A[ok ? coff + (16 * bi + 4 * v) * ld + 16 * bj : 0];
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int bj = 0; bj < BJ; ++bj) {
+        const bool ok = ((rmask >> (4 * bi + v)) & (cmask >> bj) & 1u) != 0;
+        if (ok) A[coff + (16 * bi + 4 * v) * ld + 16 * bj] = SET ? acc[bi][bj][v] : cv[v][bj] + acc[bi][bj][v];
+      }
+  }
+}
+
+// A[r0:r1, c0:c1] -= A[r0:r1, k0:k1] A[k0:k1, c0:c1]; the three blocks are
+// disjoint.  Called by all NT threads of the workgroup; ends with a barrier.
+// NT = 512: 4 x 2 wavefronts of 32 x 64 outputs; NT = 256: 2 x 2 wavefronts
+// of 64 x 64 (twice the MFMAs per LDS operand read, and two workgroups share
+// a CU, so that one's tile loads and stores overlap the other's products).
+// With 256 threads a block of one tile that ends inside the 128 x 128 grid
+// takes a smaller shape, picked once (no branch inside the K loop): 64 rows
+// (2 x 2 wavefronts of 32 x 64), 64 columns (of 64 x 32), both (32 x 32),
+// or 80 columns -- the 65 right-hand sides padded to 80 -- as 4 x 1
+// wavefronts of 32 x 80 (16 x 80 with 64 rows).  Without them every step's
+// last row tile and last column tile cost a full tile of MFMAs.
+// Addresses are one per-lane base pointer plus workgroup-uniform offsets, and
+// the edge tests are per-lane bit masks, to keep register use low.
+// SET: A[r0:r1, c0:c1] = Lb[r - lro, k - lko] A[k0:k1, c0:c1] with a separate
+// left factor Lb (leading dimension ldl); the right factor may be the output
+// block itself (every read precedes the final barrier, every write follows it).
+template <bool SET, int NT>
+__device__ __attribute__((always_inline)) void gemm_op(gdouble* __restrict__ A, int ld, int r0, int r1, int c0, int c1,
+                                                        int k0, int k1, const gdouble* Lb, int ldl, int lro, int lko,
+                                                        GemmLds& s) {
+  if constexpr (NT == 256) {
+    if (r1 - r0 <= kGT && c1 - c0 <= kGT) {   // one tile (every LU launch's unit): pick its shape
+      const bool short_r = r1 - r0 <= kGT / 2;
+      const int wcols = c1 - c0;
+      if (wcols > 80) {
+        if (short_r) gemm_tile<SET, NT, 2, 2, 4>(A, ld, r0, r1, c0, c1, k0, k1, Lb, ldl, lro, lko, s);
+        else gemm_tile<SET, NT, 2, 4, 4>(A, ld, r0, r1, c0, c1, k0, k1, Lb, ldl, lro, lko, s);
+      } else if (wcols > 64) {
+        if (short_r) gemm_tile<SET, NT, 4, 1, 5>(A, ld, r0, r1, c0, c1, k0, k1, Lb, ldl, lro, lko, s);
+        else gemm_tile<SET, NT, 4, 2, 5>(A, ld, r0, r1, c0, c1, k0, k1, Lb, ldl, lro, lko, s);
+      } else {
+        if (short_r) gemm_tile<SET, NT, 2, 2, 2>(A, ld, r0, r1, c0, c1, k0, k1, Lb, ldl, lro, lko, s);
+        else gemm_tile<SET, NT, 2, 4, 2>(A, ld, r0, r1, c0, c1, k0, k1, Lb, ldl, lro, lko, s);
+      }
+      __syncthreads();
+      return;
+    }
+  }
+  constexpr int WR = NT == 512 ? 4 : 2, BI = NT == 512 ? 2 : 4;
+#pragma unroll 1
+  for (int rt = r0; rt < r1; rt += kGT) {
+#pragma unroll 1
+    for (int ct = c0; ct < c1; ct += kGT) gemm_tile<SET, NT, WR, BI, 4>(A, ld, rt, r1, ct, c1, k0, k1, Lb, ldl, lro, lko, s);
   }
   __syncthreads();
 }
