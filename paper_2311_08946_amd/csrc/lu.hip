@@ -63,6 +63,31 @@ constexpr int kPad = 1;
 constexpr int kWave = 64;
 constexpr int kTB = 32;         // triangular block
 
+// Step boundaries.  Step 0 takes the remainder of n modulo 128 (rounded up
+// to a multiple of the 32-column group), every later step 128 columns; a
+// multiple of 128 gives plain 128-column steps.  With the short step first,
+// the tallest panel (all n rows) is also the narrowest, every later panel has
+// at most n - lead rows, and the row tiles of the pre-update are whole.
+__host__ __device__ __forceinline__ int lu_lead(int n) {
+  const int r = n % kOuter;
+  return r == 0 ? kOuter : (r + kTB - 1) / kTB * kTB;
+}
+__host__ __device__ __forceinline__ int lu_steps(int n) { return (n + kOuter - 1) / kOuter; }
+// first column of step s
+__host__ __device__ __forceinline__ int lu_k0(int n, int s) {
+  const int k = s == 0 ? 0 : lu_lead(n) + (s - 1) * kOuter;
+  return k < n ? k : n;
+}
+// width of the step that starts at column K0
+__host__ __device__ __forceinline__ int lu_kb(int n, int K0) {
+  const int w = K0 == 0 ? lu_lead(n) : kOuter;
+  const int kb = w < n - K0 ? w : n - K0;
+  __builtin_assume(kb <= kOuter);
+  return kb;
+}
+// index of the step that starts at column K0
+__host__ __device__ __forceinline__ int lu_step(int n, int K0) { return K0 == 0 ? 0 : (K0 - lu_lead(n)) / kOuter + 1; }
+
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 
@@ -778,7 +803,7 @@ __device__ __attribute__((always_inline)) void panel_body(const GItem& it, int K
   const int n = it.n, ld = it.ld;
   gwork* W = it.work;
   const int tid = threadIdx.x;
-  const int kb = min(kOuter, n - K0);
+  const int kb = lu_kb(n, K0);
   int singular = 0;
   for (int r = tid; r < n; r += kThreads) sh.slot[r] = -1;
   // groups of kTB columns, each factorised by sub-panels of NB columns; the
@@ -813,7 +838,7 @@ __device__ __attribute__((always_inline)) void panel_body(const GItem& it, int K
     }
     __syncthreads();
   }
-  const int par = (K0 / kOuter) & 1;
+  const int par = lu_step(n, K0) & 1;
   // the step's composed permutation, formed in LDS and copied out
   if (tid == 0) compose_perm(sh.piv, K0, kb, sh.perm.rows, sh.perm.src, &sh.perm.count, sh.slot);
   __syncthreads();
@@ -1103,7 +1128,7 @@ __device__ __attribute__((always_inline)) void panel_own_body(const GItem& it, i
   gwork* W = it.work;
   const int nthr = blockDim.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = nthr >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int m = n - K0, kb = min(kOuter, m);
+  const int m = n - K0, kb = lu_kb(n, K0);
   const bool own = tid < m;
   const gdouble* arow = A + (size_t)(K0 + (own ? tid : 0)) * ld;
   int pos = own ? tid : 0x7fff;
@@ -1236,7 +1261,7 @@ __device__ __attribute__((always_inline)) void panel_own_body(const GItem& it, i
   for (int v = 0; v < w; ++v) base += sh.u.g.wcount[v];
   if (moved) sh.u.g.slot[tid] = (short)(base + __popcll(mm & ((1ull << lane) - 1ull)));
   __syncthreads();
-  const int par = (K0 / kOuter) & 1;
+  const int par = lu_step(n, K0) & 1;
   if (moved) {
     const int e = sh.u.g.slot[tid];
     W->rows[par][e] = K0 + tid;
@@ -1296,9 +1321,9 @@ __device__ __attribute__((always_inline)) void wave_tile(Opnd P, Opnd Q, double 
 __device__ __attribute__((always_inline)) void linv_body(const GItem& it, int K0) {
   const int n = it.n, ld = it.ld;
   gwork* W = it.work;
-  gdouble* __restrict__ X = &W->linv[(K0 / kOuter) & 1][0][0];
+  gdouble* __restrict__ X = &W->linv[lu_step(n, K0) & 1][0][0];
   const int tid = threadIdx.x, w = tid >> 6;
-  const int kb = min(kOuter, n - K0);
+  const int kb = lu_kb(n, K0);
   auto L = [&](int a, int b) {            // block (a, b), a > b, of L11
     return Opnd{it.A + (size_t)(K0 + kTB * a) * ld + K0 + kTB * b, ld, kb - kTB * a, kb - kTB * b};
   };
@@ -1367,14 +1392,14 @@ __device__ __attribute__((always_inline)) void urow_body(const GItem& it, int K0
   const int n = it.n, ld = it.ld;
   const gwork* W = it.work;
   const int tid = threadIdx.x;
-  const int kb = min(kOuter, n - K0);
-  if (LEFT && t == K0 / kGT) {           // the last unit of the LEFT launch
+  const int kb = lu_kb(n, K0);
+  if (LEFT && t == (K0 + kGT - 1) / kGT) {   // the last unit of the LEFT launch
     linv_body(it, K0);
     return;
   }
   const int c0 = LEFT ? t * kGT : K0 + kb + t * kGT;
   const int c1 = min(LEFT ? K0 : ld, c0 + kGT);
-  const int par = (K0 / kOuter) & 1;
+  const int par = lu_step(n, K0) & 1;
   if (tid == 0) perm.count = W->count[par];
   for (int e = tid; e < 2 * kOuter; e += (int)blockDim.x) {
     perm.rows[e] = W->rows[par][e];
@@ -1394,20 +1419,20 @@ __device__ __attribute__((always_inline)) void urow_body(const GItem& it, int K0
 // A[K0 + 128 t .., K0 : K0 + kb] -= L[.., 0 : K0] U[0 : K0, K0 : K0 + kb].
 __device__ __attribute__((always_inline)) void pupd_body(const GItem& it, int K0, int t, GemmLds& g) {
   const int n = it.n;
-  const int kb = min(kOuter, n - K0);
+  const int kb = lu_kb(n, K0);
   const int ra = K0 + t * kGT;
   gemm_sub<kGemmThreads>(it.A, it.ld, ra, min(n, ra + kGT), K0, K0 + kb, 0, K0, g);
 }
 
 // Back substitution U W = R' on columns [n, n + nrhs), from the bottom in
-// blocks of kOuter rows aligned with the factorisation: the diagonal block is
+// blocks of rows aligned with the factorisation's steps: the diagonal block is
 // solved by its 32-row triangles (stored inverses on MFMA) and MFMA updates
 // inside the block ...
 __device__ __attribute__((always_inline)) void bdiag_body(const GItem& it, int k0, MatLds& u) {
   gdouble* A = it.A;
   const int n = it.n, ld = it.ld, nrhs = it.nrhs;
   const int tid = threadIdx.x;
-  const int k1 = min(n, k0 + kOuter);
+  const int k1 = k0 + lu_kb(n, k0);
   for (int a0 = k0 + (k1 - 1 - k0) / kTB * kTB; a0 >= k0; a0 -= kTB) {
     const int b1 = min(k1, a0 + kTB);
     for (int idx = tid; idx < kTB * kTB; idx += kThreads)
@@ -1426,7 +1451,7 @@ __device__ __attribute__((always_inline)) void bdiag_body(const GItem& it, int k
 // block instead of one short product per block above each solved one).
 __device__ __attribute__((always_inline)) void bupd_body(const GItem& it, int k0, GemmLds& g) {
   const int n = it.n;
-  const int k1 = min(n, k0 + kOuter);
+  const int k1 = k0 + lu_kb(n, k0);
   gemm_sub<kGemmThreads>(it.A, it.ld, k0, k1, n, n + it.nrhs, k1, n, g);
 }
 
@@ -1456,7 +1481,7 @@ __device__ __forceinline__ int xcd_index() {
 }
 
 __device__ __forceinline__ int back_block(const GItem& it, int step) {
-  return ((it.n + kOuter - 1) / kOuter - 1 - step) * kOuter;
+  return lu_k0(it.n, lu_steps(it.n) - 1 - step);
 }
 
 // The register-panel kernel of the taller panels (orders above kOwnMax).
@@ -1466,7 +1491,8 @@ __device__ __attribute__((always_inline)) void panel_launch(const LuItem* __rest
                                                             PanelShared<NB>& sh) {
   const int gi = blockIdx.x;                 // one workgroup per matrix
   if (gi >= pre[count]) return;
-  panel_body<ROWS, NB>(gitem(items[owner(pre, count, gi)]), step * kOuter, sh);
+  const int m = owner(pre, count, gi);
+  panel_body<ROWS, NB>(gitem(items[m]), lu_k0(items[m].n, step), sh);
 }
 
 // Row-ownership panel: one workgroup per matrix, a thread per panel row
@@ -1477,7 +1503,8 @@ __global__ __launch_bounds__(kOwnMax) void lu_panel_own_kernel(const LuItem* __r
   __shared__ __attribute__((aligned(16))) OwnLds sh;
   const int gi = blockIdx.x;                 // one workgroup per matrix
   if (gi >= pre[count]) return;
-  panel_own_body(gitem(items[owner(pre, count, gi)]), step * kOuter, sh);
+  const int m = owner(pre, count, gi);
+  panel_own_body(gitem(items[m]), lu_k0(items[m].n, step), sh);
 }
 
 template <int ROWS, int NB>
@@ -1502,12 +1529,12 @@ __global__ __launch_bounds__(LEFT ? kThreads : kGemmThreads) __attribute__((amdg
     const int gi = xcd_index();
     if (gi >= total) return;
     const int m = owner(pre, count, gi);
-    urow_body<LEFT>(gitem(items[m]), step * kOuter, gi - pre[m] + OFF, u, perm);
+    urow_body<LEFT>(gitem(items[m]), lu_k0(items[m].n, step), gi - pre[m] + OFF, u, perm);
     return;
   }
   for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
     const int m = owner(pre, count, gi);
-    urow_body<LEFT>(gitem(items[m]), step * kOuter, gi - pre[m] + OFF, u, perm);
+    urow_body<LEFT>(gitem(items[m]), lu_k0(items[m].n, step), gi - pre[m] + OFF, u, perm);
     __syncthreads();
   }
 }
@@ -1521,12 +1548,12 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(2)
     const int gi = xcd_index();
     if (gi >= total) return;
     const int m = owner(pre, count, gi);
-    pupd_body(gitem(items[m]), step * kOuter, gi - pre[m], g);
+    pupd_body(gitem(items[m]), lu_k0(items[m].n, step), gi - pre[m], g);
     return;
   }
   for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
     const int m = owner(pre, count, gi);
-    pupd_body(gitem(items[m]), step * kOuter, gi - pre[m], g);
+    pupd_body(gitem(items[m]), lu_k0(items[m].n, step), gi - pre[m], g);
   }
 }
 
@@ -1579,11 +1606,11 @@ int lu_plan_tiles(const LuItem& it, int kind, int step) {
   const int n = it.n, ld = it.ld;
   const int nsteps = (n + kOuter - 1) / kOuter;
   if (step >= nsteps) return 0;
-  const int K0 = step * kOuter, kb = std::min(kOuter, n - K0);
+  const int K0 = lu_k0(n, step), kb = lu_kb(n, K0);
   switch (kind) {
     case LU_PANEL0: case LU_PANEL1: case LU_PANEL2: case LU_PANEL3:
       return it.cls == kind - LU_PANEL0 ? 1 : 0;
-    case LU_LSWAP: return K0 / kGT + 1;     // the left tiles, then L11^-1
+    case LU_LSWAP: return (K0 + kGT - 1) / kGT + 1;     // the left tiles, then L11^-1
     case LU_UROW0: return (ld - K0 - kb + kGT - 1) / kGT > 0 ? 1 : 0;
     case LU_UREST: return std::max(0, (ld - K0 - kb + kGT - 1) / kGT - 1);
     case LU_PUPD: return K0 > 0 ? (n - K0 + kGT - 1) / kGT : 0;
@@ -1616,9 +1643,9 @@ void LuPlan::build(const std::vector<LuItem>& its) {
   own_threads.assign((size_t)2 * nsteps, kWave);
   for (const auto& it : its)
     if (it.cls <= 1)
-      for (int s = 0; s * kOuter < it.n; ++s) {
+      for (int s = 0; s < lu_steps(it.n); ++s) {
         int32_t& t = own_threads[(size_t)it.cls * nsteps + s];
-        t = std::max(t, (it.n - s * kOuter + kWave - 1) / kWave * kWave);
+        t = std::max(t, (it.n - lu_k0(it.n, s) + kWave - 1) / kWave * kWave);
       }
   d_items.upload(items);
   d_pre.upload(pre);
