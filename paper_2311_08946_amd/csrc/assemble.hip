@@ -668,7 +668,7 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
     a.out_steps = out_steps.ptr<uint64_t>();
     a.out_capped = out_capped.ptr<uint64_t>();
     a.out_gamma = out_gamma.ptr<uint64_t>();
-    launch_mc_paths(P, dp.const_coef != 0, a, side);
+    launch_mc_paths(P, dp, a, side);
     launch_gram_cholesky(a, (int32_t)n_perim, gram.ptr<double>(), gram_status.ptr<int32_t>(), side);
     launch_mc_finalize(a, (int32_t)n_mc, H.max_arc, gram.ptr<double>(), val, se, bv, se_b, side);
     PDD_HIP(hipGetLastError());

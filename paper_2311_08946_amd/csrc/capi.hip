@@ -279,6 +279,23 @@ static pdd_status to_dev_field(const pdd_field& f, DevField& d, const char* name
       d.b[q] = f.b[q];
       if (f.kind == PDD_FIELD_SINSUM) { d.c[q] = f.c[q]; d.d[q] = f.d[q]; }
     }
+    if (f.kind == PDD_FIELD_SINSUM) {
+      // integer wave numbers: a_q sin(2 pi (b_q x + c_q y) + d_q)
+      //   = Im(a_q e^{i d_q} E^{b_q} F^{c_q}), E = e^{2 pi i x}, F = e^{2 pi i y}
+      bool wave = true;
+      for (int q = 0; q < f.n_terms; ++q)
+        wave = wave && f.b[q] == std::nearbyint(f.b[q]) && f.c[q] == std::nearbyint(f.c[q]) &&
+               std::fabs(f.b[q]) <= kWaveMax && std::fabs(f.c[q]) <= kWaveMax;
+      d.wave = wave ? 1 : 0;
+      for (int q = 0; wave && q < f.n_terms; ++q) {
+        d.ix[q] = (int32_t)std::fabs(f.b[q]);
+        d.iy[q] = (int32_t)std::fabs(f.c[q]);
+        d.sx[q] = f.b[q] < 0 ? -1.0 : 1.0;
+        d.sy[q] = f.c[q] < 0 ? -1.0 : 1.0;
+        d.wr[q] = f.a[q] * std::cos(f.d[q]);
+        d.wi[q] = f.a[q] * std::sin(f.d[q]);
+      }
+    }
   }
   return PDD_OK;
 }
@@ -297,6 +314,14 @@ pdd_status make_dev_problem(const pdd_problem& p, DevProblem& D) {
   bool allc = true;
   for (int t = 0; t < 7; ++t) allc = allc && fs[t]->kind == PDD_FIELD_CONST;
   D.const_coef = allc ? 1 : 0;
+  auto wave_or_const = [&](int t) {
+    return D.fld[t].kind == PDD_FIELD_CONST || (D.fld[t].kind == PDD_FIELD_SINSUM && D.fld[t].wave);
+  };
+  bool all = !allc;
+  for (int t = 0; t < 6; ++t) all = all && wave_or_const(t);
+  all = all && (wave_or_const(F_F) || (D.fld[F_F].kind == PDD_FIELD_DERIVED_F &&
+                                       D.fld[F_U].kind == PDD_FIELD_SINSUM && D.fld[F_U].wave));
+  D.wave_all = all ? 1 : 0;
   for (int t = 0; t < 7; ++t) D.k[t] = fs[t]->base;
   if (p.domain.kind == PDD_DOMAIN_DISK && (p.domain.n_holes < 0 || p.domain.n_holes > PDD_MAX_HOLES))
     return fail(PDD_EINVAL, "too many holes");

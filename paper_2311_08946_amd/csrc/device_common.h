@@ -9,10 +9,19 @@
 
 namespace pdd {
 
+// Largest |wave number| of a sine-sum term that the Monte Carlo kernels
+// evaluate from a per-lane table of powers instead of a sine per term.
+constexpr int kWaveMax = 4;
+
 struct DevField {
-  int32_t kind, n, clip, pad;
+  int32_t kind, n, clip;
+  int32_t wave;          // SINSUM with integer wave numbers, |b|, |c| <= kWaveMax
   double base;
   double a[PDD_MAX_TERMS], b[PDD_MAX_TERMS], c[PDD_MAX_TERMS], d[PDD_MAX_TERMS];
+  // with `wave`: term q is Im(w_q e^{2 pi i (b_q x + c_q y)}), w_q = a_q e^{i d_q}
+  // = (wr_q, wi_q); ix, iy = |b_q|, |c_q|; sx, sy = their signs (+1 for 0)
+  int32_t ix[PDD_MAX_TERMS], iy[PDD_MAX_TERMS];
+  double sx[PDD_MAX_TERMS], sy[PDD_MAX_TERMS], wr[PDD_MAX_TERMS], wi[PDD_MAX_TERMS];
 };
 
 enum { F_AXX = 0, F_AXY, F_AYY, F_BX, F_BY, F_C, F_F, F_G, F_U, F_COUNT };
@@ -21,7 +30,8 @@ struct DevProblem {
   pdd_domain dom;
   DevField fld[F_COUNT];
   int32_t const_coef;        // every coefficient and f is PDD_FIELD_CONST
-  int32_t pad;
+  int32_t wave_all;          // every coefficient and f is CONST or a `wave` sine sum (f
+                             // possibly derived from a `wave` u), and not all are CONST
   double k[7];               // their values when const_coef
 };
 
@@ -136,6 +146,90 @@ __device__ __forceinline__ void coefficients_at(const DevProblem& P, double x, d
               co[4] * j[2] + co[5] * j[0]);
   } else {
     co[6] = field_plain(F, x, y);
+  }
+}
+
+// Per-lane table of the powers E^k and F^k, k = 0 .. kWaveMax, of
+// E = e^{2 pi i x} and F = e^{2 pi i y} (E^k at p[k stride], F^k at
+// p[(kWaveMax + 1 + k) stride], each as (re, im)), so that a sine-sum term
+// with integer wave numbers costs a complex product instead of a sine:
+// a sin(2 pi (b x + c y) + d) = Im(a e^{i d} E^b F^c), E^-k = conj(E^k).
+struct WaveTab {
+  double2* p;   // this lane's first entry (LDS)
+  int stride;   // entries between powers
+};
+
+__device__ __forceinline__ void wave_fill(const WaveTab& t, double x, double y) {
+  double es, ec, fs, fc;
+  sincospi(2.0 * x, &es, &ec);
+  sincospi(2.0 * y, &fs, &fc);
+  double er = 1.0, ei = 0.0, fr = 1.0, fi = 0.0;
+#pragma unroll
+  for (int k = 0; k <= kWaveMax; ++k) {
+    t.p[k * t.stride] = double2{er, ei};
+    t.p[(kWaveMax + 1 + k) * t.stride] = double2{fr, fi};
+    const double er1 = er * ec - ei * es, ei1 = er * es + ei * ec;
+    const double fr1 = fr * fc - fi * fs, fi1 = fr * fs + fi * fc;
+    er = er1; ei = ei1; fr = fr1; fi = fi1;
+  }
+}
+
+// e^{2 pi i (b_q x + c_q y)} of term q from the table
+__device__ __forceinline__ void wave_term(const DevField& F, int q, const WaveTab& t, double& zr, double& zi) {
+  const double2 e = t.p[F.ix[q] * t.stride];
+  const double2 f = t.p[(kWaveMax + 1 + F.iy[q]) * t.stride];
+  const double ey = F.sx[q] * e.y, fy = F.sy[q] * f.y;
+  zr = e.x * f.x - ey * fy;
+  zi = e.x * fy + ey * f.x;
+}
+
+__device__ __forceinline__ double sinsum_tab(const DevField& F, const WaveTab& t) {
+  double v = F.base;
+  for (int q = 0; q < F.n; ++q) {
+    double zr, zi;
+    wave_term(F, q, t, zr, zi);
+    v += F.wr[q] * zi + F.wi[q] * zr;
+  }
+  if (F.clip) v = fmin(v, 0.0);
+  return v;
+}
+
+// field_jet of a `wave` sine sum from the table
+__device__ __forceinline__ void sinsum_jet_tab(const DevField& F, const WaveTab& t, double* j) {
+  double u = F.base, ux = 0, uy = 0, uxx = 0, uxy = 0, uyy = 0;
+  for (int q = 0; q < F.n; ++q) {
+    double zr, zi;
+    wave_term(F, q, t, zr, zi);
+    const double as = F.wr[q] * zi + F.wi[q] * zr;   // a sin(theta)
+    const double ac = F.wr[q] * zr - F.wi[q] * zi;   // a cos(theta)
+    const double kx = kTwoPiD * F.b[q], ky = kTwoPiD * F.c[q];
+    u += as;
+    ux += kx * ac;
+    uy += ky * ac;
+    uxx -= kx * kx * as;
+    uxy -= kx * ky * as;
+    uyy -= ky * ky * as;
+  }
+  j[0] = u; j[1] = ux; j[2] = uy; j[3] = uxx; j[4] = uxy; j[5] = uyy;
+}
+
+// coefficients_at for the Monte Carlo kernels when `wave_all` holds: the
+// table is filled for (x, y) and every sine sum read from it.
+__device__ __forceinline__ void coefficients_wave(const DevProblem& P, double x, double y, double* co,
+                                                  const WaveTab& t) {
+  wave_fill(t, x, y);
+  for (int k = 0; k < 6; ++k) {
+    const DevField& F = P.fld[k];
+    co[k] = F.kind == PDD_FIELD_CONST ? F.base : sinsum_tab(F, t);
+  }
+  const DevField& F = P.fld[F_F];
+  if (F.kind == PDD_FIELD_DERIVED_F) {
+    double j[6];
+    sinsum_jet_tab(P.fld[F_U], t, j);
+    co[6] = -(0.5 * co[0] * j[3] + co[1] * j[4] + 0.5 * co[2] * j[5] + co[3] * j[1] +
+              co[4] * j[2] + co[5] * j[0]);
+  } else {
+    co[6] = F.kind == PDD_FIELD_CONST ? F.base : sinsum_tab(F, t);
   }
 }
 

@@ -44,7 +44,8 @@ struct McArgs {
   int64_t gram_stride;         // max_arc^2
 };
 
-void launch_mc_paths(const DevProblem* P, bool const_coef, const McArgs& a, hipStream_t st);
+// `host`: the host copy of *P (selects the kernel variant).
+void launch_mc_paths(const DevProblem* P, const DevProblem& host, const McArgs& a, hipStream_t st);
 void launch_gram_cholesky(const McArgs& a, int32_t n_perim, double* Lf, int32_t* status,
                           hipStream_t st);
 void launch_mc_finalize(const McArgs& a, int32_t n_mc, int32_t max_arc, const double* Lf,

@@ -23,6 +23,7 @@ namespace pdd {
 namespace {
 
 constexpr int kW = 64;
+constexpr int kCoefGeneral = 0, kCoefConst = 1, kCoefWave = 2;
 
 // Lane l's double, read by every lane (l wavefront-uniform).
 __device__ __forceinline__ double readlane_f64(double v, int l) {
@@ -172,7 +173,10 @@ __device__ __forceinline__ bool near_boundary(const pdd_domain& d, double qx, do
   return false;
 }
 
-template <bool CONST_COEF, bool SHIFT>
+// COEF: kCoefGeneral, kCoefConst (constant coefficients, Laplace-type
+// problems) or kCoefWave (every variable field a sine sum with integer wave
+// numbers, evaluated from the per-lane power table).
+template <int COEF, bool SHIFT>
 __device__ __forceinline__ void paths_body(const DevProblem* __restrict__ P, const McArgs& a) {
   const int lane = threadIdx.x & 63;
   const int64_t unit = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -195,6 +199,11 @@ __device__ __forceinline__ void paths_body(const DevProblem* __restrict__ P, con
   const uint32_t key0 = (uint32_t)a.seed, key1 = (uint32_t)(a.seed >> 32);
   const int cap = a.step_cap;
   const DevProblem& PP = *P;
+  // this lane's table of the powers of e^{2 pi i x}, e^{2 pi i y} (variable
+  // coefficients with integer wave numbers)
+  constexpr bool CONST_COEF = COEF == kCoefConst;
+  __shared__ double2 wtab[COEF == kCoefWave ? 2 * (kWaveMax + 1) : 1][256];
+  const WaveTab tab{&wtab[0][threadIdx.x], 256};
 
   // arc knots in chunks of 64 (lane l holds knot l + 64 s); chunks is uniform
   const int chunks = (n_arc + kW - 1) / kW;
@@ -240,7 +249,8 @@ __device__ __forceinline__ void paths_body(const DevProblem* __restrict__ P, con
         bx = kbx; by = kby; cc = kc; ff = kf; a11 = s11; a21 = s21; a22 = s22; ec = eck;
       } else {
         double co[7];
-        coefficients_at(PP, x, y, co);
+        if (COEF == kCoefWave) coefficients_wave(PP, x, y, co, tab);
+        else coefficients_at(PP, x, y, co);
         a11 = sqrt(co[0]);
         a21 = co[1] / a11;
         a22 = sqrt(co[2] - a21 * a21);
@@ -290,7 +300,17 @@ __device__ __forceinline__ void paths_body(const DevProblem* __restrict__ P, con
           Ze = Z + ff * Y * ts * h;
           on_gamma = tc <= td;
         }
-        acc_g += (on_gamma ? 0.0 : boundary_value(PP, xe, ye) * Ye) + Ze;
+        double gv = 0.0;
+        if (!on_gamma) {
+          const DevField& G = PP.fld[F_G];
+          if (COEF == kCoefWave && G.kind == PDD_FIELD_SINSUM && G.wave) {
+            wave_fill(tab, xe, ye);          // the step's coefficients are done with the table
+            gv = sinsum_tab(G, tab);
+          } else {
+            gv = boundary_value(PP, xe, ye);
+          }
+        }
+        acc_g += (on_gamma ? 0.0 : gv * Ye) + Ze;
         steps += (uint64_t)k + 1;
         exited = true;
         if (on_gamma) {
@@ -352,17 +372,18 @@ __device__ __forceinline__ void paths_body(const DevProblem* __restrict__ P, con
   }
 }
 
-template <bool CONST_COEF>
-__global__ __launch_bounds__(256) void paths_kernel(const DevProblem* __restrict__ P, McArgs a) {
-  paths_body<CONST_COEF, false>(P, a);
+template <int COEF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void paths_kernel(
+    const DevProblem* __restrict__ P, McArgs a) {
+  paths_body<COEF, false>(P, a);
 }
 
 // The shifted scheme's extra live values would otherwise push the kernel
 // to one wavefront per SIMD.
-template <bool CONST_COEF>
+template <int COEF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void paths_shifted_kernel(
     const DevProblem* __restrict__ P, McArgs a) {
-  paths_body<CONST_COEF, true>(P, a);
+  paths_body<COEF, true>(P, a);
 }
 
 // Packed lower-triangle index (j <= i).
@@ -525,18 +546,16 @@ __global__ void boundary_rows_kernel(const DevProblem* __restrict__ P, const int
 
 }  // namespace
 
-void launch_mc_paths(const DevProblem* P, bool const_coef, const McArgs& a, hipStream_t st) {
+void launch_mc_paths(const DevProblem* P, const DevProblem& host, const McArgs& a, hipStream_t st) {
   if (a.n_units == 0) return;
   const unsigned blocks = (unsigned)((a.n_units + 3) / 4);
   const bool shift = a.scheme == 1;
-  if (const_coef && shift)
-    hipLaunchKernelGGL(paths_shifted_kernel<true>, dim3(blocks), dim3(256), 0, st, P, a);
-  else if (const_coef)
-    hipLaunchKernelGGL(paths_kernel<true>, dim3(blocks), dim3(256), 0, st, P, a);
-  else if (shift)
-    hipLaunchKernelGGL(paths_shifted_kernel<false>, dim3(blocks), dim3(256), 0, st, P, a);
-  else
-    hipLaunchKernelGGL(paths_kernel<false>, dim3(blocks), dim3(256), 0, st, P, a);
+  typedef void (*Kern)(const DevProblem*, McArgs);
+  Kern k;
+  if (host.const_coef) k = shift ? paths_shifted_kernel<kCoefConst> : paths_kernel<kCoefConst>;
+  else if (host.wave_all) k = shift ? paths_shifted_kernel<kCoefWave> : paths_kernel<kCoefWave>;
+  else k = shift ? paths_shifted_kernel<kCoefGeneral> : paths_kernel<kCoefGeneral>;
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, st, P, a);
 }
 
 void launch_gram_cholesky(const McArgs& a, int32_t n_perim, double* Lf, int32_t* status,
