@@ -421,27 +421,52 @@ def cpu_baseline_subprocess(workload, frac):
 
 # ------------------------------------------------------------------- report
 
-def measured_traffic(workload, phase):
-    """HBM bytes per step of a phase, from the rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary committed under profiles/ (calibrated against a copy kernel), or
-    None when there is none for this workload and phase, or when the kernel
-    source it was taken on has changed since (its SHA-256 is recorded)."""
+def _profile_value(name, key, sources):
+    """A number recorded in profiles/<name> (a committed rocprofv3 summary),
+    or None when the file is missing or the kernel sources it was taken on
+    have changed since: the summary records the SHA-256 of the listed
+    sources (under paper_2311_08946_amd/csrc/, concatenated in order)."""
     import hashlib
     import re
     here = os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(here, "profiles", f"hbm_traffic_{phase}_{workload}.md")
-    src = {"lu": "lu.hip", "bicgstab": "solve.hip"}.get(phase)
-    if src is None or not os.path.exists(path):
+    path = os.path.join(here, "profiles", name)
+    if not os.path.exists(path):
         return None
     text = open(path).read()
     m_sha = re.search(r"source_sha256: ([0-9a-f]{64})", text)
-    m_b = re.search(r"bytes_per_step: ([0-9]+)", text)
-    if not (m_sha and m_b):
+    m_v = re.search(key + r": ([0-9.eE+-]+)", text)
+    if not (m_sha and m_v):
         return None
-    with open(os.path.join(here, "paper_2311_08946_amd", "csrc", src), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != m_sha.group(1):
-            return None
-    return float(m_b.group(1))
+    h = hashlib.sha256()
+    for src in sources:
+        with open(os.path.join(here, "paper_2311_08946_amd", "csrc", src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != m_sha.group(1):
+        return None
+    return float(m_v.group(1))
+
+
+# kernel sources behind each phase's counters
+PHASE_SOURCES = {"lu": ["lu.hip"], "bicgstab": ["solve.hip"], "mc": ["mc.hip", "device_common.h"]}
+
+
+def measured_traffic(workload, phase):
+    """HBM bytes per step of a phase, from the FETCH_SIZE / WRITE_SIZE summary
+    profiles/hbm_traffic_<phase>_<workload>.md (calibrated against a copy
+    kernel), or None (no summary, or the kernels changed since)."""
+    if phase not in PHASE_SOURCES:
+        return None
+    return _profile_value(f"hbm_traffic_{phase}_{workload}.md", "bytes_per_step", PHASE_SOURCES[phase])
+
+
+def measured_valu(workload):
+    """VALU issue utilisation and lane instructions per path step of the paths
+    kernel, from profiles/pmc_valu_paths_<workload>.md, or None."""
+    util = _profile_value(f"pmc_valu_paths_{workload}.md", "valu_active_frac", PHASE_SOURCES["mc"])
+    per = _profile_value(f"pmc_valu_paths_{workload}.md", "valu_insts_per_path_step", PHASE_SOURCES["mc"])
+    if util is None or per is None:
+        return None
+    return {"valu_active_frac": util, "valu_insts_per_path_step": per}
 
 
 def phase_rooflines(cover, cfg, results, with_adj):
@@ -559,6 +584,8 @@ def main():
     roof = phase_rooflines(cover, cfg, results, with_adj)
     for ph in roof:
         roof[ph]["traffic"] = measured_traffic(args.workload, ph)
+    if "mc" in roof:
+        roof["mc"]["counters"] = measured_valu(args.workload)
     # the headline roofline: the phase that takes the most time per step
     dom = max(roof, key=lambda k: roof[k]["ms"])
     kernels = {
