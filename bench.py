@@ -584,6 +584,11 @@ def main():
     roof = phase_rooflines(cover, cfg, results, with_adj)
     for ph in roof:
         roof[ph]["traffic"] = measured_traffic(args.workload, ph)
+    if "bicgstab" in roof:
+        per_it = _profile_value(f"hbm_traffic_bicgstab_{args.workload}.md", "bytes_per_iteration",
+                                PHASE_SOURCES["bicgstab"])
+        its = results[-1]["iters"] + results[-1]["iters_t"]     # as in the roofline's work
+        roof["bicgstab"]["traffic"] = per_it * its if per_it is not None else None
     if "mc" in roof:
         roof["mc"]["counters"] = measured_valu(args.workload)
     # the headline roofline: the phase that takes the most time per step
