@@ -519,7 +519,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="config5")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default=None,
+                    help="default: config5 (config2 with --ras, whose dense part inverses are sized "
+                         "for 32x32 circles)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -532,6 +534,8 @@ def main():
     ap.add_argument("--ras", default=None, metavar="PXxPY",
                     help="instead of the step, measure GMRES with the RAS preconditioner of PXxPY parts")
     args = ap.parse_args()
+    if args.workload is None:
+        args.workload = "config2" if args.ras else "config5"
     if args.cpu_baseline_only:
         print(json.dumps(cpu_baseline(args.workload, args.cpu_frac)), flush=True)
         return

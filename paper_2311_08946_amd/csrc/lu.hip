@@ -4,9 +4,10 @@
 //
 // Each matrix is the augmented array [A_II | R] (n x ld, row-major, R in
 // columns n .. n + nrhs).  Blocked factorisation in steps of kOuter = 128
-// columns, left-looking (Crout order: the trailing matrix is never updated as
-// a whole; each block is brought up to date with one long-K product when it
-// is reached), four launches per step over the whole batch:
+// columns (the first one shorter when n is not a multiple of 128),
+// left-looking (Crout order: the trailing matrix is never updated as a
+// whole; each block is brought up to date with one long-K product when it is
+// reached), four launches per step over the whole batch:
 //   * lu_pupd_kernel (one workgroup per matrix and 128-row tile of the
 //     panel): A[K0:n, K0:K0+128] -= L[K0:n, 0:K0] U[0:K0, K0:K0+128];
 //   * lu_panel_own_kernel (one workgroup per matrix, a thread per panel row;
@@ -17,13 +18,14 @@
 //     MFMA update of the rest of the panel; the rows that moved are written
 //     to their positions once at the end.  It stores the step's composed row
 //     permutation and the inverses of the 32 x 32 diagonal blocks of L11 and
-//     U11 in a per-matrix work area.  Larger orders use lu_panel_wide_kernel
-//     (sub-panels of NB columns in registers, thread t owning rows
-//     k0 + t + 512 s, interchanges applied after each sub-panel);
-//   * lu_urow_kernel<LEFT> (one workgroup per matrix and 128-column tile
-//     left of the panel): applies the step's interchanges to L; one more
-//     workgroup per matrix forms L11^-1 from the inverses of its 32 x 32
-//     diagonal blocks;
+//     U11 in a per-matrix work area, and moves the left part (L) of the rows
+//     that moved.  Larger orders use lu_panel_wide_kernel (sub-panels of NB
+//     columns in registers, thread t owning rows k0 + t + 512 s, interchanges
+//     applied after each sub-panel);
+//   * lu_urow_kernel<LEFT> (one workgroup per matrix): forms L11^-1 from the
+//     inverses of its 32 x 32 diagonal blocks; after a wide panel, one more
+//     workgroup per 128-column tile left of the panel applies the step's
+//     interchanges to L;
 //   * lu_urow_kernel (one workgroup per matrix and 128-column tile right of
 //     the panel): applies the step's interchanges to the tile, brings rows
 //     [K0, K0 + kb) up to date with one long-K product and forms
@@ -1250,6 +1252,24 @@ __device__ __attribute__((always_inline)) void panel_own_body(const GItem& it, i
         if (c < gw) wr[c] = P[c];
     }
   }
+  // ... and so do their entries left of the panel (the step's interchanges
+  // on L; only the tiles right of the panel are left to the U-row launches)
+#pragma unroll 1
+  for (int c0 = 0; c0 < K0; c0 += kTB) {
+    const int cw = min(kTB, K0 - c0);
+    double P[kTB];
+    if (moved) {
+#pragma unroll
+      for (int c = 0; c < kTB; ++c) P[c] = arow[c0 + min(c, cw - 1)];
+    }
+    __syncthreads();
+    if (moved) {
+      gdouble* __restrict__ wr = A + (size_t)(K0 + pos) * ld + c0;
+#pragma unroll
+      for (int c = 0; c < kTB; ++c)
+        if (c < cw) wr[c] = P[c];
+    }
+  }
   // the step's permutation for the other columns: row K0 + t receives the
   // old contents of row K0 + who[t]
   __syncthreads();                           // the LDS is reused
@@ -1393,7 +1413,9 @@ __device__ __attribute__((always_inline)) void urow_body(const GItem& it, int K0
   const gwork* W = it.work;
   const int tid = threadIdx.x;
   const int kb = lu_kb(n, K0);
-  if (LEFT && t == (K0 + kGT - 1) / kGT) {   // the last unit of the LEFT launch
+  // the last unit of the LEFT launch (the only one where the row-ownership
+  // panel moved the rows left of it itself)
+  if (LEFT && t == (it.cls <= 1 ? 0 : (K0 + kGT - 1) / kGT)) {
     linv_body(it, K0);
     return;
   }
@@ -1610,7 +1632,8 @@ int lu_plan_tiles(const LuItem& it, int kind, int step) {
   switch (kind) {
     case LU_PANEL0: case LU_PANEL1: case LU_PANEL2: case LU_PANEL3:
       return it.cls == kind - LU_PANEL0 ? 1 : 0;
-    case LU_LSWAP: return (K0 + kGT - 1) / kGT + 1;     // the left tiles, then L11^-1
+    case LU_LSWAP:      // the left tiles, then L11^-1 (the row-ownership panels move their rows' left part)
+      return it.cls <= 1 ? 1 : (K0 + kGT - 1) / kGT + 1;
     case LU_UROW0: return (ld - K0 - kb + kGT - 1) / kGT > 0 ? 1 : 0;
     case LU_UREST: return std::max(0, (ld - K0 - kb + kGT - 1) / kGT - 1);
     case LU_PUPD: return K0 > 0 ? (n - K0 + kGT - 1) / kGT : 0;
