@@ -636,6 +636,7 @@ def main():
         "step_wall_ms": [round(r["wall_ms"], 1) for r in results],
         "schedule": {"plan": args.plan, "mixed_buckets": bool(st[-1].mixed_buckets),
                      "grid_cap": int(st[-1].grid_cap), "lookahead": bool(st[-1].lu_lookahead),
+                     "mc_after_floating": bool(st[-1].mc_after_floating),
                      "groups": int(st[-1].n_groups),
                      "graph_replays": int(st[-1].graph_replays), "lu_launches": int(st[-1].n_launch_spectral)},
         "factor_bytes_kept": int(st[-1].factor_bytes),

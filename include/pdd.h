@@ -336,7 +336,11 @@ typedef struct pdd_system_stats {
   float ms_autotune;       /* time spent tuning in this call (0 when cached)         */
   int64_t gamma_exits;     /* Monte Carlo paths that exited on the interface Gamma_m  */
   int32_t lu_lookahead;    /* 1: the LU launches used the look-ahead stream           */
-  int32_t reserved;
+  int32_t mc_after_floating; /* 1: the Monte Carlo rows ran after the floating rows
+                              instead of beside them (PDD_PLAN_AUTOTUNED does so when
+                              the previous assembly on the cover found the Monte Carlo
+                              work at least 0.8 times as long as the floating rows:
+                              the LU launches then only wait for it to free the CUs) */
 } pdd_system_stats;
 
 pdd_status pdd_system_get_stats(pdd_system sys, pdd_system_stats* out);

@@ -94,7 +94,7 @@ class SystemStats(C.Structure):
                [("factor_bytes", C.c_int64), ("recompute", C.c_int32), ("n_groups", C.c_int32),
                 ("mixed_buckets", C.c_int32), ("grid_cap", C.c_int32), ("graph_replays", C.c_int32),
                 ("ms_autotune", C.c_float), ("gamma_exits", C.c_int64), ("lu_lookahead", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("mc_after_floating", C.c_int32)]
 
 
 class SolveOpts(C.Structure):

@@ -609,7 +609,11 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
     sched.lookahead = D.tuned_lookahead;
   }
   // The Monte Carlo and boundary rows run on a second stream, concurrently
-  // with the floating rows; both write disjoint rows of the CSR arrays.
+  // with the floating rows; both write disjoint rows of the CSR arrays.  When
+  // the last autotuned assembly on this cover found the Monte Carlo work about
+  // as long as the floating rows, the floating rows gained nothing beside it
+  // (their panels need whole CUs, which its workgroups keep refilling): it
+  // then starts after them.
   DevBuf lu_fail;
   lu_fail.alloc(sizeof(uint64_t) * 5);
   PDD_HIP(hipMemsetAsync(lu_fail.ptr<void>(), 0, sizeof(uint64_t) * 5, st));
@@ -622,73 +626,78 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
     hipEvent_t a, b;
     ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
   } ev_guard{ev_fork, ev_join};
-  PDD_HIP(hipEventRecord(ev_fork, st));
-  PDD_HIP(hipStreamWaitEvent(side, ev_fork, 0));
+  const bool mc_after = plan == PDD_PLAN_AUTOTUNED && D.last_ms_mc > 0.0f &&
+                        D.last_ms_mc >= 0.8f * D.last_ms_float;
 
   // ---- perimeter rows by Monte Carlo (side stream)
   const int64_t n_mc = (int64_t)H.mc_knots.size();
   const int64_t n_perim = (int64_t)H.perim_ids.size();
   DevBuf out_phi, out_g, out_steps, out_capped, out_gamma, gram, gram_status, hcirc;
   int32_t n_launch_mc = 0;
-  if (n_mc > 0) {
-    const int e = timer.begin(PH_MC, side);
-    McArgs a{};
-    a.mc_knots = D.mc_knots.ptr<int32_t>();
-    a.assigned = D.assigned.ptr<int32_t>();
-    a.perim_ids = D.perim_ids.ptr<int32_t>();
-    a.perim_pos = D.perim_pos.ptr<int32_t>();
-    a.cx = D.cx.ptr<double>(); a.cy = D.cy.ptr<double>(); a.rad = D.rad.ptr<double>();
-    a.arc0 = D.arc0.ptr<double>(); a.arc1 = D.arc1.ptr<double>(); a.rbf_c2 = D.rbf_c2.ptr<double>();
-    a.knot_off = D.knot_off.ptr<int64_t>();
-    a.kx = D.kx.ptr<double>(); a.ky = D.ky.ptr<double>(); a.ktheta = D.ktheta.ptr<double>();
-    a.rowptr = D.rowptr.ptr<int64_t>();
-    if (mc->h_per_circle) {
-      std::vector<double> hv(mc->h_per_circle, mc->h_per_circle + H.nc);
-      hcirc.upload(hv);
-      a.h_circle = hcirc.ptr<double>();
+  auto mc_rows = [&]() {
+    PDD_HIP(hipEventRecord(ev_fork, st));
+    PDD_HIP(hipStreamWaitEvent(side, ev_fork, 0));
+    if (n_mc > 0) {
+      const int e = timer.begin(PH_MC, side);
+      McArgs a{};
+      a.mc_knots = D.mc_knots.ptr<int32_t>();
+      a.assigned = D.assigned.ptr<int32_t>();
+      a.perim_ids = D.perim_ids.ptr<int32_t>();
+      a.perim_pos = D.perim_pos.ptr<int32_t>();
+      a.cx = D.cx.ptr<double>(); a.cy = D.cy.ptr<double>(); a.rad = D.rad.ptr<double>();
+      a.arc0 = D.arc0.ptr<double>(); a.arc1 = D.arc1.ptr<double>(); a.rbf_c2 = D.rbf_c2.ptr<double>();
+      a.knot_off = D.knot_off.ptr<int64_t>();
+      a.kx = D.kx.ptr<double>(); a.ky = D.ky.ptr<double>(); a.ktheta = D.ktheta.ptr<double>();
+      a.rowptr = D.rowptr.ptr<int64_t>();
+      if (mc->h_per_circle) {
+        std::vector<double> hv(mc->h_per_circle, mc->h_per_circle + H.nc);
+        hcirc.upload(hv);
+        a.h_circle = hcirc.ptr<double>();
+      }
+      a.h = mc->h;
+      a.seed = mc->seed;
+      a.paths = mc->paths;
+      a.n_batches = mc->n_batches;
+      a.step_cap = mc->step_cap;
+      a.scheme = mc->scheme;
+      a.n_units = n_mc * mc->n_batches;
+      a.out_stride = std::max<int64_t>(1, H.max_arc);
+      a.gram_stride = (int64_t)H.max_arc * (H.max_arc + 1) / 2;
+      out_phi.alloc(std::max<int64_t>(1, a.n_units * a.out_stride) * sizeof(double));
+      out_g.alloc(std::max<int64_t>(1, a.n_units) * sizeof(double));
+      out_steps.alloc(std::max<int64_t>(1, a.n_units) * sizeof(uint64_t));
+      out_capped.alloc(std::max<int64_t>(1, a.n_units) * sizeof(uint64_t));
+      out_gamma.alloc(std::max<int64_t>(1, a.n_units) * sizeof(uint64_t));
+      gram.alloc(std::max<int64_t>(1, n_perim * a.gram_stride) * sizeof(double));
+      gram_status.alloc(std::max<int64_t>(1, n_perim) * sizeof(int32_t));
+      a.out_phi = out_phi.ptr<double>();
+      a.out_g = out_g.ptr<double>();
+      a.out_steps = out_steps.ptr<uint64_t>();
+      a.out_capped = out_capped.ptr<uint64_t>();
+      a.out_gamma = out_gamma.ptr<uint64_t>();
+      launch_mc_paths(P, dp, a, side);
+      launch_gram_cholesky(a, (int32_t)n_perim, gram.ptr<double>(), gram_status.ptr<int32_t>(), side);
+      launch_mc_finalize(a, (int32_t)n_mc, H.max_arc, gram.ptr<double>(), val, se, bv, se_b, side);
+      PDD_HIP(hipGetLastError());
+      hipLaunchKernelGGL(reduce_u64_kernel, dim3(1), dim3(256), 0, side, out_steps.ptr<uint64_t>(),
+                         a.n_units, lu_fail.ptr<uint64_t>() + 1);
+      hipLaunchKernelGGL(reduce_u64_kernel, dim3(1), dim3(256), 0, side, out_capped.ptr<uint64_t>(),
+                         a.n_units, lu_fail.ptr<uint64_t>() + 2);
+      if (n_perim > 0)
+        hipLaunchKernelGGL(reduce_i32_kernel, dim3(1), dim3(256), 0, side, gram_status.ptr<int32_t>(),
+                           n_perim, lu_fail.ptr<uint64_t>() + 3);
+      hipLaunchKernelGGL(reduce_u64_kernel, dim3(1), dim3(256), 0, side, out_gamma.ptr<uint64_t>(),
+                         a.n_units, lu_fail.ptr<uint64_t>() + 4);
+      n_launch_mc = 3;
+      timer.end(e);
     }
-    a.h = mc->h;
-    a.seed = mc->seed;
-    a.paths = mc->paths;
-    a.n_batches = mc->n_batches;
-    a.step_cap = mc->step_cap;
-    a.scheme = mc->scheme;
-    a.n_units = n_mc * mc->n_batches;
-    a.out_stride = std::max<int64_t>(1, H.max_arc);
-    a.gram_stride = (int64_t)H.max_arc * (H.max_arc + 1) / 2;
-    out_phi.alloc(std::max<int64_t>(1, a.n_units * a.out_stride) * sizeof(double));
-    out_g.alloc(std::max<int64_t>(1, a.n_units) * sizeof(double));
-    out_steps.alloc(std::max<int64_t>(1, a.n_units) * sizeof(uint64_t));
-    out_capped.alloc(std::max<int64_t>(1, a.n_units) * sizeof(uint64_t));
-    out_gamma.alloc(std::max<int64_t>(1, a.n_units) * sizeof(uint64_t));
-    gram.alloc(std::max<int64_t>(1, n_perim * a.gram_stride) * sizeof(double));
-    gram_status.alloc(std::max<int64_t>(1, n_perim) * sizeof(int32_t));
-    a.out_phi = out_phi.ptr<double>();
-    a.out_g = out_g.ptr<double>();
-    a.out_steps = out_steps.ptr<uint64_t>();
-    a.out_capped = out_capped.ptr<uint64_t>();
-    a.out_gamma = out_gamma.ptr<uint64_t>();
-    launch_mc_paths(P, dp, a, side);
-    launch_gram_cholesky(a, (int32_t)n_perim, gram.ptr<double>(), gram_status.ptr<int32_t>(), side);
-    launch_mc_finalize(a, (int32_t)n_mc, H.max_arc, gram.ptr<double>(), val, se, bv, se_b, side);
+    launch_boundary_rows(P, D0.bnd_knots.ptr<int32_t>(), (int32_t)H0.bnd_knots.size(), D0.kx.ptr<double>(),
+                         D0.ky.ptr<double>(), D0.rowptr.ptr<int64_t>(), sys->val.ptr<double>(),
+                         sys->se.ptr<double>(), sys->b.ptr<double>(), sys->se_b.ptr<double>(), side);
     PDD_HIP(hipGetLastError());
-    hipLaunchKernelGGL(reduce_u64_kernel, dim3(1), dim3(256), 0, side, out_steps.ptr<uint64_t>(),
-                       a.n_units, lu_fail.ptr<uint64_t>() + 1);
-    hipLaunchKernelGGL(reduce_u64_kernel, dim3(1), dim3(256), 0, side, out_capped.ptr<uint64_t>(),
-                       a.n_units, lu_fail.ptr<uint64_t>() + 2);
-    if (n_perim > 0)
-      hipLaunchKernelGGL(reduce_i32_kernel, dim3(1), dim3(256), 0, side, gram_status.ptr<int32_t>(),
-                         n_perim, lu_fail.ptr<uint64_t>() + 3);
-    hipLaunchKernelGGL(reduce_u64_kernel, dim3(1), dim3(256), 0, side, out_gamma.ptr<uint64_t>(),
-                       a.n_units, lu_fail.ptr<uint64_t>() + 4);
-    n_launch_mc = 3;
-    timer.end(e);
-  }
-  launch_boundary_rows(P, D0.bnd_knots.ptr<int32_t>(), (int32_t)H0.bnd_knots.size(), D0.kx.ptr<double>(),
-                       D0.ky.ptr<double>(), D0.rowptr.ptr<int64_t>(), sys->val.ptr<double>(),
-                       sys->se.ptr<double>(), sys->b.ptr<double>(), sys->se_b.ptr<double>(), side);
-  PDD_HIP(hipGetLastError());
-  PDD_HIP(hipEventRecord(ev_join, side));
+    PDD_HIP(hipEventRecord(ev_join, side));
+  };
+  if (!mc_after) mc_rows();
 
   // ---- floating rows in groups (see the schedule in pdd.h)
   const auto groups = make_groups(D, plan, keep_all, budget, sched.mixed);
@@ -720,6 +729,7 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
     n_launch_spectral += run.group(grp, fs, S, &timer, val, bv, lu_fail.ptr<uint64_t>());
   }
   run.finish();
+  if (mc_after) mc_rows();
 
   PDD_HIP(hipStreamWaitEvent(st, ev_join, 0));
   if (avg && N0 > 0) {
@@ -748,6 +758,7 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
   s.mixed_buckets = sched.mixed ? 1 : 0;
   s.grid_cap = sched.grid_cap;
   s.lu_lookahead = sched.lookahead ? 1 : 0;
+  s.mc_after_floating = mc_after ? 1 : 0;
   s.graph_replays = run.replays;
   s.ms_autotune = ms_tune;
   s.n_launch_mc = n_launch_mc;
@@ -758,6 +769,10 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
   s.ms_eval = timer.total(PH_EVAL);
   s.ms_mc = timer.total(PH_MC);
   s.ms_total = timer.total(PH_TOTAL);
+  if (plan == PDD_PLAN_AUTOTUNED) {
+    D.last_ms_mc = s.ms_mc;
+    D.last_ms_float = s.ms_sample + s.ms_build + s.ms_lu + s.ms_eval;
+  }
   if (s.breakdowns) {
     *out = sys.release();
     return fail(PDD_EBREAKDOWN, "pdd_assemble_G: zero pivot in a collocation LU or non-SPD Gram matrix");

@@ -108,6 +108,8 @@ struct DeviceCover {
   bool tuned_mixed = true;
   int tuned_cap = 0;
   bool tuned_lookahead = true;
+  // the last autotuned assembly's Monte Carlo and floating-row times (ms)
+  float last_ms_mc = 0.0f, last_ms_float = 0.0f;
   std::vector<std::unique_ptr<BucketData>> buckets;
   void upload(const HostCover& H);
   ChunkDesc chunk(const BucketData& b, int32_t first, int32_t count) const;
@@ -135,6 +137,7 @@ struct LuPlan {
   std::vector<int32_t> pre;      // [kind][step][count + 1]
   std::vector<int32_t> totals;   // [kind][step]
   std::vector<int32_t> own_threads;   // [class 0, 1][step]: block size of the row-ownership panels
+  bool wide_rhs = false;              // some matrix has more than 128 right-hand sides
   DevBuf d_items, d_pre;
   // the second stream of the look-ahead and its per-step events
   hipStream_t side = nullptr;
