@@ -1450,6 +1450,10 @@ __device__ __attribute__((always_inline)) void pupd_body(const GItem& it, int K0
 // blocks of rows aligned with the factorisation's steps: the diagonal block is
 // solved by its 32-row triangles (stored inverses on MFMA) and MFMA updates
 // inside the block ...
+// WIDE: right-hand sides beyond kGT columns (the updates inside the block
+// then go through the tiled product, whose registers would otherwise halve
+// the occupancy of the common case).
+template <bool WIDE>
 __device__ __attribute__((always_inline)) void bdiag_body(const GItem& it, int k0, MatLds& u) {
   gdouble* A = it.A;
   const int n = it.n, ld = it.ld, nrhs = it.nrhs;
@@ -1462,7 +1466,9 @@ __device__ __attribute__((always_inline)) void bdiag_body(const GItem& it, int k
     __syncthreads();
     tri_apply<kTB>(A, ld, a0, b1 - a0, n, n + nrhs, u.t);
     if (a0 > k0) {
-      if (nrhs <= kGT) strip_update(A, ld, k0, a0, n, n + nrhs, a0, b1, u.g.Lt);
+      // (the choice per matrix, not per batch, so that a matrix gets the same
+      // bits in any batch)
+      if (!WIDE || nrhs <= kGT) strip_update(A, ld, k0, a0, n, n + nrhs, a0, b1, u.g.Lt);
       else gemm_sub<kThreads>(A, ld, k0, a0, n, n + nrhs, a0, b1, u.g);
     }
   }
@@ -1579,13 +1585,14 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(2)
   }
 }
 
+template <bool WIDE>
 __global__ __launch_bounds__(kThreads) void lu_bdiag_kernel(const LuItem* __restrict__ items,
                                                             const int32_t* __restrict__ pre, int count, int step) {
   __shared__ MatLds u;
   const int gi = blockIdx.x;                 // one workgroup per matrix
   if (gi >= pre[count]) return;
   const GItem it = gitem(items[owner(pre, count, gi)]);
-  bdiag_body(it, back_block(it, step), u);
+  bdiag_body<WIDE>(it, back_block(it, step), u);
 }
 
 template <bool PERSISTENT>
@@ -1651,6 +1658,8 @@ LuPlan::~LuPlan() {
 void LuPlan::build(const std::vector<LuItem>& its) {
   items = its;
   count = (int32_t)its.size();
+  wide_rhs = false;
+  for (const auto& it : its) wide_rhs = wide_rhs || it.nrhs > kGT;
   nsteps = 0;
   for (const auto& it : its) nsteps = std::max(nsteps, (it.n + kOuter - 1) / kOuter);
   pre.assign((size_t)LU_KINDS * nsteps * (count + 1), 0);
@@ -1736,7 +1745,7 @@ int LuPlan::launch(hipStream_t st, int grid_cap, bool lookahead) const {
   if (rest >= 0) PDD_HIP(hipStreamWaitEvent(st, ev_rest[rest], 0));
   for (int s = 0; s < nsteps; ++s) {
     go(LU_BUPD, s, lu_bupd_kernel<false>, lu_bupd_kernel<true>, st);
-    go(LU_BDIAG, s, lu_bdiag_kernel, nullptr, st);
+    go(LU_BDIAG, s, wide_rhs ? lu_bdiag_kernel<true> : lu_bdiag_kernel<false>, nullptr, st);
   }
   return launches;
 }
