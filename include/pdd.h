@@ -275,6 +275,12 @@ typedef struct pdd_assemble_opts {
                               second stream beside the next step's panel
                               (look-ahead); 1: every LU launch in order on one
                               stream                                                  */
+  int32_t mc_order;        /* Monte Carlo rows against the floating rows: 0 = beside
+                              them, except that PDD_PLAN_AUTOTUNED starts them after
+                              the floating rows when the last assembly on the cover
+                              found them at least 0.8 times as long; 1 = always
+                              beside; 2 = always after.  The results are the same.  */
+  int32_t reserved;
 } pdd_assemble_opts;
 
 /*

@@ -79,10 +79,12 @@ class McOpts(C.Structure):
 class AssembleOpts(C.Structure):
     _fields_ = [("plan", C.c_int32), ("keep_factors", C.c_int32), ("hbm_budget_bytes", C.c_int64),
                 ("mixed_buckets", C.c_int32), ("grid_cap", C.c_int32), ("use_graph", C.c_int32),
-                ("no_lookahead", C.c_int32)]
+                ("no_lookahead", C.c_int32), ("mc_order", C.c_int32), ("reserved", C.c_int32)]
 
 
 PLANS = {"batched": 0, "per_circle": 1, "autotuned": 2}
+# the Monte Carlo rows beside the floating rows or after them (pdd_assemble_opts.mc_order)
+MC_ORDERS = {"auto": 0, "beside": 1, "after": 2}
 
 
 class SystemStats(C.Structure):
@@ -331,7 +333,7 @@ class System:
 
     def __init__(self, cover, problem, mc, samples=None, keep_factors=False, plan="batched",
                  hbm_budget_bytes=0, mixed_buckets=True, grid_cap=0, use_graph=False, lookahead=True,
-                 stream=None):
+                 mc_order="auto", stream=None):
         import torch
         L = lib()
         self.cover = cover
@@ -346,7 +348,7 @@ class System:
             mo.h_per_circle = _dptr(hpc)
         ao = AssembleOpts(PLANS[plan], int(bool(keep_factors)), int(hbm_budget_bytes),
                           int(bool(mixed_buckets)), int(grid_cap), int(bool(use_graph)),
-                          int(not lookahead))
+                          int(not lookahead), MC_ORDERS[mc_order], 0)
         sm = None
         if samples is not None:
             for k, v in samples.items():

@@ -626,8 +626,10 @@ pdd_status assemble_impl(pdd_cover cover, const pdd_problem* problem, const pdd_
     hipEvent_t a, b;
     ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
   } ev_guard{ev_fork, ev_join};
-  const bool mc_after = plan == PDD_PLAN_AUTOTUNED && D.last_ms_mc > 0.0f &&
-                        D.last_ms_mc >= 0.8f * D.last_ms_float;
+  const int mc_order = opts ? opts->mc_order : 0;
+  if (mc_order < 0 || mc_order > 2) return fail(PDD_EINVAL, "mc_order must be 0, 1 or 2");
+  const bool mc_after = mc_order == 2 || (mc_order == 0 && plan == PDD_PLAN_AUTOTUNED && D.last_ms_mc > 0.0f &&
+                                          D.last_ms_mc >= 0.8f * D.last_ms_float);
 
   // ---- perimeter rows by Monte Carlo (side stream)
   const int64_t n_mc = (int64_t)H.mc_knots.size();

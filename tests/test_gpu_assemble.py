@@ -136,8 +136,8 @@ def test_schedules_are_bitwise_equal():
     """Every schedule of the floating circles -- mixed-bucket or per-bucket
     groups, persistent grids of one or two workgroups per compute unit, graph
     replay, the autotuned choice, small factor budgets that split the work into
-    many groups -- runs the same arithmetic per circle, so C and r are
-    bitwise equal."""
+    many groups, the Monte Carlo rows beside or after them -- runs the same
+    arithmetic per circle and per path, so C and r are bitwise equal."""
     pdd = _gpu()
     import torch
     _say("[gpu] schedules")
@@ -156,6 +156,8 @@ def test_schedules_are_bitwise_equal():
             dict(hbm_budget_bytes=int(1.5 * per), mixed_buckets=False, use_graph=True),
             dict(plan="autotuned"),
             dict(plan="autotuned", use_graph=True),
+            dict(mc_order="after"),
+            dict(plan="autotuned", mc_order="beside"),
         ]
         for kw in variants:
             s = pdd.System(cv, prob, cfg["mc"], **kw)
@@ -163,5 +165,7 @@ def test_schedules_are_bitwise_equal():
                 assert torch.equal(a, b), (cfg["name"], kw)
             _say(f"[gpu] {cfg['name']} {kw}: groups {s.stats.n_groups}, graph replays {s.stats.graph_replays}, "
                  f"mixed {s.stats.mixed_buckets}, cap {s.stats.grid_cap}")
+            if "mc_order" in kw:
+                assert s.stats.mc_after_floating == (kw["mc_order"] == "after")
             if kw.get("hbm_budget_bytes") and cfg["name"] == "small_variable":
                 assert s.stats.n_groups > 1 and s.stats.graph_replays > 0
