@@ -337,10 +337,26 @@ __global__ __launch_bounds__(kEThreads) __attribute__((amdgpu_waves_per_eu(2))) 
         }
         Eb[t * (kEQ + 1) + qq] = e;
       }
-      // W rows q0 .. q0 + qn (columns n .. n + nrhs), zero-padded
-      for (int idx = tid; idx < kEQ * NC; idx += kEThreads) {
-        const int qq = idx / NC, c = idx - qq * NC;
-        Wb[qq * (NC + 1) + c] = (qq < qn && c < nrhs) ? A[(int64_t)(q0 + qq) * ld + n + c] : 0.0;
+      // W rows q0 .. q0 + qn (columns n .. n + nrhs), zero-padded: every load
+      // of the block issued before the first LDS store (entries outside it
+      // read the valid A[0] and are zeroed on the way in)
+      {
+        constexpr int kWPT = 8;                 // loads in flight per thread and pass
+#pragma unroll 1
+        for (int i0 = 0; i0 < kEQ * NC; i0 += kWPT * kEThreads) {
+          double wv[kWPT];
+#pragma unroll
+          for (int k = 0; k < kWPT; ++k) {
+            const int idx = i0 + tid + kEThreads * k, qq = idx / NC, c = idx - qq * NC;
+            const bool ok = idx < kEQ * NC && qq < qn && c < nrhs;
+            wv[k] = A[ok ? (int64_t)(q0 + qq) * ld + n + c : 0];
+          }
+#pragma unroll
+          for (int k = 0; k < kWPT; ++k) {
+            const int idx = i0 + tid + kEThreads * k, qq = idx / NC, c = idx - qq * NC;
+            if (idx < kEQ * NC) Wb[qq * (NC + 1) + c] = (qq < qn && c < nrhs) ? wv[k] : 0.0;
+          }
+        }
       }
       __syncthreads();
       mma();
@@ -354,15 +370,44 @@ __global__ __launch_bounds__(kEThreads) __attribute__((amdgpu_waves_per_eu(2))) 
         const int t = idx / kEQ, qq = idx - t * kEQ;
         Eb[t * (kEQ + 1) + qq] = qq < ln ? -eps[t * st + l0 + qq] : 0.0;
       }
-      for (int idx = tid; idx < kEQ * NC; idx += kEThreads) {
-        const int qq = idx / NC, c = idx - qq * NC;
-        Wb[qq * (NC + 1) + c] = (qq < ln && c < M) ? T.H[(int64_t)(l0 + qq) * M + c] : 0.0;
+      {
+        constexpr int kWPT = 8;
+#pragma unroll 1
+        for (int i0 = 0; i0 < kEQ * NC; i0 += kWPT * kEThreads) {
+          double hv[kWPT];
+#pragma unroll
+          for (int k = 0; k < kWPT; ++k) {
+            const int idx = i0 + tid + kEThreads * k, qq = idx / NC, c = idx - qq * NC;
+            const bool ok = idx < kEQ * NC && qq < ln && c < M;
+            hv[k] = T.H[ok ? (int64_t)(l0 + qq) * M + c : 0];
+          }
+#pragma unroll
+          for (int k = 0; k < kWPT; ++k) {
+            const int idx = i0 + tid + kEThreads * k, qq = idx / NC, c = idx - qq * NC;
+            if (idx < kEQ * NC) Wb[qq * (NC + 1) + c] = (qq < ln && c < M) ? hv[k] : 0.0;
+          }
+        }
       }
       __syncthreads();
       mma();
       __syncthreads();
     }
-    // D layout: acc[u][v] is knot 16 rb + 4 v + lk, column 16 cb + li
+    // D layout: acc[u][v] is knot 16 rb + 4 v + lk, column 16 cb + li.  The
+    // four knots' rows are looked up once, all loads at once (inside the
+    // store loop every lookup would wait for the one before: the stores
+    // may alias the index arrays as far as the compiler knows)
+    int kn[4];
+    int64_t kro[4];
+    {
+      const int64_t lo = C.knot_off[m];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int t = 16 * rb + 4 * v + lk;
+        kn[v] = C.fk_ids[base + (t < cnt ? t : 0)];
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) kro[v] = C.rowptr[kn[v]] + ((kn[v] < lo) ? 1 : 0);
+    }
 #pragma unroll
     for (int u = 0; u < kEMaxCB; ++u) {
       const int cb = cb0 + 2 * u;
@@ -373,14 +418,8 @@ __global__ __launch_bounds__(kEThreads) __attribute__((amdgpu_waves_per_eu(2))) 
           const int t = 16 * rb + 4 * v + lk;
           if (t < cnt) {
             const double x = acc[u][v];
-            const int i = C.fk_ids[base + t];
-            if (c < M) {
-              const int64_t lo = C.knot_off[m];
-              const int shift = (i < lo) ? 1 : 0;
-              val[C.rowptr[i] + shift + c] = x;
-            } else {
-              bvec[i] = x;
-            }
+            if (c < M) val[kro[v] + c] = x;
+            else bvec[kn[v]] = x;
           }
         }
       }
