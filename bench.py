@@ -469,6 +469,22 @@ def measured_valu(workload):
     return {"valu_active_frac": util, "valu_insts_per_path_step": per}
 
 
+def isolated_phases(cover, cfg, budget, plan, keep, reps=2):
+    """Median LU, Monte Carlo and build times of `reps` assemblies with the
+    Monte Carlo rows after the floating rows (untimed by the step): each phase
+    then has the GPU to itself, while in the step the Monte Carlo kernel shares
+    it with the build and the first LU panels."""
+    import numpy as np
+    import paper_2311_08946_amd.binding as pdd
+    st = []
+    for _ in range(reps):
+        sysm = pdd.System(cover, cfg["problem"], cfg["mc"], keep_factors=keep, hbm_budget_bytes=budget,
+                          plan=plan, mc_order="after")
+        st.append(sysm.stats)
+        del sysm
+    return {k: float(np.median([getattr(s, "ms_" + k) for s in st])) for k in ("lu", "mc", "build", "total")}
+
+
 def phase_rooflines(cover, cfg, results, with_adj):
     """One roofline entry per phase, each from times measured in this run."""
     import numpy as np
@@ -595,6 +611,13 @@ def main():
         roof["bicgstab"]["traffic"] = per_it * its if per_it is not None else None
     if "mc" in roof:
         roof["mc"]["counters"] = measured_valu(args.workload)
+        if not st[-1].mc_after_floating:
+            print("[bench] phases alone (Monte Carlo after the floating rows)", file=sys.stderr, flush=True)
+            iso = isolated_phases(cover, cfg, wl["budget"], args.plan, with_adj)
+            for ph in ("lu", "mc"):
+                a = roof[ph]["achieved"] * roof[ph]["ms"] / iso[ph]
+                roof[ph]["alone"] = {"ms": iso[ph], "achieved": a, "frac": a / roof[ph]["peak"],
+                                     "assembly_ms": iso["total"]}
     # the headline roofline: the phase that takes the most time per step
     dom = max(roof, key=lambda k: roof[k]["ms"])
     kernels = {
