@@ -10,10 +10,12 @@
 // assigned to m.  On the first solve of a system the values are re-laid out
 // per row -- the stencil entries in knot order at rowptr[i] - i, the diagonal
 // apart -- so that a product reads 8 bytes per entry and no column indices:
-//   C x   : a 16-lane group per row, y_i = C_ii x_i + sum_j V_ij x[so_i + j],
-//           the gathers from x contiguous; a wavefront takes 64 consecutive
-//           rows, their metadata in one round trip, and keeps the loads of
-//           16 rows in flight;
+//   C x   : a wavefront per circle m, y_i = C_ii x_i + sum_j V_ij x_{s0 + j}
+//           for the rows i assigned to m: the inputs at m's knots stay in
+//           registers (x_{s0 + j} in lane j, read once per circle rather than
+//           once per row), each row's entries one coalesced load (16 rows'
+//           loads in flight), and a butterfly over the lanes adds 16 rows at
+//           once; the boundary rows (C_ii alone) follow as one more list;
 //   C^T x : a wavefront per circle m, its lanes over the knots j of m,
 //           y_j = C_jj x_j + sum_{rows i of m} V_ij x_i, each row's entries
 //           one coalesced load (16 rows' loads in flight) and x_i broadcast
@@ -53,7 +55,7 @@ constexpr int kLanes = 16;           // lanes per row in the row products
 constexpr int kRowsPerPass = kThreads / kLanes;
 constexpr int kItersPerSync = 8;
 
-enum { OP_CSR = 0, OP_ROWS = 1, OP_CIRCLES = 2 };
+enum { OP_CSR = 0, OP_ROWS_BY_CIRCLE = 1, OP_CIRCLES = 2 };
 
 enum {
   S_RHO = 0, S_ALPHA, S_OMEGA, S_BETA, S_RV, S_TS, S_TT, S_RR, S_BB, S_TOL2, S_DONE, S_FAIL,
@@ -68,11 +70,11 @@ struct SolveCtx {
   const double* val;       // OP_CSR
   const double* vblk;      // blocked: stencil entries of row i at rowptr[i] - i
   const double* dg;        // blocked: diagonal
-  const int32_t* so;       // OP_ROWS: first knot of row i's stencil
-  const int64_t* knot_off; // OP_CIRCLES: knots of circle m are [knot_off[m], knot_off[m + 1])
-  const int64_t* circ_off; // OP_CIRCLES: rows of circle m are circ_rows[circ_off[m] ..)
+  const int64_t* knot_off; // blocked: knots of circle m are [knot_off[m], knot_off[m + 1])
+  const int64_t* circ_off; // blocked: rows of circle m are circ_rows[circ_off[m] ..), m <= nc
+                           // (list nc: the boundary rows)
   const int32_t* circ_rows;
-  const int64_t* circ_roff; // OP_CIRCLES: rowptr[i] - i of the row at each circ_rows slot
+  const int64_t* circ_roff; // blocked: rowptr[i] - i of the row at each circ_rows slot
   int32_t nc;
   int64_t N;
   double* x;
@@ -129,14 +131,28 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-__device__ __forceinline__ int64_t shfl_i64(int64_t v, int l) {
-  const int lo = __shfl((int)v, l, 64), hi = __shfl((int)(v >> 32), l, 64);
-  return ((int64_t)hi << 32) | (unsigned)lo;
-}
-
 __device__ __forceinline__ int64_t readlane_i64(int64_t v, int l) {
   const int lo = __builtin_amdgcn_readlane((int)v, l), hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
   return ((int64_t)hi << 32) | (unsigned)lo;
+}
+
+// Sums of 16 rows held across a wavefront: p[u] is this lane's term of row
+// u.  Four halving exchanges (lanes 32, 16, 8, 4 apart) each keep the half of
+// the rows named by that lane bit and add the partner's terms of them, then
+// two exchanges add the last four lanes: lanes 4u .. 4u + 3 end with the sum
+// of row u (the same order of additions whichever of them holds it).
+__device__ __forceinline__ double rows_sum16(const double (&p)[16], int lane) {
+  double a8[8], a4[4], a2[2];
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a8[k] = (b5 ? p[k + 8] : p[k]) + __shfl_xor(b5 ? p[k] : p[k + 8], 32, 64);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) a4[k] = (b4 ? a8[k + 4] : a8[k]) + __shfl_xor(b4 ? a8[k] : a8[k + 4], 16, 64);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) a2[k] = (b3 ? a4[k + 2] : a4[k]) + __shfl_xor(b3 ? a4[k] : a4[k + 2], 8, 64);
+  double a = (b2 ? a2[1] : a2[0]) + __shfl_xor(b2 ? a2[0] : a2[1], 4, 64);
+  a += __shfl_xor(a, 1, 64);
+  return a + __shfl_xor(a, 2, 64);
 }
 
 // Visits every output (A x)_i once, in a partition fixed by the grid, calling
@@ -144,6 +160,66 @@ __device__ __forceinline__ int64_t readlane_i64(int64_t v, int l) {
 template <int OPK, class X, class Sink>
 __device__ __forceinline__ void apply_op(const SolveCtx& c, const X& in, Sink& sink) {
   const int tid = threadIdx.x;
+  if (OPK == OP_ROWS_BY_CIRCLE) {
+    // C x by the circles the rows are assigned to: circle m's inputs x_j
+    // (its knots, the stencil of each of its rows) stay in registers, x_{s0+j}
+    // in lane j; its rows go sixteen at a time, lane j loading entry j of
+    // each (a row per coalesced load) times its x_j, and rows_sum16 adds
+    // them.  The boundary rows (C_ii alone) are the list after the last
+    // circle's rows, spread over every thread.
+    const int lane = tid & 63, u_out = (lane >> 2) & 15;
+    for (int m = blockIdx.x * (kThreads / 64) + (tid >> 6); m < c.nc; m += gridDim.x * (kThreads / 64)) {
+      const int64_t s0 = c.knot_off[m], len = c.knot_off[m + 1] - s0;
+      const int64_t q0 = c.circ_off[m], q1 = c.circ_off[m + 1];
+      if (q0 == q1) continue;
+      const double x0 = lane < len ? in(s0 + lane) : 0.0;
+      for (int64_t qb = q0; qb < q1; qb += 64) {
+        const int cnt = (int)min((int64_t)64, q1 - qb);
+        int64_t off = 0;
+        int32_t row = 0;
+        double dterm = 0.0;
+        if (lane < cnt) {
+          off = c.circ_roff[qb + lane];
+          row = c.circ_rows[qb + lane];
+          dterm = c.dg[row] * in(row);
+        }
+        for (int q = 0; q < cnt; q += 16) {
+          // (the address is clamped and the value masked, so that every
+          // load of the sixteen rows is in flight at once)
+          double p[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int64_t o = readlane_i64(off, q + u);
+            const bool okv = lane < len && q + u < cnt;
+            const double v = c.vblk[okv ? o + lane : 0];
+            p[u] = okv ? v * x0 : 0.0;
+          }
+          for (int64_t jb = 64; jb < len; jb += 64) {   // stencils of more than 64 knots
+            const bool okj = jb + lane < len;
+            const double xj = okj ? in(s0 + jb + lane) : 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+              const int64_t o = readlane_i64(off, q + u);
+              const bool okv = okj && q + u < cnt;
+              const double v = c.vblk[okv ? o + jb + lane : 0];
+              p[u] += okv ? v * xj : 0.0;
+            }
+          }
+          const double sum = rows_sum16(p, lane);
+          const int src = q + u_out;
+          const int32_t ri = __shfl(row, src, 64);
+          const double dt = __shfl(dterm, src, 64);
+          if ((lane & 3) == 0 && src < cnt) sink(ri, dt + sum);
+        }
+      }
+    }
+    for (int64_t q = c.circ_off[c.nc] + (int64_t)blockIdx.x * kThreads + tid; q < c.circ_off[c.nc + 1];
+         q += (int64_t)gridDim.x * kThreads) {
+      const int64_t i = c.circ_rows[q];
+      sink(i, c.dg[i] * in(i));
+    }
+    return;
+  }
   if (OPK == OP_CIRCLES) {
     // circle m: lanes over its knots j; its rows' offsets and inputs are
     // staged one per lane (64 rows at a time) and broadcast by readlane, so
@@ -200,76 +276,6 @@ __device__ __forceinline__ void apply_op(const SolveCtx& c, const X& in, Sink& s
           }
         }
         if (ok) sink(j, c.dg[j] * in(j) + (a0 + a1));
-      }
-    }
-    return;
-  }
-  if (OPK == OP_ROWS) {
-    // chunks of 64 consecutive rows per wavefront: the rows' metadata one per
-    // lane (one round trip), then batches of 16 rows -- a 16-lane group per
-    // row, four rows per group -- with every load of a batch issued at once
-    const int lane = tid & 63, sub = lane & (kLanes - 1), grp = lane / kLanes;
-    const int64_t wv = (int64_t)blockIdx.x * (kThreads / 64) + (tid >> 6);
-    const int64_t nwv = (int64_t)gridDim.x * (kThreads / 64);
-    for (int64_t r0 = wv * 64; r0 < c.N; r0 += nwv * 64) {
-      const int64_t ri = r0 + lane;
-      int64_t lo = 0, so = 0;
-      int len = 0;
-      double dterm = 0.0;
-      if (ri < c.N) {
-        const int64_t a = c.rowptr[ri], b = c.rowptr[ri + 1];
-        lo = a - ri;
-        len = (int)(b - a - 1);
-        so = c.so[ri];
-        dterm = c.dg[ri] * in(ri);
-      }
-      // (inputs formed from two vectors: half the rows per batch, so that
-      // the loads in flight fit in registers)
-      constexpr int NP = X::kTwoLoads ? 1 : 2;
-#pragma unroll 1
-      for (int bt = 0; bt < 64; bt += 4 * NP) {
-        int64_t lo_p[NP], so_p[NP];
-        int len_p[NP];
-        double acc[NP];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {           // the group's row of pass p: bt + 4 p + grp
-          const int rr = bt + 4 * p + grp;
-          lo_p[p] = shfl_i64(lo, rr);
-          so_p[p] = shfl_i64(so, rr);
-          len_p[p] = __shfl(len, rr, 64);
-        }
-        // four entries per lane per row, every load issued before the products
-        for (int jb = 0;; jb += 4 * kLanes) {
-          double v[NP][4], x[NP][4];
-#pragma unroll
-          for (int p = 0; p < NP; ++p)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const int j = jb + sub + kLanes * u;
-              const bool okj = j < len_p[p];
-              v[p][u] = okj ? c.vblk[lo_p[p] + j] : 0.0;
-              x[p][u] = okj ? in(so_p[p] + j) : 0.0;
-            }
-#pragma unroll
-          for (int p = 0; p < NP; ++p) {
-            double a = jb == 0 ? 0.0 : acc[p];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) a += v[p][u] * x[p][u];
-            acc[p] = a;
-          }
-          int lmax = 0;
-#pragma unroll
-          for (int p = 0; p < NP; ++p) lmax = max(lmax, len_p[p]);
-          if (!__any(jb + 4 * kLanes < lmax)) break;    // rows longer than 64 entries are rare
-        }
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          double a = acc[p];
-          for (int o = kLanes / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, kLanes);
-          const int rr = bt + 4 * p + grp;
-          const double dt = __shfl(dterm, rr, 64);
-          if (sub == 0 && r0 + rr < c.N) sink(r0 + rr, dt + a);
-        }
       }
     }
     return;
@@ -595,12 +601,13 @@ void ensure_blocked(pdd_cover cover) {
   const int64_t N = H.N();
   bool ok = H.pairs == nullptr;
   std::vector<int32_t> so(N, 0);
-  std::vector<int64_t> coff(H.nc + 1, 0);
+  std::vector<int64_t> coff(H.nc + 2, 0);   // the boundary rows last, as list nc
   for (int64_t i = 0; ok && i < N; ++i) {
     const int64_t lo = H.rowptr[i], len = H.rowptr[i + 1] - lo;
     const int32_t m = H.assigned[i];
     if (m < 0) {                           // boundary row: C_ii alone
       ok = len == 1 && H.cols[lo] == i;
+      ++coff[H.nc + 1];
       continue;
     }
     const int64_t s0 = H.knot_off[m], s1 = H.knot_off[m + 1];
@@ -613,16 +620,15 @@ void ensure_blocked(pdd_cover cover) {
     ++coff[m + 1];
   }
   if (ok) {
-    for (int32_t m = 0; m < H.nc; ++m) coff[m + 1] += coff[m];
-    std::vector<int32_t> rows(coff[H.nc]);
-    std::vector<int64_t> roff(coff[H.nc]);
+    for (int32_t m = 0; m <= H.nc; ++m) coff[m + 1] += coff[m];
+    std::vector<int32_t> rows(coff[H.nc + 1]);
+    std::vector<int64_t> roff(coff[H.nc + 1]);
     std::vector<int64_t> fill(coff.begin(), coff.end() - 1);
-    for (int64_t i = 0; i < N; ++i)
-      if (H.assigned[i] >= 0) {
-        const int64_t q = fill[H.assigned[i]]++;
-        rows[q] = (int32_t)i;
-        roff[q] = H.rowptr[i] - i;
-      }
+    for (int64_t i = 0; i < N; ++i) {
+      const int64_t q = fill[H.assigned[i] >= 0 ? H.assigned[i] : H.nc]++;
+      rows[q] = (int32_t)i;
+      roff[q] = H.rowptr[i] - i;
+    }
     D.blk_so.upload(so);
     D.blk_circ_off.upload(coff);
     D.blk_circ_rows.upload(rows);
@@ -689,11 +695,10 @@ void bind(SolveCtx& c, pdd_system sys, bool transpose, double* u, double* w) {
   const DeviceCover& D = sys->cover->D;
   const int64_t N = sys->cover->H.N();
   if (D.blocked_ok) {
-    c.kind = transpose ? OP_CIRCLES : OP_ROWS;
+    c.kind = transpose ? OP_CIRCLES : OP_ROWS_BY_CIRCLE;
     c.rowptr = D.rowptr.ptr<int64_t>();
     c.vblk = sys->vblk.ptr<double>();
     c.dg = sys->dg.ptr<double>();
-    c.so = D.blk_so.ptr<int32_t>();
     c.knot_off = D.knot_off.ptr<int64_t>();
     c.circ_off = D.blk_circ_off.ptr<int64_t>();
     c.circ_rows = D.blk_circ_rows.ptr<int32_t>();
@@ -735,7 +740,8 @@ void launch_iterations(const SolveCtx& c, hipStream_t st, int first, int count, 
 void launch_init(const SolveCtx& c, const double* b, bool guess, hipStream_t st) {
   if (guess) {
     if (c.kind == OP_CSR) hipLaunchKernelGGL(guess_product_kernel<OP_CSR>, dim3(kGrid), dim3(kThreads), 0, st, c);
-    else if (c.kind == OP_ROWS) hipLaunchKernelGGL(guess_product_kernel<OP_ROWS>, dim3(kGrid), dim3(kThreads), 0, st, c);
+    else if (c.kind == OP_ROWS_BY_CIRCLE)
+      hipLaunchKernelGGL(guess_product_kernel<OP_ROWS_BY_CIRCLE>, dim3(kGrid), dim3(kThreads), 0, st, c);
     else hipLaunchKernelGGL(guess_product_kernel<OP_CIRCLES>, dim3(kGrid), dim3(kThreads), 0, st, c);
   }
   hipLaunchKernelGGL(init_kernel, dim3(kGrid), dim3(kThreads), 0, st, c, b, guess ? 1 : 0);
@@ -749,7 +755,7 @@ int enqueue_batch(const SolveCtx& c, hipStream_t st, int enq, int max_iter, doub
   const int batch = std::min(kItersPerSync, max_iter - enq);
   const int first = enq == 0 ? 1 : 0;
   if (c.kind == OP_CSR) launch_iterations<OP_CSR>(c, st, first, batch, rtol);
-  else if (c.kind == OP_ROWS) launch_iterations<OP_ROWS>(c, st, first, batch, rtol);
+  else if (c.kind == OP_ROWS_BY_CIRCLE) launch_iterations<OP_ROWS_BY_CIRCLE>(c, st, first, batch, rtol);
   else launch_iterations<OP_CIRCLES>(c, st, first, batch, rtol);
   enq += batch;
   hipLaunchKernelGGL(status_kernel, dim3(1), dim3(kThreads), 0, st, c, enq == 0 ? 1 : 0, rtol);
