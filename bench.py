@@ -99,8 +99,7 @@ def bicgstab_bytes_per_iter(N, nnz):
     every vector it needs once with s = r - alpha v formed on the fly:
     p = r + beta (p - omega v) reads r, p, v and writes p (32 N); v = A p
     reads p and r0, writes v (24 N); t = A s reads r and v, writes t (24 N);
-    the x, r update reads r, v, x, p, t, r0 and writes x, r (64 N).  (The
-    kernels store s over r instead, 152 N: this count is the smaller one.)
+    the x, r update reads r, v, x, p, t, r0 and writes x, r (64 N).
     Index arrays are not counted: the method needs the values, not a
     particular sparse format."""
     return 16.0 * nnz + (32.0 + 24.0 + 24.0 + 64.0) * N

@@ -23,10 +23,11 @@
 // Rows of the averaged rule (eqs. 38-39) hold several stencils; those systems
 // keep the CSR form (and a transposed CSR copy for C^T).
 //
-// One iteration is five launches: p = r + beta (p - omega v); v = A p with
-// per-workgroup partial sums of (r0, v); s = r - alpha v, stored over r; t = A s
-// with partial sums of (t, s), (t, t); the x and r updates with partial sums
-// of (r, r) and (r0, r).  Every kernel runs on a fixed grid of kGrid
+// One iteration is four launches: p = r + beta (p - omega v); v = A p with
+// per-workgroup partial sums of (r0, v); t = A s with partial sums of (t, s),
+// (t, t), where s = r - alpha v is formed from r and v wherever it is read
+// and never stored; the x and r updates with partial sums of (r, r) and
+// (r0, r).  Every kernel runs on a fixed grid of kGrid
 // workgroups striding over its rows or circles, and each workgroup first adds
 // the kGrid partial sums of the kernel before it -- every workgroup the same
 // partials in the same fixed order, so all derive the same scalars (alpha,
@@ -413,10 +414,11 @@ __global__ __launch_bounds__(kThreads) void spmv_v_kernel(SolveCtx c) {
   if (threadIdx.x == 0) c.part_v[blockIdx.x] = sv;
 }
 
-// alpha = rho / (r0, v); s = r - alpha v, stored in place of r (r itself is
-// not needed again: the update forms the next r from s), so that the product
-// t = A s gathers one vector
-__global__ __launch_bounds__(kThreads) void form_s_kernel(SolveCtx c) {
+// alpha = rho / (r0, v) (every workgroup adds the partial sums of (r0, v)
+// itself); t = A s with s = r - alpha v formed from r and v wherever it is
+// read (s is never stored), partial sums of (t, s) and (t, t)
+template <int OPK>
+__global__ __launch_bounds__(kThreads) void spmv_t_kernel(SolveCtx c) {
   __shared__ double s4[4];
   if (c.sc[S_DONE] != 0.0) return;
   const double rv = sum_parts(c.part_v, s4);
@@ -425,25 +427,16 @@ __global__ __launch_bounds__(kThreads) void form_s_kernel(SolveCtx c) {
     c.sc[S_RV] = rv;
     c.sc[S_ALPHA] = alpha;
   }
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < c.N; i += (int64_t)gridDim.x * kThreads)
-    c.r[i] = c.r[i] - alpha * c.v[i];
-}
-
-// t = A s (s in r), partial sums of (t, s) and (t, t)
-template <int OPK>
-__global__ __launch_bounds__(kThreads) void spmv_t_kernel(SolveCtx c) {
-  __shared__ double s4[4];
-  if (c.sc[S_DONE] != 0.0) return;
   struct Sink {
     const SolveCtx& c;
-    double pts, ptt;
+    double alpha, pts, ptt;
     __device__ void operator()(int64_t i, double y) {
       c.t[i] = y;
-      pts += y * c.r[i];
+      pts += y * (c.r[i] - alpha * c.v[i]);
       ptt += y * y;
     }
-  } sink{c, 0.0, 0.0};
-  apply_op<OPK>(c, In<false>{c.r, nullptr, 0.0}, sink);
+  } sink{c, alpha, 0.0, 0.0};
+  apply_op<OPK>(c, In<true>{c.r, c.v, alpha}, sink);
   const double sts = block_sum(sink.pts, s4);
   const double stt = block_sum(sink.ptt, s4);
   if (threadIdx.x == 0) {
@@ -452,8 +445,8 @@ __global__ __launch_bounds__(kThreads) void spmv_t_kernel(SolveCtx c) {
   }
 }
 
-// omega = (t, s) / (t, t); x += alpha p + omega s; r = s - omega t (s in r);
-// partial sums of (r, r) and (r0, r)
+// omega = (t, s) / (t, t); x += alpha p + omega s; r = s - omega t with
+// s = r - alpha v; partial sums of (r, r) and (r0, r)
 __global__ __launch_bounds__(kThreads) void update_xr_kernel(SolveCtx c) {
   __shared__ double s4[4];
   if (c.sc[S_DONE] != 0.0) return;
@@ -469,7 +462,7 @@ __global__ __launch_bounds__(kThreads) void update_xr_kernel(SolveCtx c) {
   }
   double prr = 0.0, prho = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < c.N; i += (int64_t)gridDim.x * kThreads) {
-    const double si = c.r[i];
+    const double si = c.r[i] - alpha * c.v[i];
     c.x[i] = c.x[i] + alpha * c.p[i] + omega * si;
     const double ri = si - omega * c.t[i];
     c.r[i] = ri;
@@ -730,7 +723,6 @@ void launch_iterations(const SolveCtx& c, hipStream_t st, int first, int count, 
   for (int k = 0; k < count; ++k) {
     hipLaunchKernelGGL(update_p_kernel, dim3(kGrid), dim3(kThreads), 0, st, c, k == 0 ? first : 0, rtol);
     hipLaunchKernelGGL(spmv_v_kernel<OPK>, dim3(kGrid), dim3(kThreads), 0, st, c);
-    hipLaunchKernelGGL(form_s_kernel, dim3(kGrid), dim3(kThreads), 0, st, c);
     hipLaunchKernelGGL(spmv_t_kernel<OPK>, dim3(kGrid), dim3(kThreads), 0, st, c);
     hipLaunchKernelGGL(update_xr_kernel, dim3(kGrid), dim3(kThreads), 0, st, c);
   }
