@@ -623,7 +623,7 @@ def main():
         "lu": f"batched LU + triangular solves of {n_float} circles (lu_pupd/lu_panel/lu_urow/lu_bdiag/"
               "lu_bupd launch sequence, HIP events around it on the calling stream)",
         "mc": "paths_kernel (Euler-Maruyama paths, one per lane) on the side stream",
-        "bicgstab": "BiCGStab on C and C^T (update_p/spmv_v/form_s/spmv_t/update_xr per iteration)",
+        "bicgstab": "BiCGStab on C and C^T (update_p/spmv_v/spmv_t/update_xr per iteration)",
         "adjoint": "adjoint_kernel over the stored factors",
     }
     roofline = dict(roof[dom])
